@@ -1,0 +1,266 @@
+#!/usr/bin/env python
+"""Forward+backward throughput of the splatting step on one MI355X.
+
+Workload (default): 5,000,000 Gaussians from a 512-blob mixture in a 200 m
+cube, SH degree 3, one 3840x2160 view (fx = fy = 3000) looking at the scene
+centre from the cube surface; FP32 forward, L2 loss against a uniform target,
+backward to every parameter.  Inputs are seeded and synthetic and resident in
+HBM before timing starts.
+
+Two paths are timed on the same inputs:
+  plain   - one workgroup per tile, every call launched eagerly;
+  batched - persistent rasterisers fed by a heavy-first (view, tile) queue and
+            the whole step replayed from one captured HIP graph.
+The reported ``value`` is the batched path's megapixels/s; the plain path's
+figure is reported beside it.  The roofline object covers the kernel with the
+largest share of the step, timed with HIP events on the launch stream.  The
+CPU baseline is the FP64 oracle timed on a bounded sample of the same step.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# HBM / VALU peaks of one MI355X (published)
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic FP32 operations per list entry a pixel examines (FMA = 2)
+FWD_FLOPS_PER_VISIT = 25
+BWD_FLOPS_PER_VISIT = 63
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_scene(cfg, n_override=None):
+    from paper_2606_11390_amd import scenes
+    kw = {} if n_override is None else {"n_gaussians": n_override}
+    if cfg == "tiny":
+        return scenes.tiny(**kw)
+    if cfg == "hd":
+        return scenes.hd(**kw)
+    if cfg == "uhd":
+        return scenes.uhd(**kw)
+    if cfg == "multiview":
+        return scenes.multiview(**kw)
+    if cfg == "city":
+        return scenes.city(**kw)
+    raise SystemExit(f"unknown config {cfg}")
+
+
+def timed(fn, steps, torch):
+    """Run fn `steps` times between two events on the current stream; ms per call."""
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def stage_times(r, P, cams, tg, grads, steps, torch):
+    """Average duration of each call of the step, each timed over `steps`
+    back-to-back launches with HIP events on the launch stream."""
+    r.forward(P, cams)
+    r.loss_l2(tg)
+    out = {}
+    out["project"] = timed(lambda: r.project(P, cams), steps, torch)
+    out["bin_sort"] = timed(r.bin_sort, steps, torch)
+    out["raster_fwd"] = timed(r.raster_fwd, steps, torch)
+    out["loss"] = timed(lambda: r.loss_l2(tg), steps, torch)
+    from paper_2606_11390_amd import binding as B
+    s, q = r._sched()
+    out["raster_bwd"] = timed(lambda: B.rasterize_bwd(r.splats, r.isect_gid, r.ranges, r.n, r.sizes, r.tile,
+                                                      r.background, s, q, r.T_final, r.n_contrib, r.d_images,
+                                                      None, r.grad2d, accumulate=True), steps, torch)
+    out["project_bwd"] = timed(lambda: r.project_bwd(P, cams, grads), steps, torch)
+    return out
+
+
+def cpu_baseline(scene, tile, seed=0, frac=0.02, crop_frac=0.1):
+    """FP64 oracle on a bounded sample of the same step, scaled to the frame.
+
+    Per-Gaussian work (projection + its backward) is timed on a seeded
+    `frac` sample of the Gaussians with the full camera and scaled by
+    1/frac; per-pixel work (binning, compositing forward and backward, loss)
+    is timed on a centred crop of `crop_frac` of the width and height (all
+    Gaussians projected into the crop camera, untimed) and scaled by the
+    pixel ratio."""
+    import oracle
+    from paper_2606_11390_amd import scenes
+    rng = np.random.default_rng(seed)
+    N = scene.n
+    idx = np.sort(rng.choice(N, size=max(1, int(frac * N)), replace=False))
+    P = oracle.Params(scene.means[:, idx], scene.log_scales[:, idx], scene.quats[:, idx],
+                      scene.opacity_logits[idx], scene.sh[:, :, idx], scene.sh_degree)
+    W, H = (int(x) for x in scene.sizes[0])
+    vm, it = scene.viewmats[0], scene.intrinsics[0]
+    t0 = time.perf_counter()
+    pr = oracle.project(P, vm, it, W, H, tile=tile)
+    g = dict(u=np.ones(P.n), v=np.ones(P.n), conic=np.ones((3, P.n)), sigma=np.ones(P.n),
+             rgb=np.ones((3, P.n)))
+    oracle.project_bwd(P, vm, it, W, H, g, tile=tile)
+    t_gauss = (time.perf_counter() - t0) * (N / P.n)
+    # crop camera: same pose and focal length, principal point moved so the
+    # crop covers the centre of the frame
+    cw, ch = max(tile, int(W * crop_frac)), max(tile, int(H * crop_frac))
+    cit = np.array([it[0], it[1], it[2] - (W - cw) / 2.0, it[3] - (H - ch) / 2.0])
+    Pall = oracle.Params.of(scene)
+    prc = oracle.project(Pall, vm, cit, cw, ch, tile=tile)
+    target = np.random.default_rng(seed + 1).uniform(0, 1, (3, ch, cw))
+    t1 = time.perf_counter()
+    keys, vals, ranges, offs = oracle.bin_views(
+        [(prc["u"].astype(np.float32), prc["v"].astype(np.float32), prc["depth"].astype(np.float32),
+          prc["radii"])], np.array([[cw, ch]]), tile)
+    f = oracle.raster_fwd(cw, ch, tile, ranges, vals, prc)
+    _, (dimg,) = oracle.l2_loss([f["img"]], [target])
+    oracle.raster_bwd(cw, ch, tile, ranges, vals, prc, dimg)
+    t_pix = (time.perf_counter() - t1) * (W * H) / (cw * ch)
+    total = t_gauss + t_pix
+    del scenes
+    return {"value": round(W * H / total / 1e6, 6), "unit": "megapixels/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle, 1 thread: projection + projection backward of a seeded {frac:.0%} "
+                       f"sample of the {N} Gaussians (scaled x{N / P.n:.0f}); binning, compositing forward "
+                       f"and backward and L2 loss of a centred {cw}x{ch} crop (scaled x{W * H / (cw * ch):.0f}); "
+                       f"estimated full-step time {total:.1f} s"),
+            "seconds_measured": round(time.perf_counter() - t0, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="uhd", choices=["tiny", "hd", "uhd", "multiview", "city"])
+    ap.add_argument("--n-gaussians", type=int, default=None)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["all", "batched", "plain"], default="all",
+                    help="restrict to one path (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs one GPU's share of the step; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2606_11390_amd import binding as B
+    from paper_2606_11390_amd import render as R
+
+    t0 = time.time()
+    scene = make_scene(args.config, args.n_gaussians)
+    log(f"scene {scene.name}: N={scene.n} views={scene.n_views} pixels={scene.pixels} "
+        f"({time.time() - t0:.1f} s)")
+    P, cams = R.params_to_device(scene)
+    tg = R.packed_targets(scene)
+    grads = R.zeros_like_params(P)
+    pixels = scene.pixels
+    gauss = scene.n * scene.n_views
+    result = {}
+
+    def run_path(persistent, graph):
+        r = R.Renderer(scene.n, scene.sh_degree, scene.sizes, tile=args.tile, capacity=1 << 22,
+                       persistent=persistent)
+        m = r.fit_capacity(P, cams)
+        if graph:
+            r.capture(P, cams, tg, grads, warmup=max(1, args.warmup))
+            step = r.replay
+        else:
+            step = lambda: r.step(P, cams, tg, grads)
+            for _ in range(args.warmup):
+                step()
+        torch.cuda.synchronize()
+        ms = timed(step, args.steps, torch)
+        return r, m, ms
+
+    if args.only in ("all", "plain"):
+        r_plain, m, ms_plain = run_path(False, False)
+        result["plain"] = {"ms_per_step": ms_plain, "mp_per_s": pixels / ms_plain / 1e3}
+        log(f"plain: {ms_plain:.3f} ms/step, {pixels / ms_plain / 1e3:.1f} MP/s, M={m}")
+        if args.only == "plain":
+            r_main, ms_main = r_plain, ms_plain
+        del_plain = args.only == "all"
+    if args.only in ("all", "batched"):
+        r_main, m, ms_main = run_path(True, True)
+        log(f"batched: {ms_main:.3f} ms/step, {pixels / ms_main / 1e3:.1f} MP/s, M={m}")
+    if args.only == "all" and del_plain:
+        del r_plain
+        torch.cuda.empty_cache()
+
+    # per-call durations on the main path, HIP events on the launch stream
+    st = stage_times(r_main, P, cams, tg, grads, args.steps, torch)
+    log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
+    # algorithmic work of the compositing kernels
+    vis = torch.empty(pixels, dtype=torch.int32, device="cuda")
+    img2 = torch.empty(3 * pixels, device="cuda")
+    T2 = torch.empty(pixels, device="cuda")
+    c2 = torch.empty(pixels, dtype=torch.int32, device="cuda")
+    B.raster_visits(r_main.splats, r_main.isect_gid, r_main.ranges, r_main.n, r_main.sizes, r_main.tile, img2,
+                    T2, c2, vis)
+    r_main.raster_fwd()
+    fwd_visits = int(vis.to(torch.int64).sum())
+    bwd_visits = int(r_main.n_contrib.to(torch.int64).sum())
+    info = r_main.info.cpu().numpy()
+    K = (scene.sh_degree + 1) ** 2
+    param_bytes = 4 * (3 + 3 + 4 + 1 + 3 * K)
+    proj_bytes = scene.n * param_bytes + gauss * (4 * 12 + 4 + 8 + 4 + 1)
+    rooflines = {
+        "raster_fwd": ("alu", FWD_FLOPS_PER_VISIT * fwd_visits / (st["raster_fwd"] * 1e-3) / 1e12,
+                       PEAK_FP32_TFLOPS, "TFLOP/s"),
+        "raster_bwd": ("alu", BWD_FLOPS_PER_VISIT * bwd_visits / (st["raster_bwd"] * 1e-3) / 1e12,
+                       PEAK_FP32_TFLOPS, "TFLOP/s"),
+        "project": ("hbm", proj_bytes / (st["project"] * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"),
+    }
+    dom = max((k for k in st if k in rooflines), key=lambda k: st[k])
+    bound, ach, peak, unit = rooflines[dom]
+    roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                "frac": round(ach / peak, 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline and scene.n_views == 1:
+        log("cpu baseline (oracle sample) ...")
+        cpu = cpu_baseline(scene, args.tile)
+        log(f"cpu baseline: {cpu['value']} MP/s ({cpu['seconds_measured']} s)")
+
+    line = {
+        "metric": "fwd+bwd megapixels/s at 4K, 5M Gaussians: batched vs plain path, 1 MI355X",
+        "value": round(pixels / ms_main / 1e3, 3),
+        "unit": "megapixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_main, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{scene.name}: {scene.n} Gaussians, SH degree {scene.sh_degree}, "
+                               f"{scene.n_views} view(s) {'+'.join(f'{w}x{h}' for w, h in scene.sizes)}, "
+                               f"tile {args.tile}, FP32 forward + L2 loss + backward",
+                   "path": "batched" if args.only != "plain" else "plain",
+                   "gaussians": scene.n, "views": scene.n_views, "pixels": pixels,
+                   "intersections": int(info[B.INFO_ISECT]), "visible": int(info[B.INFO_VISIBLE]),
+                   "parallelism": "1 GPU"},
+        "gaussians_per_s": round(gauss / ms_main * 1e3, 1),
+        "plain": {k: round(v, 4) for k, v in result.get("plain", {}).items()},
+        "stage_ms": {k: round(v, 4) for k, v in st.items()},
+        "visits": {"forward": fwd_visits, "backward": bwd_visits},
+        "roofline": roofline,
+        "roofline_all": {k: {"bound": b, "achieved": round(a, 3), "peak": p, "unit": u, "frac": round(a / p, 4)}
+                         for k, (b, a, p, u) in rooflines.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

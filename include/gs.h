@@ -1,0 +1,280 @@
+/*
+ * gs.h - C ABI of the MI355X (gfx950) Gaussian-splatting hot path.
+ *
+ * One GPU's share of a Gaussian-splatting training step, as listed in
+ * Section 4 of "A Scalable PyTorch Abstraction for Multi-GPU Gaussian
+ * Splatting" (arXiv 2606.11390): spherical-harmonic colour and projection per
+ * Gaussian for every camera of a batch, a per-camera depth sort, rasterisation
+ * and an image-space loss, and the backward passes of all of them.  The paper
+ * takes the mathematics from 3D Gaussian Splatting (Kerbl et al. 2023); the
+ * formulas below are those.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every pointer argument is a DEVICE pointer owned by the caller unless its
+ *   comment says "host".  The library never allocates, frees or retains
+ *   memory: scratch space comes in through an explicit workspace argument.
+ * - Every call only enqueues work on `stream` (a hipStream_t passed as void*,
+ *   NULL for the default stream) and returns without synchronising; outputs
+ *   are valid once the stream reaches that point.  No call reads a device
+ *   value back to the host, so a whole step can be captured in a HIP graph.
+ * - Return value: GS_OK (0) or a negative gs_status.  Argument errors are
+ *   detected on the host before anything is enqueued; GS_ERR_HIP reports a
+ *   failed launch.  No C++ exception crosses the ABI.
+ * - N = number of Gaussians, V = number of views (1 <= V <= GS_MAX_VIEWS),
+ *   K = (sh_degree + 1)^2 SH coefficients per channel (sh_degree in 0..3),
+ *   tile = tile edge in pixels (8, 16 or 32).
+ * - Per-Gaussian parameters are planar structure-of-arrays [C][N] float32.
+ * - Per-(view, Gaussian) outputs are [V][N][...] with view v at offset v*N.
+ * - Images of view v (W_v x H_v pixels) are packed back to back: colour
+ *   images [3][H_v][W_v] starting at float offset 3 * sum_{u<v} W_u H_u,
+ *   single-channel images [H_v][W_v] starting at sum_{u<v} W_u H_u.
+ * - Pixel (i, j) (column i, row j) has its centre at (i + 0.5, j + 0.5).
+ * - Tiles of view v are numbered row-major, TX_v = ceil(W_v / tile),
+ *   TY_v = ceil(H_v / tile); the global tile id is tile_offset_v + ty*TX_v + tx
+ *   with tile_offset_v = sum_{u<v} TX_u TY_u, and T_total = tile_offset_V.
+ *
+ * The splat record (GS_SPLAT_FLOATS = 12 float32, 48 bytes, 16-byte aligned),
+ * one per (view, Gaussian), written by gs_project and read by the
+ * rasterisers:
+ *   [0] u, [1] v      projected mean in pixels
+ *   [2] m00, [3] m10, [4] m11
+ *                     lower-triangular M = [[m00, 0], [m10, m11]] with
+ *                     M M^T = (log2(e) / 2) * Q, Q = [[A, B], [B, C]] the
+ *                     conic (inverse of the EWA 2-D covariance).  Then
+ *                     q' = |M^T d|^2 = (log2 e / 2) d^T Q d and the Gaussian
+ *                     falloff exp(-d^T Q d / 2) equals 2^(-q').
+ *   [5] log2(sigma)   sigma = sigmoid(opacity logit)
+ *   [6] r, [7] g, [8] b   view-dependent colour (after the clamp at 0)
+ *   [9] sigma
+ *   [10] depth (camera-space z), [11] 0
+ * Records of culled Gaussians are left unwritten.
+ *
+ * The 2-D gradient record (GS_GRAD_FLOATS = 9 float32), one per
+ * (view, Gaussian): derivatives of the loss with respect to
+ *   [0] u, [1] v, [2] A, [3] B, [4] C (conic entries, B counted once),
+ *   [5] sigma, [6] r, [7] g, [8] b.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+#define GS_MAX_VIEWS 64
+#define GS_SPLAT_FLOATS 12
+#define GS_GRAD_FLOATS 9
+
+/* flags byte per (view, Gaussian) */
+#define GS_FLAG_VISIBLE 0x1u
+#define GS_FLAG_CLAMP_R 0x2u
+#define GS_FLAG_CLAMP_G 0x4u
+#define GS_FLAG_CLAMP_B 0x8u
+
+/* gs_bin_sort info words (device int32[4]) */
+#define GS_INFO_VISIBLE 0   /* number of visible (view, Gaussian) pairs */
+#define GS_INFO_ISECT 1     /* number of intersections M (saturates at INT32_MAX) */
+#define GS_INFO_OVERFLOW 2  /* 1 if M > capacity: lists truncated, re-run larger */
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_ARG = -1,         /* null pointer, bad size, unsupported tile/degree */
+    GS_ERR_UNSUPPORTED = -2, /* valid request this build does not implement */
+    GS_ERR_HIP = -3,         /* a HIP launch or runtime call failed */
+    GS_ERR_WORKSPACE = -4    /* workspace smaller than the *_workspace_size query */
+} gs_status;
+
+/* GS_ABI_VERSION of the loaded library */
+int gs_abi_version(void);
+
+/* static, human-readable text of a gs_status */
+const char* gs_strerror(int code);
+
+/*
+ * gs_project - forward projection and SH colour (paper Section 4: the
+ * spherical-harmonics and projection operators, per Gaussian, outputs for
+ * every camera of the batch).  Reads each Gaussian's parameters once for all
+ * V views.
+ *
+ * Inputs:
+ *   means[3][N]           world-space centres mu
+ *   log_scales[3][N]      per-axis log standard deviations (S = diag exp)
+ *   quats[4][N]           rotation quaternion (w, x, y, z), any non-zero norm
+ *   opacity_logits[N]     sigma = 1 / (1 + exp(-o))
+ *   sh[K][3][N]           real SH coefficients, index l*l + l + m, Condon-
+ *                         Shortley phase; colour = max(0, sum_k sh_k Y_k(d) + 0.5)
+ *                         with d the unit ray from the camera centre to mu
+ *   viewmats[V][12]       world-to-camera [R | t], row-major, OpenCV axes
+ *                         (+x right, +y down, +z forward)
+ *   intrinsics[V][4]      fx, fy, cx, cy (pixels)
+ *   sizes (host)[V][2]    W, H of each view
+ *   near_plane, far_plane culling planes on camera z (z <= near or z >= far)
+ *   eps2d                 isotropic dilation added to the 2-D covariance (0.3)
+ *   tile                  tile edge used to count tiles_touched
+ * Method: Sigma = R S S^T R^T; p = R_v mu + t_v; J = Jacobian of the pinhole
+ * projection at p with x/z, y/z clamped to +-1.3 * (W/2)/fx, (H/2)/fy;
+ * Sigma2 = J R_v Sigma R_v^T J^T + eps2d I; Q = Sigma2^-1; (u, v) = (fx x/z +
+ * cx, fy y/z + cy); radii = ceil(3 sqrt(Sigma2_xx)), ceil(3 sqrt(Sigma2_yy));
+ * tile rectangle [floor((u-rx)/tile), floor((u+rx)/tile)+1) x (same in y),
+ * clamped to the grid, evaluated in float32.
+ * Culled (all outputs zero, record unwritten): non-finite input, z outside
+ * (near, far), sigma < 1/255, det Sigma2 <= 0, empty tile rectangle.
+ * Outputs ([V][N] unless stated):
+ *   splats[V][N][12]      splat record (see above)
+ *   depths                camera-space z (float32; sort key)
+ *   radii[V][N][2]        rx, ry in pixels (int32)
+ *   tiles_touched         number of tiles in the rectangle (int32)
+ *   flags                 GS_FLAG_* bits (uint8)
+ */
+int gs_project(const float* means, const float* log_scales, const float* quats,
+               const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
+               const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
+               float near_plane, float far_plane, float eps2d, int tile,
+               float* splats, float* depths, int32_t* radii, int32_t* tiles_touched,
+               uint8_t* flags, void* stream);
+
+/*
+ * gs_bin_sort_workspace_size - bytes of device workspace gs_bin_sort needs
+ * for n Gaussians, V views, an intersection capacity and T_total tiles.
+ */
+size_t gs_bin_sort_workspace_size(int64_t n, int n_views, int64_t capacity, int64_t total_tiles);
+
+/*
+ * gs_bin_sort - tile binning and depth sort (paper Section 4: per camera,
+ * the Gaussians are sorted by depth before rasterisation; one record per
+ * (Gaussian, tile) intersection).
+ *
+ * Result: the M intersections of all views sorted stably by the 64-bit key
+ * (global tile id << 32) | float32 bits of depth, where intersections are
+ * enumerated per view, Gaussian index ascending and tiles row-major within
+ * each rectangle; equal keys therefore keep Gaussian order.  (Depth is
+ * positive, so its bit pattern orders like its value.)
+ * Inputs: splats (fields u, v), depths, radii, tiles_touched as written by
+ *   gs_project for the same n, V, sizes and tile; capacity = entries
+ *   available in isect_tile / isect_gid (1 <= capacity < 2^31).
+ * Outputs:
+ *   isect_tile[capacity]  global tile id of each sorted intersection
+ *   isect_gid[capacity]   Gaussian index (0..N-1) of each sorted intersection
+ *   tile_ranges[T_total][2]  first and one-past-last position of each tile's
+ *                         run in the sorted arrays (0, 0 when empty)
+ *   info[4] (device int32) GS_INFO_* words.
+ * Overflow: if M > capacity, info[GS_INFO_OVERFLOW] = 1 and only the first
+ *   `capacity` intersections (in depth-sorted enumeration order) are kept;
+ *   the lists are then incomplete and the caller must re-run with more room.
+ * workspace: >= gs_bin_sort_workspace_size() bytes, 256-byte aligned,
+ *   contents need not be initialised and are clobbered.
+ */
+int gs_bin_sort(const float* splats, const float* depths, const int32_t* radii,
+                const int32_t* tiles_touched, int64_t n, int n_views, const int32_t* sizes,
+                int tile, int64_t capacity, void* workspace, size_t workspace_bytes,
+                int32_t* isect_tile, int32_t* isect_gid, int32_t* tile_ranges, int32_t* info,
+                void* stream);
+
+/*
+ * gs_tile_schedule_size - bytes of device memory gs_tile_schedule needs for
+ * T_total tiles (its `order` plus its own scratch).
+ */
+size_t gs_tile_schedule_size(int64_t total_tiles);
+
+/*
+ * gs_tile_schedule - order tiles by decreasing list length (ties by tile
+ * id) for the persistent rasterisers, so that long tiles start first.
+ * Writes order[T_total] (int32 global tile ids) at the start of `schedule`.
+ */
+int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* schedule,
+                     size_t schedule_bytes, void* stream);
+
+/*
+ * gs_rasterize_fwd - front-to-back alpha compositing (paper Section 4: the
+ * rasterisation operator, per camera).  For each pixel, over its tile's list
+ * in sorted order: alpha = min(0.99, sigma * 2^(-q')); entries with
+ * alpha < 1/255 are skipped; compositing stops before the first entry that
+ * would bring the transmittance T below 1e-4; colour C += alpha T c,
+ * T *= 1 - alpha.  Output colour = C + T * background.
+ * Inputs: splats, isect_gid and tile_ranges from gs_project / gs_bin_sort;
+ *   background (host)[3].
+ * schedule: NULL for one workgroup per tile, or a gs_tile_schedule buffer
+ *   for the persistent kernel that pulls (view, tile) items from a global
+ *   queue; queue (device int32[1]) is the persistent kernel's counter (reset
+ *   by this call; unused when schedule is NULL).
+ * Outputs: images (packed [3][H][W] per view), T_final and n_contrib (packed
+ *   [H][W] per view): final transmittance and one past the list position of
+ *   the last composited entry.
+ */
+int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
+                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
+                     const void* schedule, int32_t* queue, float* images, float* T_final,
+                     int32_t* n_contrib, void* stream);
+
+/*
+ * gs_rasterize_bwd - backward of gs_rasterize_fwd (paper Section 4: backward
+ * of the rasteriser with gradient accumulation by atomics).  Walks each
+ * pixel's composited entries from the back, recovering each transmittance
+ * from T_final by division by (1 - alpha) instead of storing per-pixel lists.
+ * Inputs: as gs_rasterize_fwd plus its T_final and n_contrib, d_images (packed
+ *   like images) and d_alpha (packed [H][W] per view; gradient with respect
+ *   to 1 - T_final; may be NULL).
+ * Output: grad2d[V][N][9] (see the 2-D gradient record).  With accumulate = 0
+ *   the call first zeroes it (with a fill kernel, so the call stays graph
+ *   capturable) and then accumulates; with accumulate != 0 it adds to the
+ *   existing contents.  Summation order is not deterministic.
+ */
+int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
+                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
+                     const void* schedule, int32_t* queue, const float* T_final,
+                     const int32_t* n_contrib, const float* d_images, const float* d_alpha,
+                     float* grad2d, int accumulate, void* stream);
+
+/*
+ * gs_project_bwd - backward of gs_project (paper Section 4: backward of the
+ * SH and projection operators, partitioned per Gaussian).  One thread owns
+ * one Gaussian and sums its views in registers, so no atomics are used.
+ * Inputs: the gs_project inputs, its flags, and grad2d from gs_rasterize_bwd.
+ * Outputs (OVERWRITTEN, not accumulated): d_means[3][N], d_log_scales[3][N],
+ *   d_quats[4][N], d_opacity_logits[N], d_sh[K][3][N].  Gaussians culled in
+ *   every view get zeros.  Depth is not differentiated (sort key only).
+ */
+int gs_project_bwd(const float* means, const float* log_scales, const float* quats,
+                   const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
+                   const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
+                   float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
+                   float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh,
+                   void* stream);
+
+/*
+ * gs_raster_visits - instrumentation for the roofline numerator: runs the
+ * forward compositing of gs_rasterize_fwd (zero background, one workgroup per
+ * tile) and also writes visits (packed [H][W] per view, int32): the number of
+ * list entries each pixel examined, i.e. up to and including the entry that
+ * stopped it, or its whole tile list.
+ */
+int gs_raster_visits(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges, int64_t n,
+                     int n_views, const int32_t* sizes, int tile, float* images, float* T_final,
+                     int32_t* n_contrib, int32_t* visits, void* stream);
+
+/*
+ * gs_loss_workspace_size - bytes of device workspace gs_loss_l2 needs for
+ * n_elems image elements.
+ */
+size_t gs_loss_workspace_size(int64_t n_elems);
+
+/*
+ * gs_loss_l2 - image-space loss (paper Section 4: per-camera image loss; L2
+ * here): loss = sum((images - targets)^2) / n_elems and
+ * d_images = 2 (images - targets) / n_elems over n_elems packed floats.
+ * loss (device float[1]) is overwritten; the sum is reduced in a fixed order
+ * (deterministic) through `workspace`.
+ */
+int gs_loss_l2(const float* images, const float* targets, int64_t n_elems, float* loss,
+               float* d_images, void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

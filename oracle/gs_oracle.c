@@ -307,16 +307,26 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
     double ex = 3.0 * sqrt(a), ey = 3.0 * sqrt(c);
     P->margin = fmin(P->margin, int_margin(ex));
     P->margin = fmin(P->margin, int_margin(ey));
-    P->rx = (int)ceil(ex);
-    P->ry = (int)ceil(ey);
+    P->rx = (int)fmin(ceil(ex), 1073741824.0);   /* radii saturate at 2^30 px */
+    P->ry = (int)fmin(ceil(ey), 1073741824.0);
 
     /* tile rectangle, float32 arithmetic on float32-rounded values */
+    /* a floor decision can change the rectangle only where it is not clamped */
     float uf = (float)P->u, vf = (float)P->v;
     double ts = (double)tile;
-    P->margin = fmin(P->margin, int_margin(((double)uf - P->rx) / ts));
-    P->margin = fmin(P->margin, int_margin(((double)uf + P->rx) / ts));
-    P->margin = fmin(P->margin, int_margin(((double)vf - P->ry) / ts));
-    P->margin = fmin(P->margin, int_margin(((double)vf + P->ry) / ts));
+    double TXd = (double)((W + tile - 1) / tile), TYd = (double)((H + tile - 1) / tile);
+    double edges[4] = {((double)uf - P->rx) / ts, ((double)uf + P->rx) / ts,
+                       ((double)vf - P->ry) / ts, ((double)vf + P->ry) / ts};
+    for (int e = 0; e < 4; e++) {
+        double hi = e < 2 ? TXd : TYd;
+        if (edges[e] > -1.0 && edges[e] < hi + 1.0) {
+            /* distance to the tile boundary in pixels, relative to the size of
+             * the coordinate (which sets its float32 rounding error) */
+            double mag = e < 2 ? fabs((double)uf) : fabs((double)vf);
+            double d = fabs(edges[e] - nearbyint(edges[e])) * ts;
+            P->margin = fmin(P->margin, d / (mag > ts ? mag : ts));
+        }
+    }
     int r[4];
     tile_rect(uf, vf, P->rx, P->ry, tile, W, H, r);
     P->tiles = (r[2] - r[0]) * (r[3] - r[1]);

@@ -1,0 +1,224 @@
+"""ctypes binding of the C ABI in ``include/gs.h`` (argument marshalling only).
+
+Every function here checks tensor dtypes, devices and shapes, passes
+``data_ptr()`` values and torch's current HIP stream to the library, and
+returns.  All computation happens in the HIP kernels of ``libgs.so``; there is
+no fallback: if the library is missing or the tensors are not on a GPU the
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgs.so")
+
+GS_ABI_VERSION = 1
+GS_MAX_VIEWS = 64
+SPLAT_FLOATS = 12
+GRAD_FLOATS = 9
+FLAG_VISIBLE = 1
+INFO_VISIBLE, INFO_ISECT, INFO_OVERFLOW = 0, 1, 2
+
+_lib = None
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_f = ctypes.c_float
+_sz = ctypes.c_size_t
+
+# name -> (restype, argtypes), mirroring include/gs.h
+_SIGS = {
+    "gs_abi_version": (_int, []),
+    "gs_strerror": (ctypes.c_char_p, [_int]),
+    "gs_project": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _f, _f, _int,
+                          _p, _p, _p, _p, _p, _p]),
+    "gs_bin_sort_workspace_size": (_sz, [_i64, _int, _i64, _i64]),
+    "gs_bin_sort": (_int, [_p, _p, _p, _p, _i64, _int, _p, _int, _i64, _p, _sz, _p, _p, _p, _p, _p]),
+    "gs_tile_schedule_size": (_sz, [_i64]),
+    "gs_tile_schedule": (_int, [_p, _i64, _p, _sz, _p]),
+    "gs_rasterize_fwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p, _p, _p]),
+    "gs_rasterize_bwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p, _p, _p, _p, _int, _p]),
+    "gs_project_bwd": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
+                              _p, _p, _p, _p]),
+    "gs_raster_visits": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p]),
+    "gs_loss_workspace_size": (_sz, [_i64]),
+    "gs_loss_l2": (_int, [_p, _p, _i64, _p, _p, _p, _sz, _p]),
+}
+
+
+class GSError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded ``libgs.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GSError(f"{LIB_PATH} not built; run __graft_entry__.build() or "
+                          "python -m paper_2606_11390_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        if L.gs_abi_version() != GS_ABI_VERSION:
+            raise GSError("libgs.so ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return tuple(_SIGS)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise GSError(f"{what}: {lib().gs_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise GSError(f"{name} must live on the GPU (got {t.device})")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise GSError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _host_i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _host_f32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def tile_grid(sizes, tile):
+    """Per-view tiles_x, tile offsets (length V+1) and pixel offsets (length V+1)."""
+    sizes = np.asarray(sizes, np.int64).reshape(-1, 2)
+    tx = (sizes[:, 0] + tile - 1) // tile
+    ty = (sizes[:, 1] + tile - 1) // tile
+    toff = np.concatenate([[0], np.cumsum(tx * ty)])
+    poff = np.concatenate([[0], np.cumsum(sizes[:, 0] * sizes[:, 1])])
+    return tx, toff, poff
+
+
+F32, I32, U8 = torch.float32, torch.int32, torch.uint8
+
+
+def project(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes,
+            near, far, eps2d, tile, splats, depths, radii, tiles_touched, flags):
+    n = means.shape[1]
+    sz, szp = _host_i32(sizes)
+    rc = lib().gs_project(_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
+                          _ptr(quats, F32, "quats"), _ptr(opacity_logits, F32, "opacity_logits"),
+                          _ptr(sh, F32, "sh"), n, int(sh_degree), _ptr(viewmats, F32, "viewmats"),
+                          _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(near), float(far),
+                          float(eps2d), int(tile), _ptr(splats, F32, "splats"), _ptr(depths, F32, "depths"),
+                          _ptr(radii, I32, "radii"), _ptr(tiles_touched, I32, "tiles_touched"),
+                          _ptr(flags, U8, "flags"), _stream())
+    _check(rc, "gs_project")
+
+
+def bin_sort_workspace_size(n, n_views, capacity, total_tiles):
+    return int(lib().gs_bin_sort_workspace_size(n, n_views, capacity, total_tiles))
+
+
+def bin_sort(splats, depths, radii, tiles_touched, n, sizes, tile, capacity, workspace, isect_tile,
+             isect_gid, tile_ranges, info):
+    sz, szp = _host_i32(sizes)
+    rc = lib().gs_bin_sort(_ptr(splats, F32, "splats"), _ptr(depths, F32, "depths"),
+                           _ptr(radii, I32, "radii"), _ptr(tiles_touched, I32, "tiles_touched"), n,
+                           sz.shape[0], szp, int(tile), int(capacity), _ptr(workspace, U8, "workspace"),
+                           workspace.numel(), _ptr(isect_tile, I32, "isect_tile"),
+                           _ptr(isect_gid, I32, "isect_gid"), _ptr(tile_ranges, I32, "tile_ranges"),
+                           _ptr(info, I32, "info"), _stream())
+    _check(rc, "gs_bin_sort")
+
+
+def tile_schedule_size(total_tiles):
+    return int(lib().gs_tile_schedule_size(total_tiles))
+
+
+def tile_schedule(tile_ranges, total_tiles, schedule):
+    rc = lib().gs_tile_schedule(_ptr(tile_ranges, I32, "tile_ranges"), int(total_tiles),
+                                _ptr(schedule, U8, "schedule"), schedule.numel(), _stream())
+    _check(rc, "gs_tile_schedule")
+
+
+def rasterize_fwd(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, queue, images,
+                  T_final, n_contrib):
+    sz, szp = _host_i32(sizes)
+    bg, bgp = _host_f32(background)
+    rc = lib().gs_rasterize_fwd(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
+                                _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile), bgp,
+                                _ptr(schedule, U8, "schedule"), _ptr(queue, I32, "queue"),
+                                _ptr(images, F32, "images"), _ptr(T_final, F32, "T_final"),
+                                _ptr(n_contrib, I32, "n_contrib"), _stream())
+    _check(rc, "gs_rasterize_fwd")
+
+
+def rasterize_bwd(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, queue, T_final,
+                  n_contrib, d_images, d_alpha, grad2d, accumulate=False):
+    sz, szp = _host_i32(sizes)
+    bg, bgp = _host_f32(background)
+    rc = lib().gs_rasterize_bwd(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
+                                _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile), bgp,
+                                _ptr(schedule, U8, "schedule"), _ptr(queue, I32, "queue"),
+                                _ptr(T_final, F32, "T_final"), _ptr(n_contrib, I32, "n_contrib"),
+                                _ptr(d_images, F32, "d_images"), _ptr(d_alpha, F32, "d_alpha"),
+                                _ptr(grad2d, F32, "grad2d"), int(bool(accumulate)), _stream())
+    _check(rc, "gs_rasterize_bwd")
+
+
+def project_bwd(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes,
+                eps2d, flags, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits, d_sh):
+    n = means.shape[1]
+    sz, szp = _host_i32(sizes)
+    rc = lib().gs_project_bwd(_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
+                              _ptr(quats, F32, "quats"), _ptr(opacity_logits, F32, "opacity_logits"),
+                              _ptr(sh, F32, "sh"), n, int(sh_degree), _ptr(viewmats, F32, "viewmats"),
+                              _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(eps2d),
+                              _ptr(flags, U8, "flags"), _ptr(grad2d, F32, "grad2d"),
+                              _ptr(d_means, F32, "d_means"), _ptr(d_log_scales, F32, "d_log_scales"),
+                              _ptr(d_quats, F32, "d_quats"), _ptr(d_opacity_logits, F32, "d_opacity_logits"),
+                              _ptr(d_sh, F32, "d_sh"), _stream())
+    _check(rc, "gs_project_bwd")
+
+
+def loss_workspace_size(n_elems):
+    return int(lib().gs_loss_workspace_size(n_elems))
+
+
+def loss_l2(images, targets, loss, d_images, workspace):
+    rc = lib().gs_loss_l2(_ptr(images, F32, "images"), _ptr(targets, F32, "targets"), images.numel(),
+                          _ptr(loss, F32, "loss"), _ptr(d_images, F32, "d_images"),
+                          _ptr(workspace, U8, "workspace"), workspace.numel(), _stream())
+    _check(rc, "gs_loss_l2")
+
+
+def raster_visits(splats, isect_gid, tile_ranges, n, sizes, tile, images, T_final, n_contrib, visits):
+    sz, szp = _host_i32(sizes)
+    rc = lib().gs_raster_visits(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
+                                _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile),
+                                _ptr(images, F32, "images"), _ptr(T_final, F32, "T_final"),
+                                _ptr(n_contrib, I32, "n_contrib"), _ptr(visits, I32, "visits"), _stream())
+    _check(rc, "gs_raster_visits")

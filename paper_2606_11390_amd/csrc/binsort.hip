@@ -1,0 +1,605 @@
+// Tile binning with a stable radix sort on the (tile id | depth) key (gfx950).
+//
+// Paper Section 4: per camera the Gaussians are sorted by depth before
+// rasterisation, with one record per (Gaussian, tile) intersection; the paper
+// uses a CUB radix sort.  The result here is the stable sort of the 64-bit
+// key (global tile id << 32) | bits(depth) over intersections enumerated
+// (view, Gaussian, tile row-major).
+//
+// An LSD radix sort processes the low (depth) digits first.  All intersections
+// of one (view, Gaussian) pair share its depth, so the depth passes are run
+// once per visible pair instead of once per intersection:
+//   1. depth passes (4 x 8 bits) over the visible (view, Gaussian) pairs,
+//      the first pass compacting them out of the projection outputs;
+//   2. exclusive scan of tiles_touched in that order;
+//   3. load-balanced emission of (global tile id, Gaussian) pairs, each
+//      pair's tiles in row-major order;
+//   4. stable passes over the tile-id bits;
+//   5. per-tile [start, end) ranges.
+// Because every pass is stable, this equals the stable sort of the full key
+// over the (view, Gaussian, tile) enumeration, equal keys in Gaussian order.
+//
+// Each pass is reduce-then-scan: per-block digit histograms, a per-digit scan
+// across blocks, then a scatter that ranks keys stably inside 2048-key chunks
+// (wave ballots match equal digits, wave-private LDS counters order waves)
+// and writes them through LDS so that runs of equal digits leave coalesced.
+// Every element count is read from device memory, so no call syncs the host.
+#include "gs_device.h"
+
+namespace gs {
+namespace {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / GS_WAVE;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;     // keys per chunk
+constexpr int RS_WAVE_SPAN = GS_WAVE * RS_ITEMS;     // keys per wave per chunk
+constexpr int RS_MAX_BLOCKS = 1024;
+
+enum Source { SRC_PAIRS = 0, SRC_PROJ = 1, SRC_TILE_LEN = 2 };
+
+struct SortIO {
+    const uint32_t* keys_in;   // SRC_PAIRS
+    const uint32_t* vals_in;
+    const float* depths;       // SRC_PROJ
+    const int* tiles;
+    const int2* ranges;        // SRC_TILE_LEN
+    uint32_t* keys_out;
+    uint32_t* vals_out;
+    uint32_t n_const;          // element count when n_dev is NULL
+    const uint32_t* n_dev;     // device element count
+};
+
+__device__ __forceinline__ uint32_t io_count(const SortIO& io)
+{
+    return io.n_dev ? *io.n_dev : io.n_const;
+}
+
+__device__ __forceinline__ void block_span(uint32_t n, int nb, int b, uint32_t& beg, uint32_t& end)
+{
+    uint32_t per = (n + (uint32_t)nb - 1u) / (uint32_t)nb;
+    per = (per + RS_CHUNK - 1u) / RS_CHUNK * RS_CHUNK;
+    const unsigned long long b0 = (unsigned long long)per * (unsigned)b;
+    beg = (uint32_t)min((unsigned long long)n, b0);
+    end = (uint32_t)min((unsigned long long)n, b0 + per);
+}
+
+template <int SRC>
+__device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t end, uint32_t& k,
+                                        uint32_t& v)
+{
+    if (i >= end) return false;
+    if (SRC == SRC_PAIRS) {
+        k = io.keys_in[i];
+        v = io.vals_in[i];
+        return true;
+    } else if (SRC == SRC_PROJ) {
+        if (io.tiles[i] <= 0) return false;
+        k = __float_as_uint(io.depths[i]);
+        v = i;
+        return true;
+    } else {
+        const int2 r = io.ranges[i];
+        const uint32_t len = (uint32_t)min(r.y - r.x, 0xFFFF);
+        k = 0xFFFFu - len;
+        v = i;
+        return true;
+    }
+}
+
+// lanes of the wave holding the same `bits`-bit digit as this lane
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits)
+{
+    uint64_t m = __ballot(valid);
+    for (int k = 0; k < bits; k++) {
+        const bool bit = (d >> k) & 1u;
+        const uint64_t b = __ballot(bit);
+        m &= bit ? b : ~b;
+    }
+    return valid ? m : 0ull;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const int l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// exclusive scan of one uint32 per thread over a 256-thread block
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t* s_tmp, uint32_t& total)
+{
+    const int lane = __lane_id(), w = threadIdx.x / GS_WAVE;
+    uint32_t inc = x;
+    for (int o = 1; o < GS_WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == GS_WAVE - 1) s_tmp[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (int i = 0; i < RS_WAVES; i++) {
+        const uint32_t t = s_tmp[i];
+        if (i < w) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + inc - x;
+}
+
+template <int SRC>
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortIO io, int shift, int bits,
+                                                        uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t s_cnt[RS_WAVES][256];
+    const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x, w = t / GS_WAVE;
+    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t n = io_count(io);
+    uint32_t beg, end;
+    block_span(n, nb, b, beg, end);
+    const uint32_t mask = (1u << bits) - 1u;
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t base = beg; base < end; base += RS_THREADS) {
+        uint32_t k = 0, v = 0;
+        const bool valid = load_kv<SRC>(io, base + t, end, k, v);
+        const uint32_t d = (k >> shift) & mask;
+        const uint64_t peers = match_digit(d, valid, bits);
+        if (valid && (peers & lt) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    if (t < 256) {
+        uint32_t s = 0;
+        for (int i = 0; i < RS_WAVES; i++) s += s_cnt[i][t];
+        hist[(size_t)t * nb + b] = s;
+    }
+}
+
+// one block per digit: exclusive scan of its counts across the nb blocks
+__global__ __launch_bounds__(1024) void k_rs_spine(uint32_t* __restrict__ hist, int nb,
+                                                   uint32_t* __restrict__ dtot)
+{
+    __shared__ uint32_t s_w[16];
+    const int d = blockIdx.x, t = threadIdx.x, lane = __lane_id(), w = t / GS_WAVE;
+    const int nw = (blockDim.x + GS_WAVE - 1) / GS_WAVE;
+    const uint32_t x = t < nb ? hist[(size_t)d * nb + t] : 0u;
+    uint32_t inc = x;
+    for (int o = 1; o < GS_WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == GS_WAVE - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int i = 0; i < nw; i++) {
+        if (i < w) before += s_w[i];
+        total += s_w[i];
+    }
+    if (t < nb) hist[(size_t)d * nb + t] = before + inc - x;
+    if (t == 0) dtot[d] = total;
+}
+
+template <int SRC>
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift, int bits,
+                                                           const uint32_t* __restrict__ excl,
+                                                           const uint32_t* __restrict__ dtot,
+                                                           uint32_t* __restrict__ count_out)
+{
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_wcnt[RS_WAVES][256];
+    __shared__ uint32_t s_cex[256];
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    __shared__ uint32_t s_k[RS_CHUNK];
+    __shared__ uint32_t s_v[RS_CHUNK];
+    const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x, w = t / GS_WAVE, lane = __lane_id();
+    const uint32_t mask = (1u << bits) - 1u;
+
+    // global start of each digit for this block
+    uint32_t all;
+    const uint32_t dbase = block_excl_scan_256(dtot[t], s_tmp, all);
+    s_base[t] = dbase + excl[(size_t)t * nb + b];
+    if (count_out && b == 0 && t == 0) *count_out = all;
+
+    const uint32_t n = io_count(io);
+    uint32_t beg, end;
+    block_span(n, nb, b, beg, end);
+    const uint64_t lt = lanemask_lt();
+
+    for (uint32_t cb = beg; cb < end; cb += RS_CHUNK) {
+        for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&s_wcnt[0][0])[i] = 0;
+        __syncthreads();
+        uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
+        bool ok[RS_ITEMS];
+        const uint32_t wb = cb + (uint32_t)w * RS_WAVE_SPAN;
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
+            key[r] = 0;
+            val[r] = 0;
+            ok[r] = load_kv<SRC>(io, wb + (uint32_t)(r * GS_WAVE + lane), end, key[r], val[r]);
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint64_t peers = match_digit(d, ok[r], bits);
+            const uint32_t before = s_wcnt[w][d];
+            rank[r] = before + (uint32_t)__popcll(peers & lt);
+            if (ok[r] && (peers & lt) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        // per digit: exclusive prefix across waves, chunk total, chunk digit start
+        uint32_t wp[RS_WAVES], tot = 0;
+        for (int i = 0; i < RS_WAVES; i++) {
+            wp[i] = tot;
+            tot += s_wcnt[i][t];
+        }
+        uint32_t ctot;
+        const uint32_t cex = block_excl_scan_256(tot, s_tmp, ctot);
+        s_cex[t] = cex;
+        for (int i = 0; i < RS_WAVES; i++) s_wcnt[i][t] = wp[i];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
+            if (!ok[r]) continue;
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t pos = s_cex[d] + s_wcnt[w][d] + rank[r];
+            s_k[pos] = key[r];
+            s_v[pos] = val[r];
+        }
+        __syncthreads();
+        for (uint32_t j = t; j < ctot; j += RS_THREADS) {
+            const uint32_t k = s_k[j];
+            const uint32_t d = (k >> shift) & mask;
+            const uint32_t dst = s_base[d] + j - s_cex[d];
+            io.keys_out[dst] = k;
+            io.vals_out[dst] = s_v[j];
+        }
+        __syncthreads();
+        s_base[t] += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scan of tiles_touched in depth order, intersection count, overflow
+// ---------------------------------------------------------------------------
+constexpr int SC_THREADS = 256;
+constexpr int SC_ITEMS = 8;
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ pids,
+                                                            const int* __restrict__ tiles,
+                                                            const uint32_t* __restrict__ n_dev,
+                                                            uint32_t* __restrict__ part)
+{
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+    uint32_t beg, end;
+    block_span(*n_dev, nb, b, beg, end);
+    uint32_t s = 0;
+    for (uint32_t i = beg + t; i < end; i += SC_THREADS) s += (uint32_t)tiles[pids[i]];
+    uint32_t tot;
+    block_excl_scan_256(s, s_tmp, tot);
+    if (t == 0) part[b] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_spine(const uint32_t* __restrict__ part, int nb,
+                                                     unsigned long long* __restrict__ part_ex,
+                                                     uint32_t capacity, uint32_t* __restrict__ cnt,
+                                                     int* __restrict__ info)
+{
+    __shared__ unsigned long long s_w[16];
+    const int t = threadIdx.x, lane = __lane_id(), w = t / GS_WAVE;
+    const unsigned long long x = t < nb ? part[t] : 0ull;
+    unsigned long long inc = x;
+    for (int o = 1; o < GS_WAVE; o <<= 1) {
+        const unsigned long long y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == GS_WAVE - 1) s_w[w] = inc;
+    __syncthreads();
+    unsigned long long before = 0, total = 0;
+    for (int i = 0; i < (int)(blockDim.x / GS_WAVE); i++) {
+        if (i < w) before += s_w[i];
+        total += s_w[i];
+    }
+    if (t < nb) part_ex[t] = before + inc - x;
+    if (t == 0) {
+        const unsigned long long cap = capacity;
+        cnt[1] = (uint32_t)(total < cap ? total : cap);
+        info[GS_INFO_VISIBLE] = (int)cnt[0];
+        info[GS_INFO_ISECT] = (int)(total < 0x7FFFFFFFull ? total : 0x7FFFFFFFull);
+        info[GS_INFO_OVERFLOW] = total > cap ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __restrict__ pids,
+                                                          const int* __restrict__ tiles,
+                                                          const uint32_t* __restrict__ n_dev,
+                                                          const unsigned long long* __restrict__ part_ex,
+                                                          uint32_t capacity,
+                                                          uint32_t* __restrict__ offs)
+{
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+    uint32_t beg, end;
+    block_span(*n_dev, nb, b, beg, end);
+    unsigned long long carry = part_ex[b];
+    for (uint32_t cb = beg; cb < end; cb += SC_THREADS * SC_ITEMS) {
+        // thread t owns SC_ITEMS consecutive elements
+        uint32_t x[SC_ITEMS], s = 0;
+        const uint32_t i0 = cb + (uint32_t)t * SC_ITEMS;
+        for (int r = 0; r < SC_ITEMS; r++) {
+            const uint32_t i = i0 + r;
+            x[r] = i < end ? (uint32_t)tiles[pids[i]] : 0u;
+            s += x[r];
+        }
+        uint32_t tot;
+        uint32_t run = block_excl_scan_256(s, s_tmp, tot);
+        for (int r = 0; r < SC_ITEMS; r++) {
+            const uint32_t i = i0 + r;
+            if (i < end) {
+                const unsigned long long o = carry + run;
+                offs[i] = (uint32_t)(o < capacity ? o : capacity);
+            }
+            run += x[r];
+        }
+        carry += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// load-balanced emission: one block per EMIT_SPAN consecutive output slots
+// ---------------------------------------------------------------------------
+constexpr int EMIT_THREADS = 256;
+constexpr int EMIT_SPAN = 2048;
+
+__global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restrict__ pids,
+                                                       const uint32_t* __restrict__ offs,
+                                                       const uint32_t* __restrict__ cnt,
+                                                       const float* __restrict__ splats,
+                                                       const int2* __restrict__ radii,
+                                                       long long N, ViewTable vt, int tile,
+                                                       uint32_t* __restrict__ keys_out,
+                                                       uint32_t* __restrict__ vals_out)
+{
+    __shared__ uint32_t s_off[EMIT_SPAN + 1];
+    __shared__ uint32_t s_gid[EMIT_SPAN + 1];
+    __shared__ uint32_t s_base[EMIT_SPAN + 1];
+    __shared__ uint32_t s_wt[EMIT_SPAN + 1];    // rect width << 16 | tiles_x... kept separate
+    __shared__ uint32_t s_tx[EMIT_SPAN + 1];
+    __shared__ uint32_t s_src[2];
+    const uint32_t n_src = cnt[0], m = cnt[1];
+    const uint32_t start = blockIdx.x * (uint32_t)EMIT_SPAN;
+    if (start >= m) return;
+    const uint32_t end = min(m, start + (uint32_t)EMIT_SPAN);
+    const int t = threadIdx.x;
+    if (t < 2) {
+        // last source whose offset is <= target
+        const uint32_t target = t == 0 ? start : end - 1;
+        uint32_t lo = 0, hi = n_src - 1;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo + 1) / 2;
+            if (offs[mid] <= target) lo = mid; else hi = mid - 1;
+        }
+        s_src[t] = lo;
+    }
+    __syncthreads();
+    const uint32_t s0 = s_src[0], ns = s_src[1] - s0 + 1;
+    for (uint32_t k = t; k < ns; k += EMIT_THREADS) {
+        const uint32_t s = s0 + k;
+        const uint32_t pid = pids[s];
+        const uint32_t v = (uint32_t)(pid / (unsigned long long)N);
+        const uint32_t g = pid - v * (uint32_t)N;
+        const float* rec = splats + (size_t)pid * GS_SPLAT_FLOATS;
+        const int2 r = radii[pid];
+        int x0, y0, x1, y1;
+        tile_rect(rec[0], rec[1], r.x, r.y, tile, vt.W[v], vt.H[v], x0, y0, x1, y1);
+        const int TX = vt.tiles_x[v];
+        s_off[k] = offs[s];
+        s_gid[k] = g;
+        s_base[k] = (uint32_t)(vt.tile_off[v] + y0 * TX + x0);
+        s_wt[k] = (uint32_t)(x1 - x0);
+        s_tx[k] = (uint32_t)TX;
+    }
+    __syncthreads();
+    for (uint32_t i = start + t; i < end; i += EMIT_THREADS) {
+        uint32_t lo = 0, hi = ns - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t j = i - s_off[lo];
+        const uint32_t wdt = s_wt[lo];
+        const uint32_t row = j / wdt, col = j - row * wdt;
+        keys_out[i] = s_base[lo] + row * s_tx[lo] + col;
+        vals_out[i] = s_gid[lo];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile ranges
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int* __restrict__ p, int value, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ cnt,
+                         uint32_t total_tiles, int2* __restrict__ ranges)
+{
+    const uint32_t m = cnt[1];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t k = keys[i];
+    if (k >= total_tiles) return;   // cannot happen for consistent inputs; never write out of range
+    if (i == 0 || keys[i - 1] != k) ranges[k].x = (int)i;
+    if (i == m - 1 || keys[i + 1] != k) ranges[k].y = (int)(i + 1);
+}
+
+int sort_blocks(unsigned long long n_max)
+{
+    unsigned long long nb = (n_max + 2 * RS_CHUNK - 1) / (2 * RS_CHUNK);
+    if (nb < 1) nb = 1;
+    if (nb > RS_MAX_BLOCKS) nb = RS_MAX_BLOCKS;
+    return (int)nb;
+}
+
+template <int SRC>
+hipError_t radix_pass(const SortIO& io, int nb, int shift, int bits, uint32_t* hist, uint32_t* dtot,
+                      uint32_t* count_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rs_hist<SRC>, dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
+    const int sp_threads = ((nb + GS_WAVE - 1) / GS_WAVE) * GS_WAVE;
+    hipLaunchKernelGGL(k_rs_spine, dim3(256), dim3(sp_threads), 0, st, hist, nb, dtot);
+    hipLaunchKernelGGL(k_rs_scatter<SRC>, dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
+                       dtot, count_out);
+    return hipGetLastError();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BinWs {
+    uint32_t *dk0, *dv0, *dk1, *dv1, *offs, *tk, *tv, *hist, *dtot, *part, *cnt;
+    unsigned long long* part_ex;
+    size_t bytes;
+};
+
+BinWs bin_layout(char* base, unsigned long long vn, unsigned long long cap)
+{
+    BinWs w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + o;
+        o += align256(bytes);
+        return p;
+    };
+    w.dk0 = (uint32_t*)take(4 * vn);
+    w.dv0 = (uint32_t*)take(4 * vn);
+    w.dk1 = (uint32_t*)take(4 * vn);
+    w.dv1 = (uint32_t*)take(4 * vn);
+    w.offs = (uint32_t*)take(4 * vn);
+    w.tk = (uint32_t*)take(4 * cap);
+    w.tv = (uint32_t*)take(4 * cap);
+    w.hist = (uint32_t*)take(4ull * 256 * RS_MAX_BLOCKS);
+    w.dtot = (uint32_t*)take(4 * 256);
+    w.part = (uint32_t*)take(4 * RS_MAX_BLOCKS);
+    w.part_ex = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
+    w.cnt = (uint32_t*)take(4 * 16);
+    w.bytes = o;
+    return w;
+}
+
+int bits_for(unsigned long long n)
+{
+    int b = 1;
+    while (b < 32 && (1ull << b) < n) b++;
+    return b;
+}
+
+}  // namespace
+
+size_t bin_sort_workspace_size(unsigned long long vn, unsigned long long cap)
+{
+    return bin_layout(nullptr, vn, cap).bytes;
+}
+
+hipError_t launch_bin_sort(const float* splats, const float* depths, const int2* radii,
+                           const int* tiles, long long N, const ViewTable& vt, int tile,
+                           unsigned long long cap, void* workspace, uint32_t* isect_tile,
+                           uint32_t* isect_gid, int2* ranges, int* info, hipStream_t st)
+{
+    const unsigned long long vn = (unsigned long long)N * vt.n_views;
+    BinWs w = bin_layout((char*)workspace, vn, cap);
+    hipError_t e;
+    // 1. depth passes over visible (view, Gaussian) pairs
+    const int nb_d = sort_blocks(vn);
+    SortIO io{};
+    io.depths = depths;
+    io.tiles = tiles;
+    io.keys_out = w.dk0;
+    io.vals_out = w.dv0;
+    io.n_const = (uint32_t)vn;
+    if ((e = radix_pass<SRC_PROJ>(io, nb_d, 0, 8, w.hist, w.dtot, w.cnt + 0, st)) != hipSuccess) return e;
+    uint32_t *ki = w.dk0, *vi = w.dv0, *ko = w.dk1, *vo = w.dv1;
+    for (int pass = 1; pass < 4; pass++) {
+        SortIO p{};
+        p.keys_in = ki; p.vals_in = vi; p.keys_out = ko; p.vals_out = vo;
+        p.n_dev = w.cnt + 0;
+        if ((e = radix_pass<SRC_PAIRS>(p, nb_d, 8 * pass, 8, w.hist, w.dtot, nullptr, st)) != hipSuccess)
+            return e;
+        uint32_t* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+    }
+    const uint32_t* pids = vi;   // visible pairs in (depth, view, Gaussian) order
+
+    // 2. scan of tiles_touched in that order
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb_d), dim3(SC_THREADS), 0, st, pids, tiles, w.cnt + 0, w.part);
+    hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, st, w.part, nb_d, w.part_ex, (uint32_t)cap,
+                       w.cnt, info);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb_d), dim3(SC_THREADS), 0, st, pids, tiles, w.cnt + 0,
+                       w.part_ex, (uint32_t)cap, w.offs);
+
+    // 3. emission; 4. tile passes (the last one lands in the caller's arrays)
+    const int tbits = bits_for((unsigned long long)vt.total_tiles);
+    const int tpasses = (tbits + 7) / 8;
+    uint32_t *ek = (tpasses % 2 == 0) ? isect_tile : w.tk;
+    uint32_t *ev = (tpasses % 2 == 0) ? isect_gid : w.tv;
+    const unsigned emit_blocks = (unsigned)((cap + EMIT_SPAN - 1) / EMIT_SPAN);
+    hipLaunchKernelGGL(k_emit, dim3(emit_blocks), dim3(EMIT_THREADS), 0, st, pids, w.offs, w.cnt, splats,
+                       radii, N, vt, tile, ek, ev);
+    const int nb_t = sort_blocks(cap);
+    uint32_t *tki = ek, *tvi = ev;
+    uint32_t *tko = (ek == isect_tile) ? w.tk : isect_tile, *tvo = (ev == isect_gid) ? w.tv : isect_gid;
+    for (int pass = 0; pass < tpasses; pass++) {
+        const int shift = 8 * pass, bits = min(8, tbits - shift);
+        SortIO p{};
+        p.keys_in = tki; p.vals_in = tvi; p.keys_out = tko; p.vals_out = tvo;
+        p.n_dev = w.cnt + 1;
+        if ((e = radix_pass<SRC_PAIRS>(p, nb_t, shift, bits, w.hist, w.dtot, nullptr, st)) != hipSuccess)
+            return e;
+        uint32_t* tk = tki; tki = tko; tko = tk;
+        uint32_t* tv = tvi; tvi = tvo; tvo = tv;
+    }
+
+    // 5. ranges
+    const long long nr = 2ll * vt.total_tiles;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, (int*)ranges, 0, nr);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, isect_tile, w.cnt,
+                       (uint32_t)vt.total_tiles, ranges);
+    return hipGetLastError();
+}
+
+size_t tile_schedule_size(long long total_tiles)
+{
+    const size_t t = (size_t)total_tiles;
+    return align256(4 * t) + 3 * align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS) + align256(4 * 256);
+}
+
+hipError_t launch_tile_schedule(const int2* ranges, long long total_tiles, void* schedule, hipStream_t st)
+{
+    char* base = (char*)schedule;
+    const size_t t = (size_t)total_tiles;
+    uint32_t* order = (uint32_t*)base;
+    uint32_t* k0 = (uint32_t*)(base + align256(4 * t));
+    uint32_t* k1 = (uint32_t*)(base + 2 * align256(4 * t));
+    uint32_t* v1 = (uint32_t*)(base + 3 * align256(4 * t));
+    uint32_t* hist = (uint32_t*)(base + 4 * align256(4 * t));
+    uint32_t* dtot = (uint32_t*)(base + 4 * align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS));
+    const int nb = sort_blocks(t);
+    SortIO a{};
+    a.ranges = ranges;
+    a.keys_out = k0;
+    a.vals_out = v1;
+    a.n_const = (uint32_t)t;
+    hipError_t e;
+    if ((e = radix_pass<SRC_TILE_LEN>(a, nb, 0, 8, hist, dtot, nullptr, st)) != hipSuccess) return e;
+    SortIO b{};
+    b.keys_in = k0; b.vals_in = v1; b.keys_out = k1; b.vals_out = order;
+    b.n_const = (uint32_t)t;
+    return radix_pass<SRC_PAIRS>(b, nb, 8, 8, hist, dtot, nullptr, st);
+}
+
+hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, value, n);
+    return hipGetLastError();
+}
+
+}  // namespace gs

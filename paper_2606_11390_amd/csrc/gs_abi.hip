@@ -1,0 +1,257 @@
+// extern "C" entry points of include/gs.h: host-side argument checks, the
+// per-launch view table, and kernel launches on the caller's stream.
+#include <cmath>
+
+#include "gs_device.h"
+
+namespace gs {
+hipError_t launch_project(int deg, const float* means, const float* log_scales, const float* quats,
+                          const float* opac, const float* sh, long long N, const float* viewmats,
+                          const float* intr, const ViewTable& vt, float near_plane, float far_plane,
+                          float eps2d, int tile, float* splats, float* depths, int2* radii,
+                          int* tiles, uint8_t* flags, hipStream_t stream);
+hipError_t launch_project_bwd(int deg, const float* means, const float* log_scales,
+                              const float* quats, const float* opac, const float* sh, long long N,
+                              const float* viewmats, const float* intr, const ViewTable& vt,
+                              float eps2d, const uint8_t* flags, const float* grad2d,
+                              float* d_means, float* d_log_scales, float* d_quats, float* d_opac,
+                              float* d_sh, hipStream_t stream);
+size_t bin_sort_workspace_size(unsigned long long vn, unsigned long long cap);
+hipError_t launch_bin_sort(const float* splats, const float* depths, const int2* radii,
+                           const int* tiles, long long N, const ViewTable& vt, int tile,
+                           unsigned long long cap, void* workspace, uint32_t* isect_tile,
+                           uint32_t* isect_gid, int2* ranges, int* info, hipStream_t st);
+size_t tile_schedule_size(long long total_tiles);
+hipError_t launch_tile_schedule(const int2* ranges, long long total_tiles, void* schedule,
+                                hipStream_t st);
+hipError_t launch_raster_fwd(int tile, const ViewTable& vt, const float* splats, const int* gids,
+                             const int2* ranges, long long N, const float* bg, const int* order,
+                             int* queue, float* img, float* Tout, int* lastout, int* visits,
+                             hipStream_t st);
+hipError_t launch_raster_bwd(int tile, const ViewTable& vt, const float* splats, const int* gids,
+                             const int2* ranges, long long N, const float* bg, const int* order,
+                             int* queue, const float* Tfin, const int* nlast, const float* dimg,
+                             const float* dalpha, float* grad2d, hipStream_t st);
+size_t loss_workspace_size(long long n);
+hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
+hipError_t launch_loss_l2(const float* img, const float* tgt, long long n, float* loss, float* dimg,
+                          void* ws, hipStream_t st);
+}  // namespace gs
+
+namespace {
+
+using gs::ViewTable;
+
+bool tile_ok(int tile) { return tile == 8 || tile == 16 || tile == 32; }
+
+// Fills the view table from host sizes; returns false on a bad size list.
+bool make_views(const int32_t* sizes, int n_views, int tile, ViewTable& vt)
+{
+    if (!sizes || n_views < 1 || n_views > GS_MAX_VIEWS) return false;
+    vt.n_views = n_views;
+    vt.tile_off[0] = 0;
+    vt.pix_off[0] = 0;
+    long long tiles = 0, pix = 0;
+    for (int v = 0; v < n_views; v++) {
+        const int W = sizes[2 * v], H = sizes[2 * v + 1];
+        if (W <= 0 || H <= 0 || W > 65536 || H > 65536) return false;
+        const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
+        vt.W[v] = W;
+        vt.H[v] = H;
+        vt.tiles_x[v] = TX;
+        tiles += (long long)TX * TY;
+        pix += (long long)W * H;
+        if (tiles > 0x3FFFFFFFll) return false;
+        vt.tile_off[v + 1] = (int)tiles;
+        vt.pix_off[v + 1] = pix;
+    }
+    vt.total_tiles = (int)tiles;
+    return true;
+}
+
+int status(hipError_t e) { return e == hipSuccess ? GS_OK : GS_ERR_HIP; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int gs_abi_version(void) { return GS_ABI_VERSION; }
+
+const char* gs_strerror(int code)
+{
+    switch (code) {
+    case GS_OK: return "ok";
+    case GS_ERR_ARG: return "invalid argument";
+    case GS_ERR_UNSUPPORTED: return "unsupported request";
+    case GS_ERR_HIP: return "HIP launch or runtime error";
+    case GS_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown gs_status";
+    }
+}
+
+int gs_project(const float* means, const float* log_scales, const float* quats,
+               const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
+               const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
+               float near_plane, float far_plane, float eps2d, int tile, float* splats, float* depths,
+               int32_t* radii, int32_t* tiles_touched, uint8_t* flags, void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || sh_degree < 0 || sh_degree > 3 || !tile_ok(tile) ||
+        !make_views(sizes, n_views, tile, vt))
+        return GS_ERR_ARG;
+    if ((unsigned long long)n * (unsigned long long)n_views > 0xFFFFFFFFull) return GS_ERR_ARG;
+    if (!(eps2d >= 0.0f) || !(near_plane > 0.0f) || !(far_plane > near_plane)) return GS_ERR_ARG;
+    if (n == 0) return GS_OK;
+    if (!means || !log_scales || !quats || !opacity_logits || !sh || !viewmats || !intrinsics ||
+        !splats || !depths || !radii || !tiles_touched || !flags || !aligned16(splats))
+        return GS_ERR_ARG;
+    return status(gs::launch_project(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
+                                     intrinsics, vt, near_plane, far_plane, eps2d, tile, splats, depths,
+                                     reinterpret_cast<int2*>(radii), tiles_touched, flags,
+                                     as_stream(stream)));
+}
+
+size_t gs_bin_sort_workspace_size(int64_t n, int n_views, int64_t capacity, int64_t total_tiles)
+{
+    (void)total_tiles;
+    if (n < 0 || n_views < 1 || capacity < 1) return 0;
+    return gs::bin_sort_workspace_size((unsigned long long)n * (unsigned long long)n_views,
+                                       (unsigned long long)capacity);
+}
+
+int gs_bin_sort(const float* splats, const float* depths, const int32_t* radii,
+                const int32_t* tiles_touched, int64_t n, int n_views, const int32_t* sizes, int tile,
+                int64_t capacity, void* workspace, size_t workspace_bytes, int32_t* isect_tile,
+                int32_t* isect_gid, int32_t* tile_ranges, int32_t* info, void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
+        return GS_ERR_ARG;
+    if ((unsigned long long)n * (unsigned long long)n_views > 0xFFFFFFFFull) return GS_ERR_ARG;
+    if (capacity < 1 || capacity > 0x7FFFFFFFll) return GS_ERR_ARG;
+    if (!isect_tile || !isect_gid || !tile_ranges || !info || !workspace) return GS_ERR_ARG;
+    if (n > 0 && (!splats || !depths || !radii || !tiles_touched)) return GS_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return GS_ERR_ARG;
+    if (workspace_bytes < gs_bin_sort_workspace_size(n, n_views, capacity, vt.total_tiles))
+        return GS_ERR_WORKSPACE;
+    return status(gs::launch_bin_sort(splats, depths, reinterpret_cast<const int2*>(radii), tiles_touched, n,
+                                      vt, tile, (unsigned long long)capacity, workspace,
+                                      reinterpret_cast<uint32_t*>(isect_tile),
+                                      reinterpret_cast<uint32_t*>(isect_gid),
+                                      reinterpret_cast<int2*>(tile_ranges), info, as_stream(stream)));
+}
+
+size_t gs_tile_schedule_size(int64_t total_tiles)
+{
+    if (total_tiles < 1 || total_tiles > 0x3FFFFFFFll) return 0;
+    return gs::tile_schedule_size(total_tiles);
+}
+
+int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* schedule,
+                     size_t schedule_bytes, void* stream)
+{
+    if (!tile_ranges || !schedule || total_tiles < 1 || total_tiles > 0x3FFFFFFFll) return GS_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(schedule) & 255u) != 0) return GS_ERR_ARG;
+    if (schedule_bytes < gs::tile_schedule_size(total_tiles)) return GS_ERR_WORKSPACE;
+    return status(gs::launch_tile_schedule(reinterpret_cast<const int2*>(tile_ranges), total_tiles, schedule,
+                                           as_stream(stream)));
+}
+
+int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
+                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
+                     const void* schedule, int32_t* queue, float* images, float* T_final,
+                     int32_t* n_contrib, void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
+        return GS_ERR_ARG;
+    if (!tile_ranges || !images || !T_final || !n_contrib || !background) return GS_ERR_ARG;
+    if (!isect_gid || (n > 0 && (!splats || !aligned16(splats)))) return GS_ERR_ARG;
+    if (schedule && !queue) return GS_ERR_ARG;
+    for (int c = 0; c < 3; c++)
+        if (!std::isfinite(background[c])) return GS_ERR_ARG;
+    return status(gs::launch_raster_fwd(tile, vt, splats, isect_gid, reinterpret_cast<const int2*>(tile_ranges),
+                                        n, background, static_cast<const int*>(schedule), queue, images,
+                                        T_final, n_contrib, nullptr, as_stream(stream)));
+}
+
+int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
+                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
+                     const void* schedule, int32_t* queue, const float* T_final,
+                     const int32_t* n_contrib, const float* d_images, const float* d_alpha,
+                     float* grad2d, int accumulate, void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
+        return GS_ERR_ARG;
+    if (!tile_ranges || !T_final || !n_contrib || !d_images || !grad2d || !background || !isect_gid)
+        return GS_ERR_ARG;
+    if (n > 0 && (!splats || !aligned16(splats))) return GS_ERR_ARG;
+    if (schedule && !queue) return GS_ERR_ARG;
+    for (int c = 0; c < 3; c++)
+        if (!std::isfinite(background[c])) return GS_ERR_ARG;
+    if (!accumulate) {
+        const hipError_t e = gs::launch_fill_i32(reinterpret_cast<int*>(grad2d), 0,
+                                                 n * n_views * GS_GRAD_FLOATS, as_stream(stream));
+        if (e != hipSuccess) return GS_ERR_HIP;
+    }
+    return status(gs::launch_raster_bwd(tile, vt, splats, isect_gid, reinterpret_cast<const int2*>(tile_ranges),
+                                        n, background, static_cast<const int*>(schedule), queue, T_final,
+                                        n_contrib, d_images, d_alpha, grad2d, as_stream(stream)));
+}
+
+int gs_project_bwd(const float* means, const float* log_scales, const float* quats,
+                   const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
+                   const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
+                   float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
+                   float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh,
+                   void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || sh_degree < 0 || sh_degree > 3 || !make_views(sizes, n_views, 16, vt))
+        return GS_ERR_ARG;
+    if (!(eps2d >= 0.0f)) return GS_ERR_ARG;
+    if (n == 0) return GS_OK;
+    if (!means || !log_scales || !quats || !opacity_logits || !sh || !viewmats || !intrinsics || !flags ||
+        !grad2d || !d_means || !d_log_scales || !d_quats || !d_opacity_logits || !d_sh)
+        return GS_ERR_ARG;
+    return status(gs::launch_project_bwd(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
+                                         intrinsics, vt, eps2d, flags, grad2d, d_means, d_log_scales, d_quats,
+                                         d_opacity_logits, d_sh, as_stream(stream)));
+}
+
+int gs_raster_visits(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges, int64_t n,
+                     int n_views, const int32_t* sizes, int tile, float* images, float* T_final,
+                     int32_t* n_contrib, int32_t* visits, void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
+        return GS_ERR_ARG;
+    if (!tile_ranges || !images || !T_final || !n_contrib || !visits || !isect_gid) return GS_ERR_ARG;
+    if (n > 0 && (!splats || !aligned16(splats))) return GS_ERR_ARG;
+    const float bg[3] = {0.0f, 0.0f, 0.0f};
+    return status(gs::launch_raster_fwd(tile, vt, splats, isect_gid, reinterpret_cast<const int2*>(tile_ranges),
+                                        n, bg, nullptr, nullptr, images, T_final, n_contrib, visits,
+                                        as_stream(stream)));
+}
+
+size_t gs_loss_workspace_size(int64_t n_elems)
+{
+    if (n_elems < 0) return 0;
+    return gs::loss_workspace_size(n_elems);
+}
+
+int gs_loss_l2(const float* images, const float* targets, int64_t n_elems, float* loss, float* d_images,
+               void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (n_elems < 0 || !loss || !workspace) return GS_ERR_ARG;
+    if (n_elems > 0 && (!images || !targets || !d_images)) return GS_ERR_ARG;
+    if (workspace_bytes < gs::loss_workspace_size(n_elems)) return GS_ERR_WORKSPACE;
+    return status(gs::launch_loss_l2(images, targets, n_elems, loss, d_images, workspace, as_stream(stream)));
+}
+
+}  // extern "C"

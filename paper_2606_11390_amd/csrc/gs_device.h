@@ -1,0 +1,110 @@
+// Device-side helpers shared by the gfx950 kernels of the splatting path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gs.h"
+
+#define GS_WAVE 64
+
+namespace gs {
+
+// Per-launch description of the views, passed by value as a kernel argument.
+struct ViewTable {
+    int n_views;
+    int total_tiles;
+    int W[GS_MAX_VIEWS];
+    int H[GS_MAX_VIEWS];
+    int tiles_x[GS_MAX_VIEWS];
+    int tile_off[GS_MAX_VIEWS + 1];   // prefix of TX*TY
+    long long pix_off[GS_MAX_VIEWS + 1];  // prefix of W*H
+};
+
+// Constants of the method (3D Gaussian Splatting compositing), float32.
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kClip = 1.3f;
+// log2(e) / 2: M M^T = kC0 * conic
+constexpr float kC0 = 0.72134752044448170368f;
+constexpr float kLn2 = 0.69314718055994530942f;
+
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int t)
+{
+    int v = 0;
+    // views are few (<= 64); binary search over the tile prefix
+    int lo = 0, hi = vt.n_views - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (vt.tile_off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    v = lo;
+    return v;
+}
+
+// Tile rectangle of a splat, float32 arithmetic without contraction so that
+// the projection (tiles_touched) and the binning (emission) agree bit for bit.
+__device__ __forceinline__ void tile_rect(float u, float v, int rx, int ry, int tile, int W, int H,
+                                          int& x0, int& y0, int& x1, int& y1)
+{
+#pragma clang fp contract(off)
+    const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
+    const float ts = (float)tile;
+    float fx0 = floorf((u - (float)rx) / ts);
+    float fx1 = floorf((u + (float)rx) / ts) + 1.0f;
+    float fy0 = floorf((v - (float)ry) / ts);
+    float fy1 = floorf((v + (float)ry) / ts) + 1.0f;
+    fx0 = fminf(fmaxf(fx0, 0.0f), (float)TX);
+    fx1 = fminf(fmaxf(fx1, 0.0f), (float)TX);
+    fy0 = fminf(fmaxf(fy0, 0.0f), (float)TY);
+    fy1 = fminf(fmaxf(fy1, 0.0f), (float)TY);
+    x0 = (int)fx0; x1 = (int)fx1; y0 = (int)fy0; y1 = (int)fy1;
+}
+
+// Splat falloff in the record's factor form.  Both rasterisers call this same
+// function so that their skip decisions agree: w = M^T d, q' = |w|^2,
+// alpha_raw = 2^(log2 sigma - q').  Explicit fma calls fix the rounding.
+struct Falloff {
+    float w0, w1, araw;
+};
+
+__device__ __forceinline__ Falloff falloff(float dx, float dy, float m00, float m10, float m11,
+                                           float ls)
+{
+#pragma clang fp contract(off)
+    Falloff f;
+    f.w1 = m11 * dy;
+    f.w0 = __builtin_fmaf(m00, dx, m10 * dy);
+    float e = __builtin_fmaf(-f.w1, f.w1, ls);
+    e = __builtin_fmaf(-f.w0, f.w0, e);
+    f.araw = __builtin_amdgcn_exp2f(e);
+    return f;
+}
+
+// Sum of x over the 64 lanes of the wave, returned uniformly (gfx9 DPP).
+__device__ __forceinline__ float wave_sum(float x)
+{
+    // xor 1, xor 2 within quads
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+    // row half mirror (8 lanes), row mirror (16 lanes)
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
+    // row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xA, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xC, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ int wave_max_i(int x)
+{
+    for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o));
+    return x;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace gs

@@ -1,0 +1,486 @@
+// Projection + spherical-harmonic colour, forward and backward (gfx950).
+//
+// Paper Section 4: the SH and projection operators are partitioned per
+// Gaussian and emit colours and projected quantities for every camera of the
+// batch; their backward is partitioned the same way.  The formulas are those
+// of 3D Gaussian Splatting (EWA splatting of a 3-D Gaussian through the local
+// affine approximation of the pinhole projection).
+//
+// GPU organisation: one thread owns one Gaussian and loops over the views, so
+// each parameter is read from HBM once per step whatever the number of views,
+// and the backward sums a Gaussian's views in registers without atomics.
+// Parameters are planar [C][N] (coalesced 256-byte wave reads per component);
+// the splat record is written with three 16-byte stores per (view, Gaussian).
+//
+// Numerics: the 2-D covariance is formed as Sigma2 = F F^T + eps I with the
+// 2x3 factor F = J W R S, so det Sigma2 = |F0 x F1|^2 + eps (|F0|^2 + |F1|^2)
+// + eps^2 (Lagrange identity) carries no cancellation, and the record stores
+// the Cholesky factor of the conic computed from it:
+//   m00 = sqrt(c0 c / D), m10 = -b sqrt(c0 / (c D)), m11 = sqrt(c0 / c)
+// for Sigma2 = [[a, b], [b, c]], D = det Sigma2, c0 = log2(e)/2.
+#include "gs_device.h"
+
+namespace gs {
+namespace {
+
+// Real spherical harmonics, orthonormal with the Condon-Shortley phase,
+// index l*l + l + m, evaluated at a unit direction.
+constexpr float SH_C0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+constexpr float SH_C1 = 0.48860251190291992f;   // sqrt(3 / (4 pi))
+constexpr float SH_C2A = 1.0925484305920792f;   // sqrt(15 / pi) / 2
+constexpr float SH_C2B = 0.31539156525252005f;  // sqrt(5 / pi) / 4
+constexpr float SH_C2C = 0.54627421529603959f;  // sqrt(15 / pi) / 4
+constexpr float SH_C3A = 0.59004358992664352f;  // sqrt(35 / (2 pi)) / 4
+constexpr float SH_C3B = 2.8906114426405538f;   // sqrt(105 / pi) / 2
+constexpr float SH_C3C = 0.45704579946446572f;  // sqrt(21 / (2 pi)) / 4
+constexpr float SH_C3D = 0.37317633259011540f;  // sqrt(7 / pi) / 4
+constexpr float SH_C3E = 1.4453057213202769f;   // sqrt(105 / pi) / 4
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y)
+{
+    Y[0] = SH_C0;
+    if (DEG >= 1) {
+        Y[1] = -SH_C1 * y;
+        Y[2] = SH_C1 * z;
+        Y[3] = -SH_C1 * x;
+    }
+    if (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = SH_C2A * x * y;
+        Y[5] = -SH_C2A * y * z;
+        Y[6] = SH_C2B * (2.0f * zz - xx - yy);
+        Y[7] = -SH_C2A * x * z;
+        Y[8] = SH_C2C * (xx - yy);
+        if (DEG >= 3) {
+            Y[9] = -SH_C3A * y * (3.0f * xx - yy);
+            Y[10] = SH_C3B * x * y * z;
+            Y[11] = -SH_C3C * y * (4.0f * zz - xx - yy);
+            Y[12] = SH_C3D * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -SH_C3C * x * (4.0f * zz - xx - yy);
+            Y[14] = SH_C3E * z * (xx - yy);
+            Y[15] = -SH_C3A * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+// sum_j s_j grad Y_j (partials of the polynomial forms above)
+template <int DEG>
+__device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const float* s, float& gx,
+                                            float& gy, float& gz)
+{
+    gx = gy = gz = 0.0f;
+    if (DEG >= 1) {
+        gy -= SH_C1 * s[1];
+        gz += SH_C1 * s[2];
+        gx -= SH_C1 * s[3];
+    }
+    if (DEG >= 2) {
+        gx += SH_C2A * y * s[4];
+        gy += SH_C2A * x * s[4];
+        gy -= SH_C2A * z * s[5];
+        gz -= SH_C2A * y * s[5];
+        gx -= 2.0f * SH_C2B * x * s[6];
+        gy -= 2.0f * SH_C2B * y * s[6];
+        gz += 4.0f * SH_C2B * z * s[6];
+        gx -= SH_C2A * z * s[7];
+        gz -= SH_C2A * x * s[7];
+        gx += 2.0f * SH_C2C * x * s[8];
+        gy -= 2.0f * SH_C2C * y * s[8];
+        if (DEG >= 3) {
+            const float xx = x * x, yy = y * y, zz = z * z;
+            gx -= 6.0f * SH_C3A * x * y * s[9];
+            gy -= 3.0f * SH_C3A * (xx - yy) * s[9];
+            gx += SH_C3B * y * z * s[10];
+            gy += SH_C3B * x * z * s[10];
+            gz += SH_C3B * x * y * s[10];
+            gx += 2.0f * SH_C3C * x * y * s[11];
+            gy -= SH_C3C * (4.0f * zz - xx - 3.0f * yy) * s[11];
+            gz -= 8.0f * SH_C3C * y * z * s[11];
+            gx -= 6.0f * SH_C3D * x * z * s[12];
+            gy -= 6.0f * SH_C3D * y * z * s[12];
+            gz += SH_C3D * (6.0f * zz - 3.0f * xx - 3.0f * yy) * s[12];
+            gx -= SH_C3C * (4.0f * zz - 3.0f * xx - yy) * s[13];
+            gy += 2.0f * SH_C3C * x * y * s[13];
+            gz -= 8.0f * SH_C3C * x * z * s[13];
+            gx += 2.0f * SH_C3E * x * z * s[14];
+            gy -= 2.0f * SH_C3E * y * z * s[14];
+            gz += SH_C3E * (xx - yy) * s[14];
+            gx -= 3.0f * SH_C3A * (xx - yy) * s[15];
+            gy += 6.0f * SH_C3A * x * y * s[15];
+        }
+    }
+}
+
+// rotation matrix (row-major) of a unit quaternion (w, x, y, z)
+__device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float* R)
+{
+    R[0] = 1.0f - 2.0f * (y * y + z * z);
+    R[1] = 2.0f * (x * y - w * z);
+    R[2] = 2.0f * (x * z + w * y);
+    R[3] = 2.0f * (x * y + w * z);
+    R[4] = 1.0f - 2.0f * (x * x + z * z);
+    R[5] = 2.0f * (y * z - w * x);
+    R[6] = 2.0f * (x * z - w * y);
+    R[7] = 2.0f * (y * z + w * x);
+    R[8] = 1.0f - 2.0f * (x * x + y * y);
+}
+
+struct Camera {
+    float r[9];   // world-to-camera rotation, row-major
+    float t[3];
+    float fx, fy, cx, cy;
+    float limx, limy;   // clamp of x/z, y/z in the Jacobian
+    int W, H;
+};
+
+__device__ __forceinline__ Camera load_camera(const float* __restrict__ viewmats,
+                                              const float* __restrict__ intr, const ViewTable& vt,
+                                              int v)
+{
+    Camera c;
+    const float* m = viewmats + v * 12;
+    c.r[0] = m[0]; c.r[1] = m[1]; c.r[2] = m[2]; c.t[0] = m[3];
+    c.r[3] = m[4]; c.r[4] = m[5]; c.r[5] = m[6]; c.t[1] = m[7];
+    c.r[6] = m[8]; c.r[7] = m[9]; c.r[8] = m[10]; c.t[2] = m[11];
+    c.fx = intr[v * 4 + 0]; c.fy = intr[v * 4 + 1];
+    c.cx = intr[v * 4 + 2]; c.cy = intr[v * 4 + 3];
+    c.W = vt.W[v]; c.H = vt.H[v];
+    c.limx = kClip * (0.5f * (float)c.W / c.fx);
+    c.limy = kClip * (0.5f * (float)c.H / c.fy);
+    return c;
+}
+
+// Geometry of one Gaussian in one view, shared by the forward and backward.
+struct Geo {
+    float px, py, pz;        // camera-space mean
+    float xr, yr;            // clamped x/z, y/z
+    bool clx, cly;
+    float T0[3], T1[3];      // T = J R_v (2x3)
+    float F0[3], F1[3];      // F = T M (2x3), M = R_q S
+    float a, b, c, D;        // Sigma2 = [[a, b], [b, c]], D = det
+};
+
+__device__ __forceinline__ void geometry(const Camera& cam, const float* mu, const float* M, float eps2d,
+                                         Geo& g)
+{
+    g.px = cam.r[0] * mu[0] + cam.r[1] * mu[1] + cam.r[2] * mu[2] + cam.t[0];
+    g.py = cam.r[3] * mu[0] + cam.r[4] * mu[1] + cam.r[5] * mu[2] + cam.t[1];
+    g.pz = cam.r[6] * mu[0] + cam.r[7] * mu[1] + cam.r[8] * mu[2] + cam.t[2];
+    const float iz = 1.0f / g.pz;
+    const float xr0 = g.px * iz, yr0 = g.py * iz;
+    g.clx = (xr0 < -cam.limx) || (xr0 > cam.limx);
+    g.cly = (yr0 < -cam.limy) || (yr0 > cam.limy);
+    g.xr = fminf(fmaxf(xr0, -cam.limx), cam.limx);
+    g.yr = fminf(fmaxf(yr0, -cam.limy), cam.limy);
+    // J = [[fx/z, 0, -fx xr/z], [0, fy/z, -fy yr/z]];  T = J R_v
+    const float jx = cam.fx * iz, jy = cam.fy * iz;
+    for (int k = 0; k < 3; k++) {
+        g.T0[k] = jx * (cam.r[k] - g.xr * cam.r[6 + k]);
+        g.T1[k] = jy * (cam.r[3 + k] - g.yr * cam.r[6 + k]);
+    }
+    for (int j = 0; j < 3; j++) {
+        g.F0[j] = g.T0[0] * M[j] + g.T0[1] * M[3 + j] + g.T0[2] * M[6 + j];
+        g.F1[j] = g.T1[0] * M[j] + g.T1[1] * M[3 + j] + g.T1[2] * M[6 + j];
+    }
+    const float aa = g.F0[0] * g.F0[0] + g.F0[1] * g.F0[1] + g.F0[2] * g.F0[2];
+    const float cc = g.F1[0] * g.F1[0] + g.F1[1] * g.F1[1] + g.F1[2] * g.F1[2];
+    g.b = g.F0[0] * g.F1[0] + g.F0[1] * g.F1[1] + g.F0[2] * g.F1[2];
+    const float x0 = g.F0[1] * g.F1[2] - g.F0[2] * g.F1[1];
+    const float x1 = g.F0[2] * g.F1[0] - g.F0[0] * g.F1[2];
+    const float x2 = g.F0[0] * g.F1[1] - g.F0[1] * g.F1[0];
+    g.a = aa + eps2d;
+    g.c = cc + eps2d;
+    g.D = (x0 * x0 + x1 * x1 + x2 * x2) + eps2d * (aa + cc) + eps2d * eps2d;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
+    long long N, const float* __restrict__ viewmats, const float* __restrict__ intr, ViewTable vt,
+    float near_plane, float far_plane, float eps2d, int tile, float* __restrict__ splats,
+    float* __restrict__ depths, int2* __restrict__ radii, int* __restrict__ tiles,
+    uint8_t* __restrict__ flags)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const float mu[3] = {means[g], means[N + g], means[2 * N + g]};
+    const float ls[3] = {log_scales[g], log_scales[N + g], log_scales[2 * N + g]};
+    const float q[4] = {quats[g], quats[N + g], quats[2 * N + g], quats[3 * N + g]};
+    const float o = opac[g];
+    bool finite = isfinite(mu[0]) && isfinite(mu[1]) && isfinite(mu[2]) && isfinite(ls[0]) &&
+                  isfinite(ls[1]) && isfinite(ls[2]) && isfinite(q[0]) && isfinite(q[1]) &&
+                  isfinite(q[2]) && isfinite(q[3]) && isfinite(o);
+    const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    finite = finite && qn2 > 0.0f;
+    const float sigma = 1.0f / (1.0f + expf(-o));
+    const float lsig = log2f(sigma);
+    const float iq = 1.0f / sqrtf(qn2);
+    float R[9], M[9];
+    quat_to_rot(q[0] * iq, q[1] * iq, q[2] * iq, q[3] * iq, R);
+    const float s[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
+
+    float coef[3 * K];
+    bool have_sh = false;
+    for (int v = 0; v < vt.n_views; v++) {
+        const Camera cam = load_camera(viewmats, intr, vt, v);
+        const long long o_vg = (long long)v * N + g;
+        Geo ge;
+        geometry(cam, mu, M, eps2d, ge);
+        bool vis = finite && ge.pz > near_plane && ge.pz < far_plane && sigma >= kAlphaMin &&
+                   ge.D > 0.0f;
+        int rx = 0, ry = 0, tt = 0;
+        float u = 0.0f, vv = 0.0f;
+        if (vis) {
+            u = cam.fx * ge.px / ge.pz + cam.cx;
+            vv = cam.fy * ge.py / ge.pz + cam.cy;
+            rx = (int)fminf(ceilf(3.0f * sqrtf(ge.a)), 1073741824.0f);
+            ry = (int)fminf(ceilf(3.0f * sqrtf(ge.c)), 1073741824.0f);
+            int x0, y0, x1, y1;
+            tile_rect(u, vv, rx, ry, tile, cam.W, cam.H, x0, y0, x1, y1);
+            tt = (x1 - x0) * (y1 - y0);
+            vis = tt > 0;
+        }
+        uint8_t fl = 0;
+        if (vis) {
+            // record: Cholesky factor of c0 * conic
+            const float sc = sqrtf(ge.c), sD = sqrtf(ge.D);
+            const float rc0 = 0.84932180028801904272f;   // sqrt(c0)
+            const float m00 = rc0 * sc / sD;
+            const float m11 = rc0 / sc;
+            const float m10 = -ge.b * (rc0 / (sc * sD));
+            // colour along the unit ray from the camera centre c = -R^T t
+            const float camc[3] = {
+                -(cam.r[0] * cam.t[0] + cam.r[3] * cam.t[1] + cam.r[6] * cam.t[2]),
+                -(cam.r[1] * cam.t[0] + cam.r[4] * cam.t[1] + cam.r[7] * cam.t[2]),
+                -(cam.r[2] * cam.t[0] + cam.r[5] * cam.t[1] + cam.r[8] * cam.t[2])};
+            float d0 = mu[0] - camc[0], d1 = mu[1] - camc[1], d2 = mu[2] - camc[2];
+            const float idn = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+            d0 *= idn; d1 *= idn; d2 *= idn;
+            float Y[K];
+            sh_basis<DEG>(d0, d1, d2, Y);
+            if (!have_sh) {
+                for (int j = 0; j < K; j++)
+                    for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
+                have_sh = true;
+            }
+            float col[3];
+            for (int ch = 0; ch < 3; ch++) {
+                float acc = 0.0f;
+                for (int j = 0; j < K; j++) acc += coef[3 * j + ch] * Y[j];
+                acc += 0.5f;
+                if (acc < 0.0f) fl |= (uint8_t)(GS_FLAG_CLAMP_R << ch);
+                col[ch] = fmaxf(acc, 0.0f);
+            }
+            fl |= GS_FLAG_VISIBLE;
+            float4* rec = reinterpret_cast<float4*>(splats + o_vg * GS_SPLAT_FLOATS);
+            rec[0] = make_float4(u, vv, m00, m10);
+            rec[1] = make_float4(m11, lsig, col[0], col[1]);
+            rec[2] = make_float4(col[2], sigma, ge.pz, 0.0f);
+        }
+        depths[o_vg] = ge.pz;
+        radii[o_vg] = vis ? make_int2(rx, ry) : make_int2(0, 0);
+        tiles[o_vg] = vis ? tt : 0;
+        flags[o_vg] = fl;
+    }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
+    long long N, const float* __restrict__ viewmats, const float* __restrict__ intr, ViewTable vt,
+    float eps2d, const uint8_t* __restrict__ flags, const float* __restrict__ grad2d,
+    float* __restrict__ d_means, float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+    float* __restrict__ d_opac, float* __restrict__ d_sh)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+
+    float gmu[3] = {0.0f, 0.0f, 0.0f};
+    float gM[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float gsig = 0.0f;
+    float gsh[3 * K];
+    for (int j = 0; j < 3 * K; j++) gsh[j] = 0.0f;
+
+    bool any = false;
+    for (int v = 0; v < vt.n_views; v++) any |= (flags[(long long)v * N + g] & GS_FLAG_VISIBLE) != 0;
+
+    const float mu[3] = {means[g], means[N + g], means[2 * N + g]};
+    const float ls[3] = {log_scales[g], log_scales[N + g], log_scales[2 * N + g]};
+    const float q[4] = {quats[g], quats[N + g], quats[2 * N + g], quats[3 * N + g]};
+    const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    const float iq = any ? 1.0f / sqrtf(qn2) : 0.0f;
+    const float qh[4] = {q[0] * iq, q[1] * iq, q[2] * iq, q[3] * iq};
+    float R[9], M[9];
+    quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
+    const float s[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
+
+    float coef[3 * K];
+    if (any) {
+        for (int j = 0; j < K; j++)
+            for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
+    }
+
+    for (int v = 0; any && v < vt.n_views; v++) {
+        const long long o_vg = (long long)v * N + g;
+        const uint8_t fl = flags[o_vg];
+        if (!(fl & GS_FLAG_VISIBLE)) continue;
+        const float* gr = grad2d + o_vg * GS_GRAD_FLOATS;
+        const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4];
+        gsig += gr[5];
+        const Camera cam = load_camera(viewmats, intr, vt, v);
+        Geo ge;
+        geometry(cam, mu, M, eps2d, ge);
+
+        // conic Q = [[A, B], [B, C]] = Sigma2^-1;  dL/dSigma2 = -Q G Q
+        const float iD = 1.0f / ge.D;
+        const float A = ge.c * iD, B = -ge.b * iD, C = ge.a * iD;
+        const float hB = 0.5f * gB;
+        const float p00 = A * gA + B * hB, p01 = A * hB + B * gC;
+        const float p10 = B * gA + C * hB, p11 = B * hB + C * gC;
+        const float s00 = -(p00 * A + p01 * B);
+        const float s01 = -(p00 * B + p01 * C);
+        const float s11 = -(p10 * B + p11 * C);
+        // Sigma2 = F F^T + eps I:  dF = 2 dSigma2 F
+        float gF0[3], gF1[3];
+        for (int j = 0; j < 3; j++) {
+            gF0[j] = 2.0f * (s00 * ge.F0[j] + s01 * ge.F1[j]);
+            gF1[j] = 2.0f * (s01 * ge.F0[j] + s11 * ge.F1[j]);
+        }
+        // F = T M:  dT = dF M^T,  dM += T^T dF
+        float gT0[3], gT1[3];
+        for (int k = 0; k < 3; k++) {
+            gT0[k] = gF0[0] * M[3 * k] + gF0[1] * M[3 * k + 1] + gF0[2] * M[3 * k + 2];
+            gT1[k] = gF1[0] * M[3 * k] + gF1[1] * M[3 * k + 1] + gF1[2] * M[3 * k + 2];
+            for (int j = 0; j < 3; j++) gM[3 * k + j] += ge.T0[k] * gF0[j] + ge.T1[k] * gF1[j];
+        }
+        // T = J R_v:  dJ_ik = dT_i . (row k of R_v)
+        const float gJ00 = gT0[0] * cam.r[0] + gT0[1] * cam.r[1] + gT0[2] * cam.r[2];
+        const float gJ02 = gT0[0] * cam.r[6] + gT0[1] * cam.r[7] + gT0[2] * cam.r[8];
+        const float gJ11 = gT1[0] * cam.r[3] + gT1[1] * cam.r[4] + gT1[2] * cam.r[5];
+        const float gJ12 = gT1[0] * cam.r[6] + gT1[1] * cam.r[7] + gT1[2] * cam.r[8];
+        // J(p) and (u, v)(p)
+        const float z = ge.pz, iz = 1.0f / z, iz2 = iz * iz;
+        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+        gz -= cam.fx * iz2 * gJ00 + cam.fy * iz2 * gJ11;
+        if (!ge.clx) { gx -= cam.fx * iz2 * gJ02; gz += 2.0f * cam.fx * ge.px * iz2 * iz * gJ02; }
+        else gz += cam.fx * ge.xr * iz2 * gJ02;
+        if (!ge.cly) { gy -= cam.fy * iz2 * gJ12; gz += 2.0f * cam.fy * ge.py * iz2 * iz * gJ12; }
+        else gz += cam.fy * ge.yr * iz2 * gJ12;
+        gx += gu * cam.fx * iz;
+        gz -= gu * cam.fx * ge.px * iz2;
+        gy += gv * cam.fy * iz;
+        gz -= gv * cam.fy * ge.py * iz2;
+        // p = R_v mu + t
+        for (int i = 0; i < 3; i++) gmu[i] += cam.r[i] * gx + cam.r[3 + i] * gy + cam.r[6 + i] * gz;
+
+        // colour
+        const float camc[3] = {
+            -(cam.r[0] * cam.t[0] + cam.r[3] * cam.t[1] + cam.r[6] * cam.t[2]),
+            -(cam.r[1] * cam.t[0] + cam.r[4] * cam.t[1] + cam.r[7] * cam.t[2]),
+            -(cam.r[2] * cam.t[0] + cam.r[5] * cam.t[1] + cam.r[8] * cam.t[2])};
+        float d0 = mu[0] - camc[0], d1 = mu[1] - camc[1], d2 = mu[2] - camc[2];
+        const float idn = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+        d0 *= idn; d1 *= idn; d2 *= idn;
+        float Y[K], sdot[K];
+        sh_basis<DEG>(d0, d1, d2, Y);
+        const float gc[3] = {(fl & GS_FLAG_CLAMP_R) ? 0.0f : gr[6], (fl & GS_FLAG_CLAMP_G) ? 0.0f : gr[7],
+                             (fl & GS_FLAG_CLAMP_B) ? 0.0f : gr[8]};
+        for (int j = 0; j < K; j++) {
+            sdot[j] = coef[3 * j] * gc[0] + coef[3 * j + 1] * gc[1] + coef[3 * j + 2] * gc[2];
+            gsh[3 * j] += Y[j] * gc[0];
+            gsh[3 * j + 1] += Y[j] * gc[1];
+            gsh[3 * j + 2] += Y[j] * gc[2];
+        }
+        if (DEG > 0) {
+            float gdx, gdy, gdz;
+            sh_grad_dot<DEG>(d0, d1, d2, sdot, gdx, gdy, gdz);
+            const float dg = d0 * gdx + d1 * gdy + d2 * gdz;
+            gmu[0] += (gdx - d0 * dg) * idn;
+            gmu[1] += (gdy - d1 * dg) * idn;
+            gmu[2] += (gdz - d2 * dg) * idn;
+        }
+    }
+
+    // M = R diag(s), s = exp(l):  dl_j = s_j sum_i dM_ij R_ij;  dR_ij = dM_ij s_j
+    float gR[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) gR[3 * i + j] = gM[3 * i + j] * s[j];
+    float gl[3];
+    for (int j = 0; j < 3; j++) gl[j] = s[j] * (gM[j] * R[j] + gM[3 + j] * R[3 + j] + gM[6 + j] * R[6 + j]);
+    const float w = qh[0], x = qh[1], y = qh[2], zq = qh[3];
+    float gq[4];
+    gq[0] = 2.0f * (-zq * gR[1] + y * gR[2] + zq * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+    gq[1] = 2.0f * (y * gR[1] + zq * gR[2] + y * gR[3] - 2.0f * x * gR[4] - w * gR[5] + zq * gR[6] +
+                    w * gR[7] - 2.0f * x * gR[8]);
+    gq[2] = 2.0f * (-2.0f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + zq * gR[5] - w * gR[6] +
+                    zq * gR[7] - 2.0f * y * gR[8]);
+    gq[3] = 2.0f * (-2.0f * zq * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0f * zq * gR[4] +
+                    y * gR[5] + x * gR[6] + y * gR[7]);
+    const float qd = w * gq[0] + x * gq[1] + y * gq[2] + zq * gq[3];
+    const float sigma = 1.0f / (1.0f + expf(-opac[g]));
+
+    for (int i = 0; i < 3; i++) d_means[i * N + g] = any ? gmu[i] : 0.0f;
+    for (int i = 0; i < 3; i++) d_log_scales[i * N + g] = any ? gl[i] : 0.0f;
+    for (int k = 0; k < 4; k++) d_quats[k * N + g] = any ? (gq[k] - qh[k] * qd) * iq : 0.0f;
+    d_opac[g] = any ? gsig * sigma * (1.0f - sigma) : 0.0f;
+    for (int j = 0; j < K; j++)
+        for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = gsh[3 * j + ch];
+}
+
+}  // namespace
+
+#define GS_PROJ_LAUNCH(DEG)                                                                          \
+    hipLaunchKernelGGL(k_project<DEG>, dim3(blocks), dim3(256), 0, stream, means, log_scales, quats, \
+                       opac, sh, N, viewmats, intr, vt, near_plane, far_plane, eps2d, tile, splats,  \
+                       depths, radii, tiles, flags)
+
+hipError_t launch_project(int deg, const float* means, const float* log_scales, const float* quats,
+                          const float* opac, const float* sh, long long N, const float* viewmats,
+                          const float* intr, const ViewTable& vt, float near_plane, float far_plane,
+                          float eps2d, int tile, float* splats, float* depths, int2* radii,
+                          int* tiles, uint8_t* flags, hipStream_t stream)
+{
+    if (N == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((N + 255) / 256);
+    switch (deg) {
+    case 0: GS_PROJ_LAUNCH(0); break;
+    case 1: GS_PROJ_LAUNCH(1); break;
+    case 2: GS_PROJ_LAUNCH(2); break;
+    default: GS_PROJ_LAUNCH(3); break;
+    }
+    return hipGetLastError();
+}
+
+#define GS_PROJ_BWD_LAUNCH(DEG)                                                                    \
+    hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(blocks), dim3(256), 0, stream, means, log_scales,  \
+                       quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d, d_means,      \
+                       d_log_scales, d_quats, d_opac, d_sh)
+
+hipError_t launch_project_bwd(int deg, const float* means, const float* log_scales,
+                              const float* quats, const float* opac, const float* sh, long long N,
+                              const float* viewmats, const float* intr, const ViewTable& vt,
+                              float eps2d, const uint8_t* flags, const float* grad2d,
+                              float* d_means, float* d_log_scales, float* d_quats, float* d_opac,
+                              float* d_sh, hipStream_t stream)
+{
+    if (N == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((N + 255) / 256);
+    switch (deg) {
+    case 0: GS_PROJ_BWD_LAUNCH(0); break;
+    case 1: GS_PROJ_BWD_LAUNCH(1); break;
+    case 2: GS_PROJ_BWD_LAUNCH(2); break;
+    default: GS_PROJ_BWD_LAUNCH(3); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,220 @@
+"""Splatting step on one GPU: buffers, autograd wrapper and a capturable step.
+
+``Renderer`` owns every device buffer of the path for a fixed Gaussian count,
+SH degree and set of view sizes, and runs the C-ABI calls in order on torch's
+current stream:
+
+    gs_project -> gs_bin_sort -> [gs_tile_schedule] -> gs_rasterize_fwd
+    -> gs_loss_l2 -> gs_rasterize_bwd -> gs_project_bwd
+
+``render()`` exposes the differentiable part as a ``torch.autograd.Function``;
+``Renderer.step()`` runs forward + L2 loss + backward without autograd and
+without any host synchronisation, so it can be captured in a HIP graph
+(``Renderer.capture()``).  Intersection capacity is fixed per renderer; the
+overflow word of ``gs_bin_sort`` tells the caller to grow it
+(``Renderer.fit_capacity()``).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class Renderer:
+    def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
+                 background=(0.0, 0.0, 0.0), persistent=False, device="cuda"):
+        self.n = int(n)
+        self.deg = int(sh_degree)
+        self.sizes = np.asarray(sizes, np.int32).reshape(-1, 2)
+        self.V = int(self.sizes.shape[0])
+        if not 1 <= self.V <= B.GS_MAX_VIEWS:
+            raise ValueError("view count out of range")
+        self.tile = int(tile)
+        self.near, self.far, self.eps2d = float(near), float(far), float(eps2d)
+        self.background = np.asarray(background, np.float32)
+        self.persistent = bool(persistent)
+        self.device = torch.device(device)
+        self.tiles_x, self.tile_off, self.pix_off = B.tile_grid(self.sizes, self.tile)
+        self.total_tiles = int(self.tile_off[-1])
+        self.pixels = int(self.pix_off[-1])
+        V, N, dev = self.V, self.n, self.device
+        e = lambda *s, dt=torch.float32: torch.empty(*s, dtype=dt, device=dev)
+        self.splats = e(V * N * B.SPLAT_FLOATS)
+        self.depths = e(V * N)
+        self.radii = e(V * N * 2, dt=torch.int32)
+        self.tiles_touched = e(V * N, dt=torch.int32)
+        self.flags = e(V * N, dt=torch.uint8)
+        self.ranges = e(self.total_tiles * 2, dt=torch.int32)
+        self.info = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.images = e(3 * self.pixels)
+        self.T_final = e(self.pixels)
+        self.n_contrib = e(self.pixels, dt=torch.int32)
+        self.grad2d = torch.zeros(V * N * B.GRAD_FLOATS, dtype=torch.float32, device=dev)
+        self.d_images = e(3 * self.pixels)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.loss_ws = e(max(1, B.loss_workspace_size(3 * self.pixels)), dt=torch.uint8)
+        self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.schedule = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
+        self.capacity = 0
+        self.set_capacity(capacity)
+        self.graph = None
+
+    # ---------------------------------------------------------------- buffers
+    def set_capacity(self, capacity):
+        capacity = int(max(1, min(capacity, 0x7FFFFFFF)))
+        if capacity == self.capacity:
+            return
+        self.capacity = capacity
+        self.isect_tile = torch.empty(capacity, dtype=torch.int32, device=self.device)
+        self.isect_gid = torch.empty(capacity, dtype=torch.int32, device=self.device)
+        ws = B.bin_sort_workspace_size(self.n, self.V, capacity, self.total_tiles)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.graph = None
+
+    def memory_bytes(self):
+        return sum(t.numel() * t.element_size() for t in self.__dict__.values() if isinstance(t, torch.Tensor))
+
+    # ------------------------------------------------------------ the stages
+    def project(self, P, cams):
+        B.project(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
+                  cams["viewmats"], cams["intrinsics"], self.sizes, self.near, self.far, self.eps2d,
+                  self.tile, self.splats, self.depths, self.radii, self.tiles_touched, self.flags)
+
+    def bin_sort(self):
+        B.bin_sort(self.splats, self.depths, self.radii, self.tiles_touched, self.n, self.sizes, self.tile,
+                   self.capacity, self.workspace, self.isect_tile, self.isect_gid, self.ranges, self.info)
+        if self.persistent:
+            B.tile_schedule(self.ranges, self.total_tiles, self.schedule)
+
+    def _sched(self):
+        return (self.schedule, self.queue) if self.persistent else (None, None)
+
+    def raster_fwd(self):
+        s, q = self._sched()
+        B.rasterize_fwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
+                        self.background, s, q, self.images, self.T_final, self.n_contrib)
+
+    def raster_bwd(self, d_images, d_alpha=None):
+        s, q = self._sched()
+        B.rasterize_bwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
+                        self.background, s, q, self.T_final, self.n_contrib, d_images, d_alpha, self.grad2d)
+
+    def project_bwd(self, P, cams, grads):
+        B.project_bwd(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
+                      cams["viewmats"], cams["intrinsics"], self.sizes, self.eps2d, self.flags, self.grad2d,
+                      grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"],
+                      grads["sh"])
+
+    def loss_l2(self, targets):
+        B.loss_l2(self.images, targets, self.loss, self.d_images, self.loss_ws)
+
+    def forward(self, P, cams):
+        self.project(P, cams)
+        self.bin_sort()
+        self.raster_fwd()
+        return self.images
+
+    def backward(self, P, cams, d_images, grads, d_alpha=None):
+        self.raster_bwd(d_images, d_alpha)
+        self.project_bwd(P, cams, grads)
+        return grads
+
+    # ---------------------------------------------------------- whole step
+    def step(self, P, cams, targets, grads):
+        """Forward, L2 loss against packed ``targets`` and backward into
+        ``grads`` (dict of tensors shaped like the parameters)."""
+        self.forward(P, cams)
+        self.loss_l2(targets)
+        return self.backward(P, cams, self.d_images, grads)
+
+    def fit_capacity(self, P, cams, headroom=1.25):
+        """Run projection + binning eagerly and grow the intersection capacity
+        until nothing overflows.  Returns the intersection count."""
+        while True:
+            self.project(P, cams)
+            self.bin_sort()
+            info = self.info.cpu().numpy()
+            m = int(info[B.INFO_ISECT])
+            if not info[B.INFO_OVERFLOW]:
+                if m > self.capacity:
+                    raise B.GSError("intersection count above capacity without overflow flag")
+                return m
+            self.set_capacity(int(m * headroom) + 1024)
+
+    def capture(self, P, cams, targets, grads, warmup=2):
+        """Capture ``step`` in a HIP graph (after eager warm-up) and return it;
+        ``replay()`` then runs the whole step with one launch."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self.step(P, cams, targets, grads)
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(P, cams, targets, grads)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+
+def params_to_device(scene, device="cuda"):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    P = dict(means=t(scene.means), log_scales=t(scene.log_scales), quats=t(scene.quats),
+             opacity_logits=t(scene.opacity_logits), sh=t(scene.sh))
+    cams = dict(viewmats=t(scene.viewmats), intrinsics=t(scene.intrinsics))
+    return P, cams
+
+
+def packed_targets(scene, device="cuda"):
+    return torch.from_numpy(np.concatenate([t.reshape(-1) for t in scene.targets])).to(device)
+
+
+def zeros_like_params(P):
+    return {k: torch.zeros_like(v) for k, v in P.items()}
+
+
+def unpack_images(flat, sizes, channels=3):
+    """Split a packed image buffer into per-view [C][H][W] views."""
+    out, o = [], 0
+    for w, h in np.asarray(sizes).reshape(-1, 2):
+        n = channels * int(w) * int(h)
+        out.append(flat[o:o + n].view(channels, int(h), int(w)) if channels > 1 else
+                   flat[o:o + n].view(int(h), int(w)))
+        o += n
+    return out
+
+
+class _Render(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer, viewmats, intrinsics, means, log_scales, quats, opacity_logits, sh):
+        P = dict(means=means.detach().contiguous(), log_scales=log_scales.detach().contiguous(),
+                 quats=quats.detach().contiguous(), opacity_logits=opacity_logits.detach().contiguous(),
+                 sh=sh.detach().contiguous())
+        cams = dict(viewmats=viewmats.contiguous(), intrinsics=intrinsics.contiguous())
+        renderer.forward(P, cams)
+        info = renderer.info.cpu().numpy()
+        if info[B.INFO_OVERFLOW]:
+            raise B.GSError(f"intersection capacity {renderer.capacity} < {int(info[B.INFO_ISECT])}; "
+                            "call Renderer.fit_capacity()")
+        ctx.renderer = renderer
+        ctx.P, ctx.cams = P, cams
+        return renderer.images.clone()
+
+    @staticmethod
+    def backward(ctx, d_images):
+        r = ctx.renderer
+        grads = zeros_like_params(ctx.P)
+        r.backward(ctx.P, ctx.cams, d_images.contiguous(), grads)
+        return (None, None, None, grads["means"], grads["log_scales"], grads["quats"],
+                grads["opacity_logits"], grads["sh"])
+
+
+def render(renderer, P, cams):
+    """Differentiable rendering of all views: packed images [sum 3 H W]."""
+    return _Render.apply(renderer, cams["viewmats"], cams["intrinsics"], P["means"], P["log_scales"],
+                         P["quats"], P["opacity_logits"], P["sh"])

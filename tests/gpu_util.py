@@ -1,0 +1,164 @@
+"""Helpers for the GPU parity tests: run one C-ABI stage on numpy inputs.
+
+Inputs of a stage come from the seeded scene generators or from the oracle
+(rounded to the ABI's float32 layout); nothing computed by the GPU is ever fed
+to the oracle.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2606_11390_amd import binding as B
+
+F32 = np.float32
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=None):
+    a = np.ascontiguousarray(a if dtype is None else np.asarray(a, dtype))
+    return torch.from_numpy(a).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------- oracle side
+def oracle_views(scene, tile, near=0.01, far=1e10, eps2d=0.3, P=None):
+    """Oracle projection of every view, plus the ABI arrays built from it."""
+    P = P or oracle.Params.of(scene)
+    V, N = scene.n_views, scene.n
+    projs = []
+    rec = np.zeros((V, N, 12), F32)
+    depth = np.zeros((V, N), F32)
+    radii = np.zeros((V, N, 2), np.int32)
+    tiles = np.zeros((V, N), np.int32)
+    flags = np.zeros((V, N), np.uint8)
+    for v in range(V):
+        W, H = (int(x) for x in scene.sizes[v])
+        pr = oracle.project(P, scene.viewmats[v], scene.intrinsics[v], W, H, near, far, eps2d, tile)
+        projs.append(pr)
+        rec[v] = oracle.to_record(pr)
+        depth[v] = pr["depth"].astype(F32)
+        radii[v] = pr["radii"].T
+        tiles[v] = pr["tiles"]
+        flags[v] = pr["visible"] | (pr["clamp"] << 1)
+    return P, projs, dict(splats=rec, depths=depth, radii=radii, tiles=tiles, flags=flags)
+
+
+def oracle_binning(arrs, sizes, tile):
+    views = [(arrs["splats"][v, :, 0], arrs["splats"][v, :, 1], arrs["depths"][v], arrs["radii"][v].T.copy())
+             for v in range(len(sizes))]
+    return oracle.bin_views(views, sizes, tile)
+
+
+# ------------------------------------------------------------------- GPU side
+def gpu_project(scene, tile, near=0.01, far=1e10, eps2d=0.3):
+    V, N = scene.n_views, scene.n
+    out = dict(splats=torch.zeros(V * N * 12, device="cuda"), depths=torch.zeros(V * N, device="cuda"),
+               radii=torch.zeros(V * N * 2, dtype=torch.int32, device="cuda"),
+               tiles=torch.zeros(V * N, dtype=torch.int32, device="cuda"),
+               flags=torch.zeros(V * N, dtype=torch.uint8, device="cuda"))
+    B.project(dev(scene.means), dev(scene.log_scales), dev(scene.quats), dev(scene.opacity_logits),
+              dev(scene.sh), scene.sh_degree, dev(scene.viewmats), dev(scene.intrinsics), scene.sizes, near,
+              far, eps2d, tile, out["splats"], out["depths"], out["radii"], out["tiles"], out["flags"])
+    h = {k: host(v) for k, v in out.items()}
+    return dict(splats=h["splats"].reshape(V, N, 12), depths=h["depths"].reshape(V, N),
+                radii=h["radii"].reshape(V, N, 2), tiles=h["tiles"].reshape(V, N),
+                flags=h["flags"].reshape(V, N))
+
+
+def gpu_bin_sort(arrs, sizes, tile, capacity):
+    V, N = arrs["depths"].shape
+    _, toff, _ = B.tile_grid(sizes, tile)
+    T = int(toff[-1])
+    ws = torch.empty(B.bin_sort_workspace_size(N, V, capacity, T), dtype=torch.uint8, device="cuda")
+    it = torch.full((capacity,), -7, dtype=torch.int32, device="cuda")
+    ig = torch.full((capacity,), -7, dtype=torch.int32, device="cuda")
+    rg = torch.full((2 * T,), -7, dtype=torch.int32, device="cuda")
+    info = torch.full((4,), -7, dtype=torch.int32, device="cuda")
+    B.bin_sort(dev(arrs["splats"].reshape(-1)), dev(arrs["depths"].reshape(-1)),
+               dev(arrs["radii"].reshape(-1)), dev(arrs["tiles"].reshape(-1)), N, sizes, tile, capacity, ws,
+               it, ig, rg, info)
+    return host(it), host(ig), host(rg).reshape(T, 2), host(info)
+
+
+def gpu_raster_fwd(splats, gids, ranges, sizes, tile, bg=(0, 0, 0), persistent=False):
+    V, N = splats.shape[:2]
+    _, toff, poff = B.tile_grid(sizes, tile)
+    P = int(poff[-1])
+    img = torch.full((3 * P,), float("nan"), device="cuda")
+    T = torch.full((P,), float("nan"), device="cuda")
+    last = torch.full((P,), -7, dtype=torch.int32, device="cuda")
+    sched, q = None, None
+    rg = dev(np.asarray(ranges, np.int32).reshape(-1))
+    if persistent:
+        sched = torch.empty(B.tile_schedule_size(int(toff[-1])), dtype=torch.uint8, device="cuda")
+        q = torch.zeros(1, dtype=torch.int32, device="cuda")
+        B.tile_schedule(rg, int(toff[-1]), sched)
+    B.rasterize_fwd(dev(splats.reshape(-1)), dev(np.asarray(gids, np.int32)), rg, N, sizes, tile, bg, sched, q,
+                    img, T, last)
+    return host(img), host(T), host(last)
+
+
+def gpu_raster_bwd(splats, gids, ranges, sizes, tile, T_final, last, d_img, d_alpha=None, bg=(0, 0, 0),
+                   persistent=False):
+    V, N = splats.shape[:2]
+    _, toff, poff = B.tile_grid(sizes, tile)
+    g = torch.zeros(V * N * 9, device="cuda")
+    sched, q = None, None
+    rg = dev(np.asarray(ranges, np.int32).reshape(-1))
+    if persistent:
+        sched = torch.empty(B.tile_schedule_size(int(toff[-1])), dtype=torch.uint8, device="cuda")
+        q = torch.zeros(1, dtype=torch.int32, device="cuda")
+        B.tile_schedule(rg, int(toff[-1]), sched)
+    B.rasterize_bwd(dev(splats.reshape(-1)), dev(np.asarray(gids, np.int32)), rg, N, sizes, tile, bg, sched, q,
+                    dev(T_final, F32), dev(last, np.int32), dev(d_img, F32),
+                    None if d_alpha is None else dev(d_alpha, F32), g)
+    return host(g).reshape(V, N, 9)
+
+
+def gpu_project_bwd(scene, flags, grad2d, eps2d=0.3):
+    N, K = scene.n, (scene.sh_degree + 1) ** 2
+    d = dict(means=torch.zeros(3, N, device="cuda"), log_scales=torch.zeros(3, N, device="cuda"),
+             quats=torch.zeros(4, N, device="cuda"), opacity_logits=torch.zeros(N, device="cuda"),
+             sh=torch.zeros(K, 3, N, device="cuda"))
+    B.project_bwd(dev(scene.means), dev(scene.log_scales), dev(scene.quats), dev(scene.opacity_logits),
+                  dev(scene.sh), scene.sh_degree, dev(scene.viewmats), dev(scene.intrinsics), scene.sizes, eps2d,
+                  dev(flags.reshape(-1)), dev(grad2d.reshape(-1), F32), d["means"], d["log_scales"], d["quats"],
+                  d["opacity_logits"], d["sh"])
+    return {k: host(v) for k, v in d.items()}
+
+
+# --------------------------------------------------------------- comparisons
+def rel_max(x, y):
+    """max |x - y| / max |y|"""
+    y = np.asarray(y, np.float64)
+    s = np.max(np.abs(y)) if y.size else 0.0
+    return float(np.max(np.abs(np.asarray(x, np.float64) - y)) / s) if s > 0 else float(np.max(np.abs(x)) if np.size(x) else 0.0)
+
+
+def rel_l2(x, y):
+    """||x - y||_2 / ||y||_2"""
+    y = np.asarray(y, np.float64)
+    s = np.linalg.norm(y)
+    d = np.linalg.norm(np.asarray(x, np.float64) - y)
+    return float(d / s) if s > 0 else float(d)
+
+
+def unpack(flat, sizes, ch):
+    out, o = [], 0
+    for w, h in np.asarray(sizes).reshape(-1, 2):
+        n = ch * int(w) * int(h)
+        out.append(flat[o:o + n].reshape((ch, int(h), int(w)) if ch > 1 else (int(h), int(w))))
+        o += n
+    return out

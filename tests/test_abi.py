@@ -1,0 +1,88 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the
+header declares, and rejects bad arguments on the host before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_11390_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_path_calls():
+    names = _declared()
+    for n in ("gs_project", "gs_bin_sort", "gs_rasterize_fwd", "gs_rasterize_bwd", "gs_project_bwd"):
+        assert n in names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = B.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(B.exported_symbols())
+    assert L.gs_abi_version() == B.GS_ABI_VERSION
+    assert L.gs_strerror(0) == b"ok"
+    assert L.gs_strerror(-4) == b"workspace too small"
+
+
+def _sizes(*wh):
+    import numpy as np
+    a = np.asarray(wh, np.int32).reshape(-1)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def test_host_side_argument_checks():
+    L = B.lib()
+    p = ctypes.c_void_p(16)          # never dereferenced: every call below fails its checks
+    sz, szp = _sizes(64, 48)
+    # gs_project: negative N, bad degree, bad tile, bad view size, bad near/far
+    args = lambda **kw: [kw.get("means", p), p, p, p, p, kw.get("n", 10), kw.get("deg", 0), p, p,
+                         kw.get("sizes", szp), kw.get("V", 1), kw.get("near", 0.01), kw.get("far", 1e10),
+                         0.3, kw.get("tile", 16), p, p, p, p, p, None]
+    assert L.gs_project(*args(n=-1)) == -1
+    assert L.gs_project(*args(deg=4)) == -1
+    assert L.gs_project(*args(tile=12)) == -1
+    assert L.gs_project(*args(V=0)) == -1
+    assert L.gs_project(*args(V=65)) == -1
+    assert L.gs_project(*args(near=0.0)) == -1
+    assert L.gs_project(*args(far=0.001)) == -1
+    assert L.gs_project(*args(means=None)) == -1
+    bad, badp = _sizes(0, 48)
+    assert L.gs_project(*args(sizes=badp)) == -1
+    # gs_bin_sort: workspace too small, capacity out of range, misaligned workspace
+    ws = B.bin_sort_workspace_size(10, 1, 100, 12)
+    assert ws > 0
+    aligned = ctypes.c_void_p(256)
+    assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 100, aligned, ws - 1, p, p, p, p, None) == -4
+    assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 0, aligned, ws, p, p, p, p, None) == -1
+    assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 100, ctypes.c_void_p(260), ws, p, p, p, p, None) == -1
+    # rasterisers: bad tile, missing outputs, persistent mode without a queue
+    bg = (ctypes.c_float * 3)(0, 0, 0)
+    assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 24, bg, None, None, p, p, p, None) == -1
+    assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 16, bg, None, None, None, p, p, None) == -1
+    assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 16, bg, p, None, p, p, p, None) == -1
+    nan = (ctypes.c_float * 3)(float("nan"), 0, 0)
+    assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 16, nan, None, None, p, p, p, None) == -1
+    assert L.gs_rasterize_bwd(p, p, p, 10, 1, szp, 16, bg, None, None, p, p, None, None, p, 0, None) == -1
+    assert L.gs_project_bwd(p, p, p, p, p, 10, 5, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, None) == -1
+    assert L.gs_loss_l2(p, p, 10, p, p, p, 0, None) == -4
+    assert L.gs_tile_schedule(p, 0, p, 0, None) == -1
+    assert L.gs_tile_schedule_size(0) == 0
+
+
+def test_workspace_sizes_grow_with_problem():
+    a = B.bin_sort_workspace_size(1000, 1, 5000, 64)
+    b = B.bin_sort_workspace_size(1000, 2, 5000, 128)
+    c = B.bin_sort_workspace_size(1000, 1, 50000, 64)
+    assert 0 < a < b and a < c
+    assert B.loss_workspace_size(10) >= 8
+    assert B.tile_schedule_size(100) >= 400

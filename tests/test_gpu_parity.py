@@ -1,0 +1,270 @@
+"""GPU parity: every C-ABI stage against the FP64 oracle on the same inputs.
+
+Stage-isolated: the inputs of each stage are the seeded scene or the oracle's
+own previous stage rounded to the ABI's float32 layout, so both sides see
+identical float32 numbers.  Tolerances (from the target of the method's FP32
+implementation): images within 1e-5 relative (max |x - y| / max |y| per view),
+gradients within 1e-4 relative (||x - y|| / ||y|| per tensor), binning bit
+exact.  A decision whose FP64 distance to its threshold is below the FP32
+error (oracle margin) may legitimately go either way in FP32; such pixels /
+Gaussians are counted, must be rare, and are excluded from the element
+comparison (their upstream gradients are zeroed in the backward tests).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_11390_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+from tests import gpu_util as G  # noqa: E402
+
+PROJ_MARGIN = 2e-6      # relative distance to a projection decision boundary (~16 ulp)
+PIX_MARGIN = 1e-4       # relative distance to a compositing decision boundary
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def _multi():
+    return scenes.blobs(5, 30_000, 64, 20.0, [(320, 240, 250.0), (200, 150, 156.0), (128, 96, 100.0),
+                                              (257, 131, 200.0)], name="multi")
+
+
+SCENES = {
+    "tiny": lambda: scenes.tiny(),
+    "ragged": lambda: scenes.tiny(seed=21, n_gaussians=1500, width=100, height=75, focal=90.0),
+    "hd": lambda: scenes.hd(n_gaussians=200_000),
+    "multi": _multi,
+}
+
+
+@functools.lru_cache(maxsize=None)
+def scene(name):
+    return SCENES[name]()
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_stage(name, tile):
+    s = scene(name)
+    P, projs, arrs = G.oracle_views(s, tile)
+    keys, vals, ranges, offs = G.oracle_binning(arrs, s.sizes, tile)
+    return P, projs, arrs, keys, vals, ranges, offs
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_fwd(name, tile, bg):
+    s = scene(name)
+    P, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
+    out = []
+    for v in range(s.n_views):
+        W, H = (int(x) for x in s.sizes[v])
+        sp = oracle.from_record(arrs["splats"][v])
+        out.append((sp, oracle.raster_fwd(W, H, tile, ranges[offs[v]:offs[v + 1]], vals, sp, bg)))
+    return out
+
+
+CASES = [("tiny", 16), ("tiny", 8), ("ragged", 16), ("ragged", 32), ("hd", 16), ("multi", 16), ("multi", 8)]
+
+
+@pytest.mark.parametrize("name,tile", CASES)
+def test_project_parity(name, tile):
+    s = scene(name)
+    G.say(f"[project] {name} tile={tile} N={s.n} V={s.n_views}")
+    g = G.gpu_project(s, tile)
+    _, projs, arrs, *_ = oracle_stage(name, tile)
+    for v, pr in enumerate(projs):
+        W, H = (int(x) for x in s.sizes[v])
+        amb = pr["margin"] < PROJ_MARGIN
+        ok = ~amb
+        assert amb.sum() <= 2e-3 * s.n + 5, amb.sum()
+        vis = pr["visible"].astype(bool)
+        gvis = (g["flags"][v] & 1).astype(bool)
+        np.testing.assert_array_equal(gvis[ok], vis[ok])
+        np.testing.assert_array_equal(g["radii"][v][ok], pr["radii"].T[ok])
+        np.testing.assert_array_equal(g["tiles"][v][ok], pr["tiles"][ok])
+        m = ok & vis
+        np.testing.assert_array_equal(g["flags"][v][m] >> 1, pr["clamp"][m])
+        rec = g["splats"][v][m].astype(np.float64)
+        full = np.zeros((m.sum(), 12))
+        full[:, 0], full[:, 1] = pr["u"][m], pr["v"][m]
+        fac = oracle.factor(pr["conic"])[:, m].T
+        full[:, 2:5] = fac
+        with np.errstate(divide="ignore"):
+            full[:, 5] = np.log2(pr["sigma"][m])
+        full[:, 6:9] = pr["rgb"][:, m].T
+        full[:, 9], full[:, 10] = pr["sigma"][m], pr["depth"][m]
+        scale = max(W, H)
+        e_uv = np.max(np.abs(rec[:, :2] - full[:, :2])) / scale if m.any() else 0
+        e_z = np.max(np.abs(rec[:, 10] - full[:, 10]) / np.abs(full[:, 10])) if m.any() else 0
+        fn = np.max(np.abs(full[:, 2:5]), axis=1, keepdims=True)
+        e_fac = np.abs(rec[:, 2:5] - full[:, 2:5]) / fn
+        e_rgb = np.max(np.abs(rec[:, 6:9] - full[:, 6:9]) / np.maximum(1.0, np.abs(full[:, 6:9]))) if m.any() else 0
+        e_sig = np.max(np.abs(rec[:, 9] - full[:, 9]) / full[:, 9]) if m.any() else 0
+        e_ls = np.max(np.abs(rec[:, 5] - full[:, 5]) / np.maximum(1.0, np.abs(full[:, 5]))) if m.any() else 0
+        G.say(f"  view {v}: visible {vis.sum()} ambiguous {amb.sum()} err uv {e_uv:.2e} z {e_z:.2e} "
+              f"factor max {e_fac.max() if m.any() else 0:.2e} p99.9 {np.quantile(e_fac, 0.999) if m.any() else 0:.2e} "
+              f"rgb {e_rgb:.2e} sigma {e_sig:.2e} log2sigma {e_ls:.2e}")
+        assert e_uv <= IMG_TOL and e_z <= IMG_TOL and e_rgb <= IMG_TOL
+        assert e_sig <= IMG_TOL and e_ls <= IMG_TOL
+        assert (e_fac.max() if m.any() else 0) <= 1e-3
+
+
+@pytest.mark.parametrize("name,tile", CASES)
+def test_bin_sort_bit_exact(name, tile):
+    s = scene(name)
+    _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
+    M = len(keys)
+    G.say(f"[bin_sort] {name} tile={tile} M={M}")
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, tile, M + 100)
+    nvis = int(sum(p["visible"].sum() for p in projs))
+    assert tuple(info[:3]) == (nvis, M, 0)
+    np.testing.assert_array_equal(it[:M], (keys >> np.uint64(32)).astype(np.int32))
+    np.testing.assert_array_equal(ig[:M], vals)
+    np.testing.assert_array_equal(rg, ranges)
+
+
+def test_bin_sort_depth_ties_keep_gaussian_order():
+    s = scene("multi")
+    tile = 16
+    _, projs, arrs, *_ = oracle_stage("multi", tile)
+    arrs = dict(arrs)
+    arrs["depths"] = np.round(arrs["depths"], 0).astype(np.float32)   # many equal depths
+    keys, vals, ranges, offs = G.oracle_binning(arrs, s.sizes, tile)
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, tile, len(keys) + 7)
+    M = len(keys)
+    assert info[1] == M and info[2] == 0
+    np.testing.assert_array_equal(ig[:M], vals)
+    np.testing.assert_array_equal(rg, ranges)
+
+
+def test_bin_sort_overflow_and_empty():
+    s = scene("tiny")
+    _, projs, arrs, keys, vals, ranges, offs = oracle_stage("tiny", 16)
+    M = len(keys)
+    cap = M // 3
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, 16, cap)
+    assert info[1] == M and info[2] == 1
+    assert rg.min() >= 0 and rg.max() <= cap
+    assert np.all(np.diff(it[:cap]) >= 0)
+    empty = {k: np.zeros_like(v) for k, v in arrs.items()}
+    it, ig, rg, info = G.gpu_bin_sort(empty, s.sizes, 16, 64)
+    assert tuple(info[:3]) == (0, 0, 0)
+    assert not rg.any()
+
+
+FWD_CASES = [("tiny", 16, (0.0, 0.0, 0.0)), ("tiny", 8, (0.0, 0.0, 0.0)), ("ragged", 16, (0.2, 0.5, 0.9)),
+             ("ragged", 32, (0.0, 0.0, 0.0)), ("hd", 16, (0.0, 0.0, 0.0)), ("multi", 16, (0.1, 0.1, 0.1)),
+             ("multi", 8, (0.0, 0.0, 0.0))]
+
+
+@pytest.mark.parametrize("name,tile,bg", FWD_CASES)
+@pytest.mark.parametrize("persistent", [False, True])
+def test_raster_fwd_parity(name, tile, bg, persistent):
+    s = scene(name)
+    _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
+    G.say(f"[raster_fwd] {name} tile={tile} bg={bg} persistent={persistent}")
+    img, T, last = G.gpu_raster_fwd(arrs["splats"], vals, ranges, s.sizes, tile, bg, persistent)
+    imgs, Ts, lasts = G.unpack(img, s.sizes, 3), G.unpack(T, s.sizes, 1), G.unpack(last, s.sizes, 1)
+    for v, (sp, f) in enumerate(oracle_fwd(name, tile, bg)):
+        amb = f["margin"] < PIX_MARGIN
+        ok = ~amb
+        assert amb.sum() <= 1e-3 * amb.size + 5, amb.sum()
+        e_img = G.rel_max(imgs[v][:, ok], f["img"][:, ok])
+        e_T = G.rel_max(Ts[v][ok], f["T"][ok])
+        n_last = int((lasts[v][ok] != f["last"][ok]).sum())
+        G.say(f"  view {v}: ambiguous px {amb.sum()} / {amb.size}, img {e_img:.2e}, T {e_T:.2e}, "
+              f"last mismatches {n_last}, visits {f['visits'].sum()}")
+        assert e_img <= IMG_TOL and e_T <= IMG_TOL and n_last == 0
+        # ambiguous pixels are still valid renders: bounded by one decision flip
+        if amb.any():
+            assert np.max(np.abs(imgs[v][:, amb] - f["img"][:, amb])) < 0.05
+
+
+BWD_CASES = [("tiny", 16, False), ("tiny", 8, True), ("ragged", 16, True), ("ragged", 32, False),
+             ("hd", 16, False), ("multi", 16, True)]
+
+
+def _bwd_inputs(name, tile, with_alpha, seed=3):
+    s = scene(name)
+    bg = (0.1, 0.2, 0.3) if with_alpha else (0.0, 0.0, 0.0)
+    rng = np.random.default_rng(seed)
+    fw = []
+    for v, (sp, f) in enumerate(oracle_fwd(name, tile, bg)):
+        amb = f["margin"] < PIX_MARGIN
+        H, W = f["T"].shape
+        dimg = rng.standard_normal((3, H, W)).astype(np.float32)
+        dimg[:, amb] = 0
+        da = None
+        if with_alpha:
+            da = rng.standard_normal((H, W)).astype(np.float32)
+            da[amb] = 0
+        fw.append((sp, f, dimg, da))
+    return s, bg, fw
+
+
+@pytest.mark.parametrize("name,tile,with_alpha", BWD_CASES)
+@pytest.mark.parametrize("persistent", [False, True])
+def test_raster_bwd_parity(name, tile, with_alpha, persistent):
+    s, bg, fw = _bwd_inputs(name, tile, with_alpha)
+    _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
+    G.say(f"[raster_bwd] {name} tile={tile} d_alpha={with_alpha} persistent={persistent}")
+    T = np.concatenate([f["T"].reshape(-1) for _, f, _, _ in fw]).astype(np.float32)
+    last = np.concatenate([f["last"].reshape(-1) for _, f, _, _ in fw])
+    dimg = np.concatenate([d.reshape(-1) for _, _, d, _ in fw])
+    da = np.concatenate([a.reshape(-1) for _, _, _, a in fw]) if with_alpha else None
+    g = G.gpu_raster_bwd(arrs["splats"], vals, ranges, s.sizes, tile, T, last, dimg, da, bg, persistent)
+    for v, (sp, f, dv, av) in enumerate(fw):
+        W, H = (int(x) for x in s.sizes[v])
+        o = oracle.raster_bwd(W, H, tile, ranges[offs[v]:offs[v + 1]], vals, sp, dv.astype(np.float64),
+                              None if av is None else av.astype(np.float64), bg)
+        ref = np.stack([o["u"], o["v"], o["conic"][0], o["conic"][1], o["conic"][2], o["sigma"],
+                        o["rgb"][0], o["rgb"][1], o["rgb"][2]], axis=1)
+        errs = [G.rel_l2(g[v][:, j], ref[:, j]) for j in range(9)]
+        G.say(f"  view {v}: rel L2 (u v A B C sigma r g b) " + " ".join(f"{e:.1e}" for e in errs))
+        assert max(errs) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged", "hd", "multi"])
+def test_project_bwd_parity(name):
+    s = scene(name)
+    tile = 16
+    P, projs, arrs, *_ = oracle_stage(name, tile)
+    rng = np.random.default_rng(11)
+    V, N = s.n_views, s.n
+    grad2d = np.zeros((V, N, 9), np.float32)
+    flags = arrs["flags"].copy()
+    for v, pr in enumerate(projs):
+        use = (pr["visible"] > 0) & (pr["margin"] >= PROJ_MARGIN)
+        grad2d[v][use] = rng.standard_normal((use.sum(), 9)).astype(np.float32)
+    G.say(f"[project_bwd] {name} N={N} V={V}")
+    g = G.gpu_project_bwd(s, flags, grad2d)
+    acc = None
+    for v in range(V):
+        W, H = (int(x) for x in s.sizes[v])
+        gv = grad2d[v].astype(np.float64)
+        up = dict(u=gv[:, 0], v=gv[:, 1], conic=gv[:, 2:5].T.copy(), sigma=gv[:, 5], rgb=gv[:, 6:9].T.copy())
+        acc = oracle.project_bwd(P, s.viewmats[v], s.intrinsics[v], W, H, up, acc=acc)
+    names = [("means", "means"), ("log_scales", "log_scales"), ("quats", "quats"),
+             ("opac", "opacity_logits"), ("sh", "sh")]
+    errs = {gn: G.rel_l2(g[gn], acc[on]) for on, gn in names}
+    G.say("  rel L2: " + " ".join(f"{k} {e:.1e}" for k, e in errs.items()))
+    assert max(errs.values()) <= GRAD_TOL
+
+
+def test_loss_parity():
+    import torch
+    from paper_2606_11390_amd import binding as B
+    rng = np.random.default_rng(4)
+    n = 3 * 257 * 131 + 5
+    img = rng.uniform(0, 1, n).astype(np.float32)
+    tgt = rng.uniform(0, 1, n).astype(np.float32)
+    loss = torch.zeros(1, device="cuda")
+    d = torch.zeros(n, device="cuda")
+    ws = torch.empty(B.loss_workspace_size(n), dtype=torch.uint8, device="cuda")
+    B.loss_l2(G.dev(img), G.dev(tgt), loss, d, ws)
+    L, (dref,) = oracle.l2_loss([img], [tgt])
+    assert G.host(loss)[0] == pytest.approx(L, rel=1e-6)
+    assert G.rel_max(G.host(d), dref) <= 1e-6

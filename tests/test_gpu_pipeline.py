@@ -1,0 +1,159 @@
+"""GPU whole-path tests: end to end against the oracle, batched against plain
+per-view launches, persistent against grid scheduling, HIP-graph replay
+against eager execution, and the autograd wrapper against the fused step.
+
+End to end, the GPU's own float32 projection feeds its binning and
+compositing, so its image differs from the FP64 pipeline by the float32
+rounding of the projected means and conics propagated through the falloff
+(see the bound in ``_e2e_tol``), not by the 1e-5 of the stage-isolated tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_11390_amd import binding as B
+from paper_2606_11390_amd import render as R
+from paper_2606_11390_amd import scenes
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+def _run_step(s, tile=16, persistent=False, capacity=1 << 16):
+    r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=tile, capacity=capacity, persistent=persistent)
+    P, cams = R.params_to_device(s)
+    r.fit_capacity(P, cams)
+    tg = R.packed_targets(s)
+    grads = R.zeros_like_params(P)
+    r.step(P, cams, tg, grads)
+    torch.cuda.synchronize()
+    return r, P, cams, tg, grads
+
+
+def _e2e_tol(s):
+    # pixel coordinates carry ~4 ulp(max(W, H)) of float32 error; the falloff
+    # exponent's sensitivity to the mean is |Q d| <= sqrt(2 q / eps2d) <= 9 px^-1
+    # over the composited support, and colour errors add linearly over at most
+    # a few dozen significant layers: a 1e-5-scale budget per unit ulp.
+    w = float(np.max(s.sizes))
+    return 64 * 4 * EPS32 * w * 9
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_end_to_end_against_oracle(name):
+    s = scenes.tiny() if name == "tiny" else scenes.tiny(seed=21, n_gaussians=1500, width=100, height=75,
+                                                         focal=90.0)
+    G.say(f"[e2e] {name}")
+    r, P, cams, tg, grads = _run_step(s)
+    o = oracle.step(s)
+    img = G.host(r.images)
+    ref = np.concatenate([i.reshape(-1) for i in o["imgs"]])
+    e_img = G.rel_max(img, ref)
+    loss = float(G.host(r.loss)[0])
+    gn = {k: G.host(v) for k, v in grads.items()}
+    errs = {k: G.rel_l2(gn[k2], o["grads"][k]) for k, k2 in
+            (("means", "means"), ("log_scales", "log_scales"), ("quats", "quats"), ("opac", "opacity_logits"),
+             ("sh", "sh"))}
+    tol = _e2e_tol(s)
+    G.say(f"  image {e_img:.2e} (bound {tol:.1e}), loss {loss:.6f} vs {o['loss']:.6f}, grads " +
+          " ".join(f"{k} {e:.1e}" for k, e in errs.items()))
+    assert e_img <= tol
+    assert loss == pytest.approx(o["loss"], rel=1e-4)
+    assert max(errs.values()) <= 20 * tol
+
+
+def _multi():
+    return scenes.blobs(5, 30_000, 64, 20.0, [(320, 240, 250.0), (200, 150, 156.0), (128, 96, 100.0),
+                                              (257, 131, 200.0)], name="multi")
+
+
+def test_batched_equals_plain_views():
+    s = _multi()
+    G.say("[batched == plain]")
+    rb, P, cams, tg, gb = _run_step(s)
+    imgs_b = G.unpack(G.host(rb.images), s.sizes, 3)
+    gsum = {k: np.zeros_like(G.host(v)) for k, v in gb.items()}
+    ranges_b = G.host(rb.ranges).reshape(-1, 2)
+    gid_b = G.host(rb.isect_gid)
+    _, toff, _ = B.tile_grid(s.sizes, 16)
+    for v in range(s.n_views):
+        sv = scenes.Scene(s.means, s.log_scales, s.quats, s.opacity_logits, s.sh, s.sh_degree,
+                          s.viewmats[v:v + 1], s.intrinsics[v:v + 1], s.sizes[v:v + 1], [s.targets[v]])
+        # the plain path's loss is a mean over its own view: rescale to the batch mean
+        r1, P1, c1, t1, g1 = _run_step(sv)
+        np.testing.assert_array_equal(G.host(r1.images).reshape(imgs_b[v].shape), imgs_b[v])
+        r1r = G.host(r1.ranges).reshape(-1, 2)
+        rbv = ranges_b[toff[v]:toff[v + 1]]
+        gid1 = G.host(r1.isect_gid)
+        for t in np.nonzero(r1r[:, 1] > r1r[:, 0])[0]:
+            np.testing.assert_array_equal(gid1[r1r[t, 0]:r1r[t, 1]], gid_b[rbv[t, 0]:rbv[t, 1]])
+        scale = (3 * int(s.sizes[v][0]) * int(s.sizes[v][1])) / (3 * s.pixels)
+        for k in gsum:
+            gsum[k] += G.host(g1[k]) * scale
+    for k in gsum:
+        e = G.rel_l2(G.host(gb[k]), gsum[k])
+        G.say(f"  grad {k}: rel L2 {e:.1e}")
+        assert e <= 1e-5
+
+
+def test_persistent_equals_grid():
+    s = _multi()
+    G.say("[persistent == grid]")
+    ra, *_, ga = _run_step(s, persistent=False)
+    rp, *_, gp = _run_step(s, persistent=True)
+    np.testing.assert_array_equal(G.host(ra.images), G.host(rp.images))
+    np.testing.assert_array_equal(G.host(ra.n_contrib), G.host(rp.n_contrib))
+    for k in ga:
+        assert G.rel_l2(G.host(gp[k]), G.host(ga[k])) <= 1e-5
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replay_matches_eager(persistent):
+    s = _multi()
+    G.say(f"[graph replay] persistent={persistent}")
+    r, P, cams, tg, grads = _run_step(s, persistent=persistent)
+    eager = {k: G.host(v).copy() for k, v in grads.items()}
+    eager_img = G.host(r.images).copy()
+    eager_loss = float(G.host(r.loss)[0])
+    r.capture(P, cams, tg, grads)
+    for rep in range(3):
+        for v in grads.values():
+            v.fill_(float("nan"))
+        r.images.fill_(float("nan"))
+        torch.cuda.synchronize()
+        r.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(G.host(r.images), eager_img)
+        assert float(G.host(r.loss)[0]) == pytest.approx(eager_loss, rel=1e-6)
+        for k, v in grads.items():
+            assert G.rel_l2(G.host(v), eager[k]) <= 1e-5, (rep, k)
+        # unrelated eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+
+
+def test_autograd_matches_fused_step():
+    s = scenes.tiny(seed=9, n_gaussians=3000, width=160, height=96, focal=110.0)
+    G.say("[autograd]")
+    r, P, cams, tg, grads = _run_step(s)
+    Pt = {k: v.clone().requires_grad_(True) for k, v in P.items()}
+    img = R.render(r, Pt, cams)
+    loss = ((img - tg) ** 2).mean()
+    loss.backward()
+    assert float(loss) == pytest.approx(float(G.host(r.loss)[0]), rel=1e-5)
+    for k in grads:
+        assert G.rel_l2(G.host(Pt[k].grad), G.host(grads[k])) <= 1e-5, k
+
+
+def test_renderer_reports_overflow():
+    s = scenes.tiny()
+    r = R.Renderer(s.n, s.sh_degree, s.sizes, capacity=100)
+    P, cams = R.params_to_device(s)
+    with pytest.raises(B.GSError):
+        R.render(r, P, cams)
+    m = r.fit_capacity(P, cams)
+    assert r.capacity >= m
+    R.render(r, P, cams)
