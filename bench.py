@@ -81,12 +81,13 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
     s, q = r._sched()
     out["raster_bwd"] = timed(lambda: B.rasterize_bwd(r.splats, r.isect_gid, r.ranges, r.n, r.sizes, r.tile,
                                                       r.background, s, q, r.T_final, r.n_contrib, r.d_images,
-                                                      None, r.grad2d, accumulate=True), steps, torch)
+                                                      None, r.grad2d, accumulate=True, block=r.block_bwd),
+                                   steps, torch)
     out["project_bwd"] = timed(lambda: r.project_bwd(P, cams, grads), steps, torch)
     return out
 
 
-def cpu_baseline(scene, tile, seed=0, frac=0.02, crop_frac=0.1):
+def cpu_baseline(scene, tile, seed=0, frac=0.05, crop_frac=0.25):
     """FP64 oracle on a bounded sample of the same step, scaled to the frame.
 
     Per-Gaussian work (projection + its backward) is timed on a seeded
@@ -144,12 +145,25 @@ def main():
     ap.add_argument("--n-gaussians", type=int, default=None)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batched path at --tile instead of the autotuned tile edge")
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all",
                     help="restrict to one path (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB three times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs one GPU's share of the step; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "dispatches": 3}))
+        return
 
     import torch
     from paper_2606_11390_amd import binding as B
@@ -166,9 +180,9 @@ def main():
     gauss = scene.n * scene.n_views
     result = {}
 
-    def run_path(persistent, graph):
-        r = R.Renderer(scene.n, scene.sh_degree, scene.sizes, tile=args.tile, capacity=1 << 22,
-                       persistent=persistent)
+    def run_path(persistent, graph, tile=None, block=(0, 0), block_bwd=None):
+        r = R.Renderer(scene.n, scene.sh_degree, scene.sizes, tile=tile or args.tile, capacity=1 << 22,
+                       persistent=persistent, block=block, block_bwd=block_bwd)
         m = r.fit_capacity(P, cams)
         if graph:
             r.capture(P, cams, tg, grads, warmup=max(1, args.warmup))
@@ -181,19 +195,64 @@ def main():
         ms = timed(step, args.steps, torch)
         return r, m, ms
 
+    def run_plain_per_view():
+        """V single-view steps launched one after another (every call of the
+        path once per view, parameters re-read and dense parameter gradients
+        produced and summed per view): the baseline the batched path replaces."""
+        rs, views = [], []
+        for v in range(scene.n_views):
+            r = R.Renderer(scene.n, scene.sh_degree, scene.sizes[v:v + 1], tile=args.tile, capacity=1 << 20)
+            cv = {k: t[v:v + 1].contiguous() for k, t in cams.items()}
+            o = int(np.sum(3 * scene.sizes[:v, 0].astype(np.int64) * scene.sizes[:v, 1]))
+            n = 3 * int(scene.sizes[v, 0]) * int(scene.sizes[v, 1])
+            r.fit_capacity(P, cv)
+            rs.append(r)
+            views.append((cv, tg[o:o + n]))
+        gv = R.zeros_like_params(P)
+
+        def step():
+            for k in grads:
+                grads[k].zero_()
+            for r, (cv, t) in zip(rs, views):
+                r.step(P, cv, t, gv)
+                for k in grads:
+                    grads[k].add_(gv[k])
+        for _ in range(args.warmup):
+            step()
+        ms = timed(step, args.steps, torch)
+        m = sum(int(r.info[B.INFO_ISECT]) for r in rs)
+        return rs[0], m, ms
+
     if args.only in ("all", "plain"):
-        r_plain, m, ms_plain = run_path(False, False)
+        if scene.n_views > 1:
+            r_plain, m, ms_plain = run_plain_per_view()
+        else:
+            r_plain, m, ms_plain = run_path(False, False)
         result["plain"] = {"ms_per_step": ms_plain, "mp_per_s": pixels / ms_plain / 1e3}
         log(f"plain: {ms_plain:.3f} ms/step, {pixels / ms_plain / 1e3:.1f} MP/s, M={m}")
         if args.only == "plain":
             r_main, ms_main = r_plain, ms_plain
         del_plain = args.only == "all"
-    if args.only in ("all", "batched"):
-        r_main, m, ms_main = run_path(True, True)
-        log(f"batched: {ms_main:.3f} ms/step, {pixels / ms_main / 1e3:.1f} MP/s, M={m}")
     if args.only == "all" and del_plain:
         del r_plain
         torch.cuda.empty_cache()
+    tuned = None
+    if args.only in ("all", "batched"):
+        tiles = (8, 16, 32) if args.autotune else (args.tile,)
+        tuned = R.autotune(P, cams, tg, scene.sh_degree, scene.sizes, tiles=tiles, steps=max(3, args.steps // 4),
+                           log=log)
+        tuned.pop("trials", None)
+        if args.tile in tiles and tuned["tile"] != args.tile:
+            # like-for-like figure at the plain path's tile edge
+            t16 = R.autotune(P, cams, tg, scene.sh_degree, scene.sizes, tiles=(args.tile,), steps=3)
+            r16, _, ms16 = run_path(True, True, args.tile, tuple(t16["block"]), tuple(t16["block_bwd"]))
+            result["batched_same_tile"] = {"tile": args.tile, "block": t16["block"], "block_bwd": t16["block_bwd"],
+                                           "ms_per_step": ms16, "mp_per_s": pixels / ms16 / 1e3}
+            del r16
+            torch.cuda.empty_cache()
+        r_main, m, ms_main = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]))
+        log(f"batched (tile {tuned['tile']}, blocks {tuned['block']} / {tuned['block_bwd']}): {ms_main:.3f} ms/step, "
+            f"{pixels / ms_main / 1e3:.1f} MP/s, M={m}")
 
     # per-call durations on the main path, HIP events on the launch stream
     st = stage_times(r_main, P, cams, tg, grads, args.steps, torch)
@@ -245,13 +304,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{scene.name}: {scene.n} Gaussians, SH degree {scene.sh_degree}, "
                                f"{scene.n_views} view(s) {'+'.join(f'{w}x{h}' for w, h in scene.sizes)}, "
-                               f"tile {args.tile}, FP32 forward + L2 loss + backward",
+                               f"FP32 forward + L2 loss + backward",
+                   "tile": r_main.tile, "wave_block_fwd": list(r_main.block),
+                   "wave_block_bwd": list(r_main.block_bwd),
                    "path": "batched" if args.only != "plain" else "plain",
                    "gaussians": scene.n, "views": scene.n_views, "pixels": pixels,
                    "intersections": int(info[B.INFO_ISECT]), "visible": int(info[B.INFO_VISIBLE]),
                    "parallelism": "1 GPU"},
         "gaussians_per_s": round(gauss / ms_main * 1e3, 1),
         "plain": {k: round(v, 4) for k, v in result.get("plain", {}).items()},
+        "batched_same_tile": result.get("batched_same_tile"),
+        "autotuned": tuned,
         "stage_ms": {k: round(v, 4) for k, v in st.items()},
         "visits": {"forward": fwd_visits, "backward": bwd_visits},
         "roofline": roofline,

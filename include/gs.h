@@ -47,8 +47,13 @@
  *   [5] log2(sigma)   sigma = sigmoid(opacity logit)
  *   [6] r, [7] g, [8] b   view-dependent colour (after the clamp at 0)
  *   [9] sigma
- *   [10] depth (camera-space z), [11] 0
- * Records of culled Gaussians are left unwritten.
+ *   [10], [11] (int32 bit patterns) conservative pixel ranges of the region
+ *                     where alpha >= 1/255: x range lo | hi << 16 and y range
+ *                     likewise (int16 column / row indices, inclusive); every
+ *                     pixel outside the box has alpha < 1/255, so the
+ *                     rasterisers may skip the splat there
+ * Records of culled Gaussians are left unwritten.  Views are at most 32767
+ * pixels wide and high.
  *
  * The 2-D gradient record (GS_GRAD_FLOATS = 9 float32), one per
  * (view, Gaussian): derivatives of the loss with respect to
@@ -198,6 +203,11 @@ int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* sche
  * T *= 1 - alpha.  Output colour = C + T * background.
  * Inputs: splats, isect_gid and tile_ranges from gs_project / gs_bin_sort;
  *   background (host)[3].
+ * block_w, px_per_lane: the pixel block one wavefront covers (block_w wide,
+ *   64 * px_per_lane / block_w rows) and the adjacent pixels each lane owns;
+ *   0, 0 selects the default (8, 1).  Valid pairs: tile 8: (8, 1); tile 16:
+ *   (8, 1), (16, 1), (16, 4); tile 32: (8, 1), (16, 4), (32, 4).  The choice
+ *   changes only speed, never a result bit.
  * schedule: NULL for one workgroup per tile, or a gs_tile_schedule buffer
  *   for the persistent kernel that pulls (view, tile) items from a global
  *   queue; queue (device int32[1]) is the persistent kernel's counter (reset
@@ -207,16 +217,17 @@ int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* sche
  *   the last composited entry.
  */
 int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
-                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
-                     const void* schedule, int32_t* queue, float* images, float* T_final,
-                     int32_t* n_contrib, void* stream);
+                     int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
+                     const float* background, const void* schedule, int32_t* queue, float* images,
+                     float* T_final, int32_t* n_contrib, void* stream);
 
 /*
  * gs_rasterize_bwd - backward of gs_rasterize_fwd (paper Section 4: backward
  * of the rasteriser with gradient accumulation by atomics).  Walks each
  * pixel's composited entries from the back, recovering each transmittance
  * from T_final by division by (1 - alpha) instead of storing per-pixel lists.
- * Inputs: as gs_rasterize_fwd plus its T_final and n_contrib, d_images (packed
+ * Inputs: as gs_rasterize_fwd (block_w and px_per_lane likewise only change
+ *   speed) plus its T_final and n_contrib, d_images (packed
  *   like images) and d_alpha (packed [H][W] per view; gradient with respect
  *   to 1 - T_final; may be NULL).
  * Output: grad2d[V][N][9] (see the 2-D gradient record).  With accumulate = 0
@@ -225,8 +236,8 @@ int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_
  *   existing contents.  Summation order is not deterministic.
  */
 int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
-                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
-                     const void* schedule, int32_t* queue, const float* T_final,
+                     int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
+                     const float* background, const void* schedule, int32_t* queue, const float* T_final,
                      const int32_t* n_contrib, const float* d_images, const float* d_alpha,
                      float* grad2d, int accumulate, void* stream);
 

@@ -170,9 +170,43 @@ def to_record(pr):
         rec[:, 5] = np.log2(pr["sigma"])
     rec[:, 6:9] = pr["rgb"].T
     rec[:, 9] = pr["sigma"]
-    rec[:, 10] = pr["depth"]
     rec[~vis] = 0.0
-    return rec.astype(np.float32)
+    out = rec.astype(np.float32)
+    bx, by = alpha_box(pr)
+    out[:, 10] = np.where(vis, bx, 0).astype(np.int32).view(np.float32)
+    out[:, 11] = np.where(vis, by, 0).astype(np.int32).view(np.float32)
+    return out
+
+
+def alpha_extent(pr):
+    """Half-widths (x, y) of the region where alpha >= 1/255, i.e. of the
+    ellipse d^T conic d <= 2 ln(255 sigma): sqrt(tau Sigma2_xx), sqrt(tau Sigma2_yy)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tau = np.maximum(2.0 * np.log(255.0 * pr["sigma"]), 0.0)
+        return np.sqrt(tau * pr["cov"][0]), np.sqrt(tau * pr["cov"][2])
+
+
+def alpha_box(pr):
+    """The record's packed pixel ranges (lo | hi << 16, int16 each) of the
+    alpha >= 1/255 region, widened by 1e-3 relative + one pixel: every pixel
+    outside has alpha < 1/255."""
+    ex, ey = alpha_extent(pr)
+
+    def pack(c, e):
+        with np.errstate(invalid="ignore"):
+            lo = np.clip(np.floor(c - e * 1.001 - 0.5) - 1, -32768, 32767)
+            hi = np.clip(np.ceil(c + e * 1.001 - 0.5) + 1, -32768, 32767)
+        lo = np.nan_to_num(lo).astype(np.int64)
+        hi = np.nan_to_num(hi).astype(np.int64)
+        return ((lo & 0xFFFF) | (hi << 16)).astype(np.int64).astype(np.uint32).view(np.int32)
+
+    return pack(pr["u"], ex), pack(pr["v"], ey)
+
+
+def unpack_box(words):
+    w = np.asarray(words).view(np.int32).astype(np.int64)
+    lo = ((w & 0xFFFF) ^ 0x8000) - 0x8000
+    return lo, w >> 16
 
 
 def from_record(rec):

@@ -42,8 +42,9 @@ _SIGS = {
     "gs_bin_sort": (_int, [_p, _p, _p, _p, _i64, _int, _p, _int, _i64, _p, _sz, _p, _p, _p, _p, _p]),
     "gs_tile_schedule_size": (_sz, [_i64]),
     "gs_tile_schedule": (_int, [_p, _i64, _p, _sz, _p]),
-    "gs_rasterize_fwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p, _p, _p]),
-    "gs_rasterize_bwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p, _p, _p, _p, _int, _p]),
+    "gs_rasterize_fwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p]),
+    "gs_rasterize_bwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p,
+                                _int, _p]),
     "gs_project_bwd": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
                               _p, _p, _p, _p]),
     "gs_raster_visits": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p]),
@@ -165,11 +166,12 @@ def tile_schedule(tile_ranges, total_tiles, schedule):
 
 
 def rasterize_fwd(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, queue, images,
-                  T_final, n_contrib):
+                  T_final, n_contrib, block=(0, 0)):
     sz, szp = _host_i32(sizes)
     bg, bgp = _host_f32(background)
     rc = lib().gs_rasterize_fwd(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
-                                _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile), bgp,
+                                _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile),
+                                int(block[0]), int(block[1]), bgp,
                                 _ptr(schedule, U8, "schedule"), _ptr(queue, I32, "queue"),
                                 _ptr(images, F32, "images"), _ptr(T_final, F32, "T_final"),
                                 _ptr(n_contrib, I32, "n_contrib"), _stream())
@@ -177,11 +179,12 @@ def rasterize_fwd(splats, isect_gid, tile_ranges, n, sizes, tile, background, sc
 
 
 def rasterize_bwd(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, queue, T_final,
-                  n_contrib, d_images, d_alpha, grad2d, accumulate=False):
+                  n_contrib, d_images, d_alpha, grad2d, accumulate=False, block=(0, 0)):
     sz, szp = _host_i32(sizes)
     bg, bgp = _host_f32(background)
     rc = lib().gs_rasterize_bwd(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
-                                _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile), bgp,
+                                _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile),
+                                int(block[0]), int(block[1]), bgp,
                                 _ptr(schedule, U8, "schedule"), _ptr(queue, I32, "queue"),
                                 _ptr(T_final, F32, "T_final"), _ptr(n_contrib, I32, "n_contrib"),
                                 _ptr(d_images, F32, "d_images"), _ptr(d_alpha, F32, "d_alpha"),

@@ -24,14 +24,15 @@ hipError_t launch_bin_sort(const float* splats, const float* depths, const int2*
 size_t tile_schedule_size(long long total_tiles);
 hipError_t launch_tile_schedule(const int2* ranges, long long total_tiles, void* schedule,
                                 hipStream_t st);
-hipError_t launch_raster_fwd(int tile, const ViewTable& vt, const float* splats, const int* gids,
-                             const int2* ranges, long long N, const float* bg, const int* order,
-                             int* queue, float* img, float* Tout, int* lastout, int* visits,
+bool raster_cfg_ok(int tile, int bw, int ppl);
+hipError_t launch_raster_fwd(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
+                             const int* gids, const int2* ranges, long long N, const float* bg,
+                             const int* order, int* queue, float* img, float* Tout, int* lastout, int* visits,
                              hipStream_t st);
-hipError_t launch_raster_bwd(int tile, const ViewTable& vt, const float* splats, const int* gids,
-                             const int2* ranges, long long N, const float* bg, const int* order,
-                             int* queue, const float* Tfin, const int* nlast, const float* dimg,
-                             const float* dalpha, float* grad2d, hipStream_t st);
+hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
+                             const int* gids, const int2* ranges, long long N, const float* bg,
+                             const int* order, int* queue, const float* Tfin, const int* nlast,
+                             const float* dimg, const float* dalpha, float* grad2d, hipStream_t st);
 size_t loss_workspace_size(long long n);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
 hipError_t launch_loss_l2(const float* img, const float* tgt, long long n, float* loss, float* dimg,
@@ -54,7 +55,7 @@ bool make_views(const int32_t* sizes, int n_views, int tile, ViewTable& vt)
     long long tiles = 0, pix = 0;
     for (int v = 0; v < n_views; v++) {
         const int W = sizes[2 * v], H = sizes[2 * v + 1];
-        if (W <= 0 || H <= 0 || W > 65536 || H > 65536) return false;
+        if (W <= 0 || H <= 0 || W > 32767 || H > 32767) return false;
         const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
         vt.W[v] = W;
         vt.H[v] = H;
@@ -162,26 +163,28 @@ int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* sche
 }
 
 int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
-                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
-                     const void* schedule, int32_t* queue, float* images, float* T_final,
-                     int32_t* n_contrib, void* stream)
+                     int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
+                     const float* background, const void* schedule, int32_t* queue, float* images,
+                     float* T_final, int32_t* n_contrib, void* stream)
 {
     ViewTable vt;
     if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
         return GS_ERR_ARG;
+    if (!gs::raster_cfg_ok(tile, block_w, px_per_lane)) return GS_ERR_ARG;
     if (!tile_ranges || !images || !T_final || !n_contrib || !background) return GS_ERR_ARG;
     if (!isect_gid || (n > 0 && (!splats || !aligned16(splats)))) return GS_ERR_ARG;
     if (schedule && !queue) return GS_ERR_ARG;
     for (int c = 0; c < 3; c++)
         if (!std::isfinite(background[c])) return GS_ERR_ARG;
-    return status(gs::launch_raster_fwd(tile, vt, splats, isect_gid, reinterpret_cast<const int2*>(tile_ranges),
-                                        n, background, static_cast<const int*>(schedule), queue, images,
-                                        T_final, n_contrib, nullptr, as_stream(stream)));
+    return status(gs::launch_raster_fwd(tile, block_w, px_per_lane, vt, splats, isect_gid,
+                                        reinterpret_cast<const int2*>(tile_ranges), n, background,
+                                        static_cast<const int*>(schedule), queue, images, T_final, n_contrib,
+                                        nullptr, as_stream(stream)));
 }
 
 int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
-                     int64_t n, int n_views, const int32_t* sizes, int tile, const float* background,
-                     const void* schedule, int32_t* queue, const float* T_final,
+                     int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
+                     const float* background, const void* schedule, int32_t* queue, const float* T_final,
                      const int32_t* n_contrib, const float* d_images, const float* d_alpha,
                      float* grad2d, int accumulate, void* stream)
 {
@@ -190,6 +193,7 @@ int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_
         return GS_ERR_ARG;
     if (!tile_ranges || !T_final || !n_contrib || !d_images || !grad2d || !background || !isect_gid)
         return GS_ERR_ARG;
+    if (!gs::raster_cfg_ok(tile, block_w, px_per_lane)) return GS_ERR_ARG;
     if (n > 0 && (!splats || !aligned16(splats))) return GS_ERR_ARG;
     if (schedule && !queue) return GS_ERR_ARG;
     for (int c = 0; c < 3; c++)
@@ -199,9 +203,10 @@ int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_
                                                  n * n_views * GS_GRAD_FLOATS, as_stream(stream));
         if (e != hipSuccess) return GS_ERR_HIP;
     }
-    return status(gs::launch_raster_bwd(tile, vt, splats, isect_gid, reinterpret_cast<const int2*>(tile_ranges),
-                                        n, background, static_cast<const int*>(schedule), queue, T_final,
-                                        n_contrib, d_images, d_alpha, grad2d, as_stream(stream)));
+    return status(gs::launch_raster_bwd(tile, block_w, px_per_lane, vt, splats, isect_gid,
+                                        reinterpret_cast<const int2*>(tile_ranges), n, background,
+                                        static_cast<const int*>(schedule), queue, T_final, n_contrib, d_images,
+                                        d_alpha, grad2d, as_stream(stream)));
 }
 
 int gs_project_bwd(const float* means, const float* log_scales, const float* quats,
@@ -234,9 +239,9 @@ int gs_raster_visits(const float* splats, const int32_t* isect_gid, const int32_
     if (!tile_ranges || !images || !T_final || !n_contrib || !visits || !isect_gid) return GS_ERR_ARG;
     if (n > 0 && (!splats || !aligned16(splats))) return GS_ERR_ARG;
     const float bg[3] = {0.0f, 0.0f, 0.0f};
-    return status(gs::launch_raster_fwd(tile, vt, splats, isect_gid, reinterpret_cast<const int2*>(tile_ranges),
-                                        n, bg, nullptr, nullptr, images, T_final, n_contrib, visits,
-                                        as_stream(stream)));
+    return status(gs::launch_raster_fwd(tile, 0, 0, vt, splats, isect_gid,
+                                        reinterpret_cast<const int2*>(tile_ranges), n, bg, nullptr, nullptr, images,
+                                        T_final, n_contrib, visits, as_stream(stream)));
 }
 
 size_t gs_loss_workspace_size(int64_t n_elems)

@@ -97,6 +97,40 @@ __device__ __forceinline__ float wave_sum(float x)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// One butterfly step of a reduce-scatter: lanes with `hi` keep the odd member
+// of the pair and send the even one, their DPP partner does the opposite, so
+// each lane ends with the pair-sum of the member it kept.
+template <int CTRL>
+__device__ __forceinline__ float bfly(float even, float odd, bool hi)
+{
+    const float keep = hi ? odd : even;
+    const float send = hi ? even : odd;
+    return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xF, 0xF, false));
+}
+
+// Wave-wide sums of nine values, scattered: afterwards lane l (l < 16) holds
+// the total of value j(l) = b3 + 2 b2 + 4 b0 + 8 b1 (b_k = bit k of l), a
+// permutation of 0..15 in which 9..15 carry zeros.  The four in-row steps
+// pair lanes across bit 3 (row mirror), bit 2 (half-row mirror), bit 0 and
+// bit 1 (quad permutes); two shuffles then add the four rows.  About 40 VALU
+// operations instead of nine full reductions.
+__device__ __forceinline__ float wave_sum9_scatter(const float* a, int& j)
+{
+    const int l = __lane_id();
+    const bool h1 = l & 8, h2 = l & 4, h3 = l & 1, h4 = l & 2;
+    const float b0 = bfly<0x140>(a[0], a[1], h1), b1 = bfly<0x140>(a[2], a[3], h1);
+    const float b2 = bfly<0x140>(a[4], a[5], h1), b3 = bfly<0x140>(a[6], a[7], h1);
+    const float b4 = bfly<0x140>(a[8], 0.0f, h1);
+    const float c0 = bfly<0x141>(b0, b1, h2), c1 = bfly<0x141>(b2, b3, h2);
+    const float c2 = bfly<0x141>(b4, 0.0f, h2);
+    const float d0 = bfly<0xB1>(c0, c1, h3), d1 = bfly<0xB1>(c2, 0.0f, h3);
+    float e = bfly<0x4E>(d0, d1, h4);
+    e += __shfl_xor(e, 16);
+    e += __shfl_xor(e, 32);
+    j = (h1 ? 1 : 0) | (h2 ? 2 : 0) | (h3 ? 4 : 0) | (h4 ? 8 : 0);
+    return e;
+}
+
 __device__ __forceinline__ int wave_max_i(int x)
 {
     for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o));

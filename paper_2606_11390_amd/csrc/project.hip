@@ -126,6 +126,15 @@ __device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, 
     R[8] = 1.0f - 2.0f * (x * x + y * y);
 }
 
+// [lo, hi] pixel indices whose centres (i + 0.5) may lie within e of c,
+// widened by one pixel, clamped to int16, packed lo | hi << 16
+__device__ __forceinline__ int pack_range(float c, float e)
+{
+    const float lo = fminf(fmaxf(floorf(c - e - 0.5f) - 1.0f, -32768.0f), 32767.0f);
+    const float hi = fminf(fmaxf(ceilf(c + e - 0.5f) + 1.0f, -32768.0f), 32767.0f);
+    return ((int)lo & 0xFFFF) | ((int)hi << 16);
+}
+
 struct Camera {
     float r[9];   // world-to-camera rotation, row-major
     float t[3];
@@ -280,7 +289,14 @@ __global__ __launch_bounds__(256) void k_project(
             float4* rec = reinterpret_cast<float4*>(splats + o_vg * GS_SPLAT_FLOATS);
             rec[0] = make_float4(u, vv, m00, m10);
             rec[1] = make_float4(m11, lsig, col[0], col[1]);
-            rec[2] = make_float4(col[2], sigma, ge.pz, 0.0f);
+            // conservative pixel box of the region where alpha >= 1/255:
+            // d^T Q d <= tau = 2 ln(255 sigma) has half-widths sqrt(tau a),
+            // sqrt(tau c); tau is inflated and the box padded by one pixel so
+            // that float32 rounding of the per-pixel alpha cannot reach out of it
+            const float tau = fmaxf(1.38629436f * (7.99435344f + lsig), 0.0f) * 1.001f + 0.01f;
+            const float ex = sqrtf(tau * ge.a), ey = sqrtf(tau * ge.c);
+            rec[2] = make_float4(col[2], sigma, __int_as_float(pack_range(u, ex)),
+                                 __int_as_float(pack_range(vv, ey)));
         }
         depths[o_vg] = ge.pz;
         radii[o_vg] = vis ? make_int2(rx, ry) : make_int2(0, 0);

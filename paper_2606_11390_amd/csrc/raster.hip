@@ -7,58 +7,80 @@
 //   alpha = min(0.99, sigma * exp(-d^T Q d / 2)), skip alpha < 1/255,
 //   stop before T would drop below 1e-4, C += alpha T c, T *= 1 - alpha.
 //
-// GPU organisation.  A work unit is one wavefront covering a band of a tile;
-// lane l owns P horizontally adjacent pixels.  Every lane of a wave walks the
-// same list position at the same time, so each splat record is fetched with
-// wave-uniform addresses: the compiler issues scalar (SMEM) loads through the
-// scalar cache and the VALU reads the record from SGPRs.  This replaces the
-// usual LDS staging: a broadcast LDS read still returns 64 copies of the data
-// through the LDS return path, while an SGPR operand costs nothing extra.
-// Waves of a tile never synchronise; each stops as soon as all of its pixels
-// have terminated (ballot).  The backward walks the same list from the back,
-// recovers T before each entry by dividing by (1 - alpha), and pre-reduces the
-// nine per-Gaussian gradient values across the wave with DPP before one lane
-// per value issues a float atomic.
+// GPU organisation.  A work unit is one wavefront on a BW x BH block of a
+// tile; lane l owns P horizontally adjacent pixels of one row.  Every lane of
+// a wave walks the same list position at the same time, so each splat index
+// and record has a wave-uniform address: the compiler issues scalar (SMEM)
+// loads through the scalar cache and the VALU reads the record from SGPRs.
+// This replaces the usual LDS staging (a broadcast LDS read still returns 64
+// copies of the data through the LDS return path; an SGPR operand is free).
+// Each record carries a conservative pixel box of its alpha >= 1/255 region;
+// a wave whose block misses the box skips the record with scalar-ALU compares
+// only, which cannot change any result since every pixel outside the box
+// would have skipped the entry anyway.  Waves of a tile never synchronise;
+// each stops as soon as all of its pixels have terminated (ballot).  The
+// backward walks the same list from the back, recovers T before each entry by
+// dividing by (1 - alpha), and pre-reduces the nine per-Gaussian gradient
+// values across the wave with DPP before nine lanes issue one float atomic.
 #include "gs_device.h"
 
 namespace gs {
 namespace {
 
 struct Rec {
-    float u, v, m00, m10, m11, ls, r, g, b;
+    float u, v, m00, m10, m11, ls, r, g, b, sigma;
+    int bx, by;
 };
 
 __device__ __forceinline__ Rec load_rec(const float* __restrict__ base, int gid)
 {
     const float4* p = reinterpret_cast<const float4*>(base + (size_t)gid * GS_SPLAT_FLOATS);
-    const float4 a = p[0], b = p[1];
-    const float c = base[(size_t)gid * GS_SPLAT_FLOATS + 8];
-    return Rec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c};
+    const float4 a = p[0], b = p[1], c = p[2];
+    return Rec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, __float_as_int(c.z), __float_as_int(c.w)};
 }
 
-template <int TS, int P>
+// does the packed [lo, hi] int16 range miss [b0, b1]?
+__device__ __forceinline__ bool misses(int packed, int b0, int b1)
+{
+    const int lo = (int)(short)(packed & 0xFFFF);
+    const int hi = packed >> 16;
+    return hi < b0 || lo > b1;
+}
+
+// A wave covers a BW x BH pixel block; BW / P lanes per pixel row.
+template <int TS, int BW, int P>
 struct Layout {
-    static constexpr int LPR = TS / P;          // lanes per pixel row
-    static constexpr int ROWS = GS_WAVE / LPR;  // pixel rows per wave
-    static constexpr int WPT = TS / ROWS;       // waves per tile
-    static_assert(TS % P == 0 && GS_WAVE % LPR == 0 && TS % ROWS == 0, "bad raster layout");
+    static constexpr int LPR = BW / P;
+    static constexpr int BH = GS_WAVE / LPR;
+    static constexpr int WX = TS / BW;          // blocks per tile row
+    static constexpr int WPT = WX * (TS / BH);  // waves per tile
+    static_assert(BW % P == 0 && GS_WAVE % LPR == 0 && TS % BW == 0 && TS % BH == 0, "bad layout");
 };
 
-template <int TS, int P>
-__device__ __forceinline__ void unit_pixels(const ViewTable& vt, int gt, int wit, int& v, int& px0,
-                                            int& py)
+struct Unit {
+    int v;               // view
+    int px0, py;         // this lane's first pixel
+    int bx0, by0;        // block origin (uniform)
+};
+
+template <int TS, int BW, int P>
+__device__ __forceinline__ Unit unit_of(const ViewTable& vt, int gt, int wit)
 {
-    using L = Layout<TS, P>;
-    v = view_of_tile(vt, gt);
-    const int lt = gt - vt.tile_off[v];
-    const int TX = vt.tiles_x[v];
+    using L = Layout<TS, BW, P>;
+    Unit u;
+    u.v = view_of_tile(vt, gt);
+    const int lt = gt - vt.tile_off[u.v];
+    const int TX = vt.tiles_x[u.v];
     const int ty = lt / TX, tx = lt - ty * TX;
+    u.bx0 = tx * TS + (wit % L::WX) * BW;
+    u.by0 = ty * TS + (wit / L::WX) * L::BH;
     const int lane = __lane_id();
-    px0 = tx * TS + (lane % L::LPR) * P;
-    py = ty * TS + wit * L::ROWS + lane / L::LPR;
+    u.px0 = u.bx0 + (lane % L::LPR) * P;
+    u.py = u.by0 + lane / L::LPR;
+    return u;
 }
 
-template <int TS, int P, bool COUNT>
+template <int TS, int BW, int P, bool COUNT>
 __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                                          const float* __restrict__ splats,
                                          const int* __restrict__ gids,
@@ -67,40 +89,48 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                                          float* __restrict__ Tout, int* __restrict__ lastout,
                                          int* __restrict__ visits)
 {
-    int v, px0, py;
-    unit_pixels<TS, P>(vt, gt, wit, v, px0, py);
-    const int W = vt.W[v], H = vt.H[v];
-    const float fy = (float)py + 0.5f;
+    using L = Layout<TS, BW, P>;
+    const Unit U = unit_of<TS, BW, P>(vt, gt, wit);
+    const int W = vt.W[U.v], H = vt.H[U.v];
+    const int bx1 = U.bx0 + BW - 1, by1 = U.by0 + L::BH - 1;
+    const float fy = (float)U.py + 0.5f;
     float fx[P], T[P], C0[P], C1[P], C2[P];
-    int last[P], nvis[P];
+    int last[P], stopk[P];
     bool done[P];
 #pragma unroll
     for (int p = 0; p < P; p++) {
-        fx[p] = (float)(px0 + p) + 0.5f;
-        nvis[p] = 0;
+        fx[p] = (float)(U.px0 + p) + 0.5f;
         T[p] = 1.0f;
         C0[p] = C1[p] = C2[p] = 0.0f;
         last[p] = 0;
-        done[p] = !(px0 + p < W && py < H);
+        stopk[p] = -1;
+        done[p] = !(U.px0 + p < W && U.py < H);
     }
     const int2 r = ranges[gt];
-    const float* base = splats + (size_t)v * (size_t)N * GS_SPLAT_FLOATS;
+    const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
+    // software pipeline: record k+1 and index k+2 are requested before entry
+    // k is composited, so the scalar-load latency overlaps the VALU work
+    Rec nxt = r.x < r.y ? load_rec(base, gids[r.x]) : Rec{};
+    int gnext = r.x + 1 < r.y ? gids[r.x + 1] : 0;
     for (int k = r.x; k < r.y; k++) {
+        const Rec s = nxt;
+        if (k + 1 < r.y) nxt = load_rec(base, gnext);
+        if (k + 2 < r.y) gnext = gids[k + 2];
         bool all_done = true;
 #pragma unroll
         for (int p = 0; p < P; p++) all_done = all_done && done[p];
         if (__ballot(!all_done) == 0ull) break;
-        const Rec s = load_rec(base, gids[k]);
+        if (misses(s.bx, U.bx0, bx1) || misses(s.by, U.by0, by1)) continue;
         const float dy = s.v - fy;
         const int k1 = k - r.x + 1;
 #pragma unroll
         for (int p = 0; p < P; p++) {
             const Falloff f = falloff(s.u - fx[p], dy, s.m00, s.m10, s.m11, s.ls);
             const float al = fminf(f.araw, kAlphaMax);
-            if (COUNT) nvis[p] += done[p] ? 0 : 1;
             bool ok = !done[p] && al >= kAlphaMin;
             const float Tn = __builtin_fmaf(-T[p], al, T[p]);
             const bool stop = ok && Tn < kTMin;
+            if (COUNT) stopk[p] = stop ? k1 : stopk[p];
             done[p] = done[p] || stop;
             ok = ok && !stop;
             const float wgt = ok ? al * T[p] : 0.0f;
@@ -111,23 +141,24 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
             last[p] = ok ? k1 : last[p];
         }
     }
-    const long long po = vt.pix_off[v];
+    const long long po = U.v < 0 ? 0 : vt.pix_off[U.v];
     const long long plane = (long long)W * H;
 #pragma unroll
     for (int p = 0; p < P; p++) {
-        if (px0 + p < W && py < H) {
-            const long long pix = (long long)py * W + px0 + p;
+        if (U.px0 + p < W && U.py < H) {
+            const long long pix = (long long)U.py * W + U.px0 + p;
             img[3 * po + pix] = __builtin_fmaf(T[p], bg0, C0[p]);
             img[3 * po + plane + pix] = __builtin_fmaf(T[p], bg1, C1[p]);
             img[3 * po + 2 * plane + pix] = __builtin_fmaf(T[p], bg2, C2[p]);
             Tout[po + pix] = T[p];
             lastout[po + pix] = last[p];
-            if (COUNT) visits[po + pix] = nvis[p];
+            // list entries this pixel examined: up to its stop, else the whole list
+            if (COUNT) visits[po + pix] = stopk[p] >= 0 ? stopk[p] : r.y - r.x;
         }
     }
 }
 
-template <int TS, int P, bool HAS_DA>
+template <int TS, int BW, int P, bool HAS_DA>
 __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                                          const float* __restrict__ splats,
                                          const int* __restrict__ gids,
@@ -138,43 +169,55 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                                          const float* __restrict__ dalpha,
                                          float* __restrict__ grad2d)
 {
-    int v, px0, py;
-    unit_pixels<TS, P>(vt, gt, wit, v, px0, py);
-    const int W = vt.W[v], H = vt.H[v];
-    const long long po = vt.pix_off[v];
+    using L = Layout<TS, BW, P>;
+    const Unit U = unit_of<TS, BW, P>(vt, gt, wit);
+    const int W = vt.W[U.v], H = vt.H[U.v];
+    const int bx1 = U.bx0 + BW - 1, by1 = U.by0 + L::BH - 1;
+    const long long po = vt.pix_off[U.v];
     const long long plane = (long long)W * H;
-    const float fy = (float)py + 0.5f;
-    float fx[P], T[P], TN[P], S0[P], S1[P], S2[P], g0[P], g1[P], g2[P], gA[P];
+    const float fy = (float)U.py + 0.5f;
+    float fx[P], T[P], S0[P], S1[P], S2[P], g0[P], g1[P], g2[P], gA[P];
     int last[P];
     int kmax = 0;
 #pragma unroll
     for (int p = 0; p < P; p++) {
-        fx[p] = (float)(px0 + p) + 0.5f;
-        const bool in = px0 + p < W && py < H;
-        const long long pix = (long long)py * W + px0 + p;
+        fx[p] = (float)(U.px0 + p) + 0.5f;
+        const bool in = U.px0 + p < W && U.py < H;
+        const long long pix = (long long)U.py * W + U.px0 + p;
         T[p] = in ? Tfin[po + pix] : 1.0f;
-        TN[p] = T[p];
         last[p] = in ? nlast[po + pix] : 0;
         g0[p] = in ? dimg[3 * po + pix] : 0.0f;
         g1[p] = in ? dimg[3 * po + plane + pix] : 0.0f;
         g2[p] = in ? dimg[3 * po + 2 * plane + pix] : 0.0f;
-        gA[p] = (HAS_DA && in) ? dalpha[po + pix] * TN[p] : 0.0f;
+        // d(1 - T_N)/d alpha_k = T_N / (1 - alpha_k): keep gA * T_N
+        gA[p] = (HAS_DA && in) ? dalpha[po + pix] * T[p] : 0.0f;
         S0[p] = bg0;
         S1[p] = bg1;
         S2[p] = bg2;
         kmax = max(kmax, last[p]);
     }
-    kmax = wave_max_i(kmax);
+    // the wave maximum is uniform; readfirstlane lets the compiler know, so the
+    // loop stays scalar and the record fetches stay scalar loads
+    kmax = __builtin_amdgcn_readfirstlane(wave_max_i(kmax));
     const int2 r = ranges[gt];
     kmax = min(kmax, r.y - r.x);
-    const float* base = splats + (size_t)v * (size_t)N * GS_SPLAT_FLOATS;
-    float* gbase = grad2d + (size_t)v * (size_t)N * GS_GRAD_FLOATS;
+    const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
+    float* gbase = grad2d + (size_t)U.v * (size_t)N * GS_GRAD_FLOATS;
     const int lane = __lane_id();
-    for (int k = r.x + kmax - 1; k >= r.x; k--) {
-        const int gid = gids[k];
-        const Rec s = load_rec(base, gid);
-        const float inv_sig = 1.0f / splats[(size_t)v * (size_t)N * GS_SPLAT_FLOATS +
-                                            (size_t)gid * GS_SPLAT_FLOATS + 9];
+    const int kend = r.x + kmax - 1;
+    int gcur = kend >= r.x ? gids[kend] : 0;
+    Rec nxt = kend >= r.x ? load_rec(base, gcur) : Rec{};
+    int gnext = kend - 1 >= r.x ? gids[kend - 1] : 0;
+    for (int k = kend; k >= r.x; k--) {
+        const int gid = gcur;
+        const Rec s = nxt;
+        if (k - 1 >= r.x) {
+            nxt = load_rec(base, gnext);
+            gcur = gnext;
+        }
+        if (k - 2 >= r.x) gnext = gids[k - 2];
+        if (misses(s.bx, U.bx0, bx1) || misses(s.by, U.by0, by1)) continue;
+        const float inv_sig = __builtin_amdgcn_rcpf(s.sigma);
         const float dy = s.v - fy;
         const int kk = k - r.x;
         float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
@@ -212,43 +255,33 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
             T[p] = ok ? Tk : T[p];
         }
         if (__ballot(any) == 0ull) continue;
-        const float r0 = wave_sum(a0), r1 = wave_sum(a1), r2 = wave_sum(a2);
-        const float r3 = wave_sum(a3), r4 = wave_sum(a4), r5 = wave_sum(a5);
-        const float r6 = wave_sum(a6), r7 = wave_sum(a7), r8 = wave_sum(a8);
-        if (lane < GS_GRAD_FLOATS) {
-            float x = r0;
-            x = lane == 1 ? r1 : x;
-            x = lane == 2 ? r2 : x;
-            x = lane == 3 ? r3 : x;
-            x = lane == 4 ? r4 : x;
-            x = lane == 5 ? r5 : x;
-            x = lane == 6 ? r6 : x;
-            x = lane == 7 ? r7 : x;
-            x = lane == 8 ? r8 : x;
-            unsafeAtomicAdd(gbase + (size_t)gid * GS_GRAD_FLOATS + lane, x);
-        }
+        const float acc[GS_GRAD_FLOATS] = {a0, a1, a2, a3, a4, a5, a6, a7, a8};
+        int j;
+        const float x = wave_sum9_scatter(acc, j);
+        if (lane < 16 && j < GS_GRAD_FLOATS) unsafeAtomicAdd(gbase + (size_t)gid * GS_GRAD_FLOATS + j, x);
     }
 }
 
-template <int TS, int P, bool COUNT>
-__global__ __launch_bounds__((GS_WAVE * Layout<TS, P>::WPT)) void k_raster_fwd(
+template <int TS, int BW, int P, bool COUNT>
+__global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_fwd(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
     float* __restrict__ img, float* __restrict__ Tout, int* __restrict__ lastout,
     int* __restrict__ visits)
 {
-    fwd_unit<TS, P, COUNT>(vt, blockIdx.x, threadIdx.x / GS_WAVE, splats, gids, ranges, N, bg0, bg1, bg2,
-                           img, Tout, lastout, visits);
+    const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
+    fwd_unit<TS, BW, P, COUNT>(vt, blockIdx.x, wit, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout, lastout,
+                               visits);
 }
 
-template <int TS, int P>
+template <int TS, int BW, int P>
 __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
     const int* __restrict__ order, int* __restrict__ queue, float* __restrict__ img,
     float* __restrict__ Tout, int* __restrict__ lastout)
 {
-    using L = Layout<TS, P>;
+    using L = Layout<TS, BW, P>;
     const int n_items = vt.total_tiles * L::WPT;
     for (;;) {
         int item = 0;
@@ -256,23 +289,24 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= n_items) break;
         const int gt = order[item / L::WPT];
-        fwd_unit<TS, P, false>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout,
-                               lastout, nullptr);
+        fwd_unit<TS, BW, P, false>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, img,
+                                   Tout, lastout, nullptr);
     }
 }
 
-template <int TS, int P, bool HAS_DA>
-__global__ __launch_bounds__((GS_WAVE * Layout<TS, P>::WPT)) void k_raster_bwd(
+template <int TS, int BW, int P, bool HAS_DA>
+__global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_bwd(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
     const float* __restrict__ Tfin, const int* __restrict__ nlast, const float* __restrict__ dimg,
     const float* __restrict__ dalpha, float* __restrict__ grad2d)
 {
-    bwd_unit<TS, P, HAS_DA>(vt, blockIdx.x, threadIdx.x / GS_WAVE, splats, gids, ranges, N, bg0, bg1,
-                            bg2, Tfin, nlast, dimg, dalpha, grad2d);
+    const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
+    bwd_unit<TS, BW, P, HAS_DA>(vt, blockIdx.x, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, dimg,
+                                dalpha, grad2d);
 }
 
-template <int TS, int P, bool HAS_DA>
+template <int TS, int BW, int P, bool HAS_DA>
 __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
@@ -280,7 +314,7 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
     const int* __restrict__ nlast, const float* __restrict__ dimg, const float* __restrict__ dalpha,
     float* __restrict__ grad2d)
 {
-    using L = Layout<TS, P>;
+    using L = Layout<TS, BW, P>;
     const int n_items = vt.total_tiles * L::WPT;
     for (;;) {
         int item = 0;
@@ -288,8 +322,8 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= n_items) break;
         const int gt = order[item / L::WPT];
-        bwd_unit<TS, P, HAS_DA>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, Tfin,
-                                nlast, dimg, dalpha, grad2d);
+        bwd_unit<TS, BW, P, HAS_DA>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, Tfin,
+                                    nlast, dimg, dalpha, grad2d);
     }
 }
 
@@ -309,89 +343,120 @@ int persistent_blocks()
     return n;
 }
 
-}  // namespace
-
-// pixels per lane for each tile edge: the whole 8x8 tile is one wave at P=1,
-// 16x16 and 32x32 tiles put four adjacent pixels of a row in each lane
-template <int TS> struct RasterCfg;
-template <> struct RasterCfg<8> { static constexpr int P = 1; };
-template <> struct RasterCfg<16> { static constexpr int P = 4; };
-template <> struct RasterCfg<32> { static constexpr int P = 4; };
-
-template <int TS>
-static hipError_t fwd_ts(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges,
-                         long long N, const float* bg, const int* order, int* queue, float* img,
-                         float* Tout, int* lastout, int* visits, hipStream_t st)
+template <int TS, int BW, int P>
+hipError_t fwd_cfg(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges, long long N,
+                   const float* bg, const int* order, int* queue, float* img, float* Tout, int* lastout,
+                   int* visits, hipStream_t st)
 {
-    constexpr int P = RasterCfg<TS>::P;
-    using L = Layout<TS, P>;
+    using L = Layout<TS, BW, P>;
     if (visits) {
-        hipLaunchKernelGGL((k_raster_fwd<TS, P, true>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st,
+        hipLaunchKernelGGL((k_raster_fwd<TS, BW, P, true>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st,
                            vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], img, Tout, lastout, visits);
     } else if (order) {
         hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, queue);
-        hipLaunchKernelGGL((k_raster_fwd_persistent<TS, P>), dim3(persistent_blocks()), dim3(GS_WAVE), 0,
+        hipLaunchKernelGGL((k_raster_fwd_persistent<TS, BW, P>), dim3(persistent_blocks()), dim3(GS_WAVE), 0,
                            st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, queue, img, Tout,
                            lastout);
     } else {
-        hipLaunchKernelGGL((k_raster_fwd<TS, P, false>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st,
-                           vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], img, Tout, lastout, nullptr);
+        hipLaunchKernelGGL((k_raster_fwd<TS, BW, P, false>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0,
+                           st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], img, Tout, lastout, nullptr);
     }
     return hipGetLastError();
 }
 
-template <int TS, bool DA>
-static hipError_t bwd_ts(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges,
-                         long long N, const float* bg, const int* order, int* queue, const float* Tfin,
-                         const int* nlast, const float* dimg, const float* dalpha, float* grad2d,
-                         hipStream_t st)
+template <int TS, int BW, int P>
+hipError_t bwd_cfg(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges, long long N,
+                   const float* bg, const int* order, int* queue, const float* Tfin, const int* nlast,
+                   const float* dimg, const float* dalpha, float* grad2d, hipStream_t st)
 {
-    constexpr int P = RasterCfg<TS>::P;
-    using L = Layout<TS, P>;
+    using L = Layout<TS, BW, P>;
     if (order) {
         hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, queue);
-        hipLaunchKernelGGL((k_raster_bwd_persistent<TS, P, DA>), dim3(persistent_blocks()), dim3(GS_WAVE),
-                           0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, queue, Tfin,
-                           nlast, dimg, dalpha, grad2d);
+        if (dalpha)
+            hipLaunchKernelGGL((k_raster_bwd_persistent<TS, BW, P, true>), dim3(persistent_blocks()),
+                               dim3(GS_WAVE), 0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order,
+                               queue, Tfin, nlast, dimg, dalpha, grad2d);
+        else
+            hipLaunchKernelGGL((k_raster_bwd_persistent<TS, BW, P, false>), dim3(persistent_blocks()),
+                               dim3(GS_WAVE), 0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order,
+                               queue, Tfin, nlast, dimg, dalpha, grad2d);
     } else {
-        hipLaunchKernelGGL((k_raster_bwd<TS, P, DA>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st,
-                           vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], Tfin, nlast, dimg, dalpha,
-                           grad2d);
+        if (dalpha)
+            hipLaunchKernelGGL((k_raster_bwd<TS, BW, P, true>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT),
+                               0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], Tfin, nlast, dimg,
+                               dalpha, grad2d);
+        else
+            hipLaunchKernelGGL((k_raster_bwd<TS, BW, P, false>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT),
+                               0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], Tfin, nlast, dimg,
+                               dalpha, grad2d);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_raster_fwd(int tile, const ViewTable& vt, const float* splats, const int* gids,
-                             const int2* ranges, long long N, const float* bg, const int* order,
-                             int* queue, float* img, float* Tout, int* lastout, int* visits,
+}  // namespace
+
+// Wave blocks available per tile edge (block width, pixels per lane); the
+// first entry of each list is the default.
+//   tile 8:  8x8 / 1
+//   tile 16: 8x8 / 1, 16x4 / 1, 16x16 / 4
+//   tile 32: 8x8 / 1, 16x16 / 4, 32x8 / 4
+bool raster_cfg_ok(int tile, int bw, int ppl)
+{
+    if (bw == 0 && ppl == 0) return tile == 8 || tile == 16 || tile == 32;
+    switch (tile) {
+    case 8: return bw == 8 && ppl == 1;
+    case 16: return (bw == 8 && ppl == 1) || (bw == 16 && ppl == 1) || (bw == 16 && ppl == 4);
+    case 32: return (bw == 8 && ppl == 1) || (bw == 16 && ppl == 4) || (bw == 32 && ppl == 4);
+    default: return false;
+    }
+}
+
+#define GS_FWD(TS, BW, P) \
+    return fwd_cfg<TS, BW, P>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st)
+
+hipError_t launch_raster_fwd(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
+                             const int* gids, const int2* ranges, long long N, const float* bg,
+                             const int* order, int* queue, float* img, float* Tout, int* lastout, int* visits,
                              hipStream_t st)
 {
     if (vt.total_tiles == 0) return hipSuccess;
+    if (bw == 0) { bw = 8; ppl = 1; }
     switch (tile) {
-    case 8: return fwd_ts<8>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st);
-    case 16: return fwd_ts<16>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st);
-    default: return fwd_ts<32>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st);
+    case 8: GS_FWD(8, 8, 1);
+    case 16:
+        if (bw == 16 && ppl == 4) GS_FWD(16, 16, 4);
+        if (bw == 16) GS_FWD(16, 16, 1);
+        GS_FWD(16, 8, 1);
+    default:
+        if (bw == 32) GS_FWD(32, 32, 4);
+        if (bw == 16) GS_FWD(32, 16, 4);
+        GS_FWD(32, 8, 1);
     }
 }
+#undef GS_FWD
 
-hipError_t launch_raster_bwd(int tile, const ViewTable& vt, const float* splats, const int* gids,
-                             const int2* ranges, long long N, const float* bg, const int* order,
-                             int* queue, const float* Tfin, const int* nlast, const float* dimg,
-                             const float* dalpha, float* grad2d, hipStream_t st)
+#define GS_BWD(TS, BW, P) \
+    return bwd_cfg<TS, BW, P>(vt, splats, gids, ranges, N, bg, order, queue, Tfin, nlast, dimg, dalpha, grad2d, st)
+
+hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
+                             const int* gids, const int2* ranges, long long N, const float* bg,
+                             const int* order, int* queue, const float* Tfin, const int* nlast,
+                             const float* dimg, const float* dalpha, float* grad2d, hipStream_t st)
 {
     if (vt.total_tiles == 0) return hipSuccess;
-    const bool da = dalpha != nullptr;
-#define GS_BWD(TS)                                                                                   \
-    return da ? bwd_ts<TS, true>(vt, splats, gids, ranges, N, bg, order, queue, Tfin, nlast, dimg,   \
-                                 dalpha, grad2d, st)                                                 \
-              : bwd_ts<TS, false>(vt, splats, gids, ranges, N, bg, order, queue, Tfin, nlast, dimg,  \
-                                  dalpha, grad2d, st)
+    if (bw == 0) { bw = 8; ppl = 1; }
     switch (tile) {
-    case 8: GS_BWD(8);
-    case 16: GS_BWD(16);
-    default: GS_BWD(32);
+    case 8: GS_BWD(8, 8, 1);
+    case 16:
+        if (bw == 16 && ppl == 4) GS_BWD(16, 16, 4);
+        if (bw == 16) GS_BWD(16, 16, 1);
+        GS_BWD(16, 8, 1);
+    default:
+        if (bw == 32) GS_BWD(32, 32, 4);
+        if (bw == 16) GS_BWD(32, 16, 4);
+        GS_BWD(32, 8, 1);
     }
-#undef GS_BWD
 }
+#undef GS_BWD
 
 }  // namespace gs

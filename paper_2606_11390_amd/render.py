@@ -24,7 +24,10 @@ from . import binding as B
 
 class Renderer:
     def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
-                 background=(0.0, 0.0, 0.0), persistent=False, device="cuda"):
+                 background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda"):
+        # wave pixel blocks (width, pixels per lane) of the forward and backward rasterisers
+        self.block = tuple(int(x) for x in block)
+        self.block_bwd = self.block if block_bwd is None else tuple(int(x) for x in block_bwd)
         self.n = int(n)
         self.deg = int(sh_degree)
         self.sizes = np.asarray(sizes, np.int32).reshape(-1, 2)
@@ -94,12 +97,13 @@ class Renderer:
     def raster_fwd(self):
         s, q = self._sched()
         B.rasterize_fwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
-                        self.background, s, q, self.images, self.T_final, self.n_contrib)
+                        self.background, s, q, self.images, self.T_final, self.n_contrib, block=self.block)
 
     def raster_bwd(self, d_images, d_alpha=None):
         s, q = self._sched()
         B.rasterize_bwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
-                        self.background, s, q, self.T_final, self.n_contrib, d_images, d_alpha, self.grad2d)
+                        self.background, s, q, self.T_final, self.n_contrib, d_images, d_alpha, self.grad2d,
+                        block=self.block_bwd)
 
     def project_bwd(self, P, cams, grads):
         B.project_bwd(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
@@ -218,3 +222,80 @@ def render(renderer, P, cams):
     """Differentiable rendering of all views: packed images [sum 3 H W]."""
     return _Render.apply(renderer, cams["viewmats"], cams["intrinsics"], P["means"], P["log_scales"],
                          P["quats"], P["opacity_logits"], P["sh"])
+
+
+# ------------------------------------------------------------------ autotune
+BLOCKS = {8: [(8, 1)], 16: [(8, 1), (16, 1), (16, 4)], 32: [(8, 1), (16, 4), (32, 4)]}
+
+
+def _time_ms(fn, steps):
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def autotune(P, cams, targets, sh_degree, sizes, tiles=(8, 16, 32), steps=5, cache_path=None, log=None):
+    """Pick the tile edge and wave block of the batched path by timing.
+
+    For every tile edge the wave blocks of the compositing forward and of its
+    backward are compared separately (they change no result bit), then the
+    whole graph-captured step is timed once per tile edge with its best blocks.  The
+    tile edge changes which Gaussians share a tile list and therefore the
+    rendered image (as in any tile-based rasteriser); callers that need a
+    fixed tile pass a single value in ``tiles``.  Returns a dict with the
+    chosen ``tile``, ``block`` (forward), ``block_bwd`` and the measured
+    milliseconds per candidate;
+    with ``cache_path`` the result is stored in a JSON file keyed by the GPU
+    name and the workload shape and reused."""
+    import json
+    import os
+    n = int(P["means"].shape[1])
+    key = f"{torch.cuda.get_device_name()}|n={n}|deg={sh_degree}|sizes={np.asarray(sizes).tolist()}|tiles={list(tiles)}"
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            return cache[key]
+    grads = zeros_like_params(P)
+    trials, best = {}, None
+    for tile in tiles:
+        r = Renderer(n, sh_degree, sizes, tile=tile, capacity=1 << 20, persistent=True)
+        r.fit_capacity(P, cams)
+        r.step(P, cams, targets, grads)
+        fwd_ms, bwd_ms = {}, {}
+        for blk in BLOCKS[tile]:
+            r.block = r.block_bwd = blk
+            r.raster_fwd()
+            fwd_ms[blk] = _time_ms(r.raster_fwd, steps)
+            r.raster_bwd(r.d_images)
+            bwd_ms[blk] = _time_ms(lambda: r.raster_bwd(r.d_images), steps)
+        r.block = min(fwd_ms, key=fwd_ms.get)
+        r.block_bwd = min(bwd_ms, key=bwd_ms.get)
+        r.raster_fwd()
+        r.capture(P, cams, targets, grads, warmup=1)
+        ms = _time_ms(r.replay, steps)
+        trials[f"tile{tile}"] = {"step_ms": ms, "fwd_ms": {f"{b[0]}x{b[1]}": v for b, v in fwd_ms.items()},
+                                 "bwd_ms": {f"{b[0]}x{b[1]}": v for b, v in bwd_ms.items()}}
+        if log:
+            log(f"autotune tile {tile}: fwd block {r.block} bwd block {r.block_bwd} step {ms:.3f} ms; fwd " +
+                ", ".join(f"{b}: {v:.3f}" for b, v in fwd_ms.items()) + "; bwd " +
+                ", ".join(f"{b}: {v:.3f}" for b, v in bwd_ms.items()))
+        if best is None or ms < best["step_ms"]:
+            best = {"tile": tile, "block": list(r.block), "block_bwd": list(r.block_bwd), "step_ms": ms}
+        del r
+        torch.cuda.empty_cache()
+    best["trials"] = trials
+    if cache_path:
+        cache[key] = best
+        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best

@@ -92,7 +92,7 @@ def gpu_bin_sort(arrs, sizes, tile, capacity):
     return host(it), host(ig), host(rg).reshape(T, 2), host(info)
 
 
-def gpu_raster_fwd(splats, gids, ranges, sizes, tile, bg=(0, 0, 0), persistent=False):
+def gpu_raster_fwd(splats, gids, ranges, sizes, tile, bg=(0, 0, 0), persistent=False, block=(0, 0)):
     V, N = splats.shape[:2]
     _, toff, poff = B.tile_grid(sizes, tile)
     P = int(poff[-1])
@@ -106,12 +106,12 @@ def gpu_raster_fwd(splats, gids, ranges, sizes, tile, bg=(0, 0, 0), persistent=F
         q = torch.zeros(1, dtype=torch.int32, device="cuda")
         B.tile_schedule(rg, int(toff[-1]), sched)
     B.rasterize_fwd(dev(splats.reshape(-1)), dev(np.asarray(gids, np.int32)), rg, N, sizes, tile, bg, sched, q,
-                    img, T, last)
+                    img, T, last, block=block)
     return host(img), host(T), host(last)
 
 
 def gpu_raster_bwd(splats, gids, ranges, sizes, tile, T_final, last, d_img, d_alpha=None, bg=(0, 0, 0),
-                   persistent=False):
+                   persistent=False, block=(0, 0)):
     V, N = splats.shape[:2]
     _, toff, poff = B.tile_grid(sizes, tile)
     g = torch.zeros(V * N * 9, device="cuda")
@@ -123,7 +123,7 @@ def gpu_raster_bwd(splats, gids, ranges, sizes, tile, T_final, last, d_img, d_al
         B.tile_schedule(rg, int(toff[-1]), sched)
     B.rasterize_bwd(dev(splats.reshape(-1)), dev(np.asarray(gids, np.int32)), rg, N, sizes, tile, bg, sched, q,
                     dev(T_final, F32), dev(last, np.int32), dev(d_img, F32),
-                    None if d_alpha is None else dev(d_alpha, F32), g)
+                    None if d_alpha is None else dev(d_alpha, F32), g, block=block)
     return host(g).reshape(V, N, 9)
 
 

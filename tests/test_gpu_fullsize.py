@@ -1,0 +1,130 @@
+"""Parity at the benchmark's full size, in the launch configuration it times.
+
+Workload: the 5M-Gaussian, SH degree 3, 3840x2160 scene of ``bench.py``,
+persistent (queue-scheduled) rasterisers.  Each stage gets the oracle's own
+float32 inputs (no GPU output is fed to the oracle):
+
+* projection: every Gaussian's record, within the projection tolerances;
+* binning: all intersections bit-exact (keys, Gaussian ids, tile ranges);
+* compositing forward: every pixel within 1e-5 (ambiguous pixels excluded);
+* compositing backward and projection backward: 2-D and parameter
+  gradients within 1e-4.
+
+The FP64 oracle needs on the order of a minute of host time for this.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_11390_amd import scenes
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+TILE = 16
+PROJ_MARGIN = 2e-6
+PIX_MARGIN = 1e-4
+
+
+@functools.lru_cache(maxsize=None)
+def _stage():
+    G.say("[fullsize] generating the 5M-Gaussian 4K scene")
+    s = scenes.uhd()
+    P, projs, arrs = G.oracle_views(s, TILE)
+    keys, vals, ranges, offs = G.oracle_binning(arrs, s.sizes, TILE)
+    G.say(f"[fullsize] oracle projection + binning done: visible {int(projs[0]['visible'].sum())}, M {len(keys)}")
+    return s, P, projs, arrs, keys, vals, ranges
+
+
+@functools.lru_cache(maxsize=None)
+def _fwd():
+    s, P, projs, arrs, keys, vals, ranges = _stage()
+    W, H = (int(x) for x in s.sizes[0])
+    sp = oracle.from_record(arrs["splats"][0])
+    f = oracle.raster_fwd(W, H, TILE, ranges, vals, sp)
+    G.say(f"[fullsize] oracle forward done: visits {int(f['visits'].sum())}")
+    return sp, f
+
+
+def test_fullsize_projection():
+    s, P, projs, arrs, *_ = _stage()
+    g = G.gpu_project(s, TILE)
+    pr = projs[0]
+    amb = pr["margin"] < PROJ_MARGIN
+    ok = ~amb
+    vis = pr["visible"].astype(bool)
+    G.say(f"[fullsize] projection: ambiguous {amb.sum()} of {s.n}")
+    assert amb.sum() <= 2e-3 * s.n
+    np.testing.assert_array_equal((g["flags"][0] & 1).astype(bool)[ok], vis[ok])
+    np.testing.assert_array_equal(g["radii"][0][ok], pr["radii"].T[ok])
+    np.testing.assert_array_equal(g["tiles"][0][ok], pr["tiles"][ok])
+    m = ok & vis
+    rec = g["splats"][0][m].astype(np.float64)
+    fac = oracle.factor(pr["conic"])[:, m].T
+    e_uv = np.max(np.abs(rec[:, :2] - np.stack([pr["u"][m], pr["v"][m]], 1))) / 3840
+    e_fac = np.max(np.abs(rec[:, 2:5] - fac) / np.max(np.abs(fac), axis=1, keepdims=True))
+    e_rgb = np.max(np.abs(rec[:, 6:9] - pr["rgb"][:, m].T))
+    G.say(f"  err uv {e_uv:.2e} factor {e_fac:.2e} rgb {e_rgb:.2e}")
+    assert e_uv <= 1e-5 and e_rgb <= 1e-5 and e_fac <= 1e-3
+
+
+def test_fullsize_binning_bit_exact():
+    s, P, projs, arrs, keys, vals, ranges = _stage()
+    M = len(keys)
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, TILE, M + 1024)
+    G.say(f"[fullsize] binning: M {M}, GPU info {info[:3]}")
+    assert info[1] == M and info[2] == 0
+    np.testing.assert_array_equal(it[:M], (keys >> np.uint64(32)).astype(np.int32))
+    np.testing.assert_array_equal(ig[:M], vals)
+    np.testing.assert_array_equal(rg, ranges)
+
+
+def test_fullsize_raster_forward_persistent():
+    s, P, projs, arrs, keys, vals, ranges = _stage()
+    sp, f = _fwd()
+    img, T, last = G.gpu_raster_fwd(arrs["splats"], vals, ranges, s.sizes, TILE, persistent=True)
+    H, W = f["T"].shape
+    img = img.reshape(3, H, W)
+    T = T.reshape(H, W)
+    last = last.reshape(H, W)
+    amb = f["margin"] < PIX_MARGIN
+    ok = ~amb
+    e_img = G.rel_max(img[:, ok], f["img"][:, ok])
+    e_T = G.rel_max(T[ok], f["T"][ok])
+    G.say(f"[fullsize] forward: ambiguous px {amb.sum()}, img {e_img:.2e}, T {e_T:.2e}")
+    assert amb.sum() <= 1e-3 * amb.size
+    assert e_img <= 1e-5 and e_T <= 1e-5
+    np.testing.assert_array_equal(last[ok], f["last"][ok])
+
+
+def test_fullsize_backward_persistent():
+    s, P, projs, arrs, keys, vals, ranges = _stage()
+    sp, f = _fwd()
+    H, W = f["T"].shape
+    rng = np.random.default_rng(5)
+    amb = f["margin"] < PIX_MARGIN
+    dimg = rng.standard_normal((3, H, W)).astype(np.float32)
+    dimg[:, amb] = 0
+    g = G.gpu_raster_bwd(arrs["splats"], vals, ranges, s.sizes, TILE, f["T"].astype(np.float32),
+                         f["last"], dimg, persistent=True)[0]
+    o = oracle.raster_bwd(W, H, TILE, ranges, vals, sp, dimg.astype(np.float64))
+    ref = np.stack([o["u"], o["v"], o["conic"][0], o["conic"][1], o["conic"][2], o["sigma"],
+                    o["rgb"][0], o["rgb"][1], o["rgb"][2]], axis=1)
+    errs = [G.rel_l2(g[:, j], ref[:, j]) for j in range(9)]
+    G.say("[fullsize] raster backward rel L2 " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) <= 1e-4
+    # projection backward driven by the oracle's own 2-D gradients
+    pr = projs[0]
+    use = (pr["visible"] > 0) & (pr["margin"] >= PROJ_MARGIN)
+    g2 = np.where(use[:, None], ref, 0.0).astype(np.float32)
+    gp = G.gpu_project_bwd(s, arrs["flags"], g2[None])
+    up = dict(u=g2[:, 0].astype(np.float64), v=g2[:, 1].astype(np.float64), conic=g2[:, 2:5].T.astype(np.float64),
+              sigma=g2[:, 5].astype(np.float64), rgb=g2[:, 6:9].T.astype(np.float64))
+    acc = oracle.project_bwd(P, s.viewmats[0], s.intrinsics[0], W, H, up)
+    perrs = {gn: G.rel_l2(gp[gn], acc[on]) for on, gn in (("means", "means"), ("log_scales", "log_scales"),
+                                                           ("quats", "quats"), ("opac", "opacity_logits"),
+                                                           ("sh", "sh"))}
+    G.say("[fullsize] projection backward rel L2 " + " ".join(f"{k} {e:.1e}" for k, e in perrs.items()))
+    assert max(perrs.values()) <= 1e-4

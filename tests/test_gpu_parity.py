@@ -95,10 +95,11 @@ def test_project_parity(name, tile):
         with np.errstate(divide="ignore"):
             full[:, 5] = np.log2(pr["sigma"][m])
         full[:, 6:9] = pr["rgb"][:, m].T
-        full[:, 9], full[:, 10] = pr["sigma"][m], pr["depth"][m]
+        full[:, 9] = pr["sigma"][m]
         scale = max(W, H)
         e_uv = np.max(np.abs(rec[:, :2] - full[:, :2])) / scale if m.any() else 0
-        e_z = np.max(np.abs(rec[:, 10] - full[:, 10]) / np.abs(full[:, 10])) if m.any() else 0
+        zg = g["depths"][v][m].astype(np.float64)
+        e_z = np.max(np.abs(zg - pr["depth"][m]) / np.abs(pr["depth"][m])) if m.any() else 0
         fn = np.max(np.abs(full[:, 2:5]), axis=1, keepdims=True)
         e_fac = np.abs(rec[:, 2:5] - full[:, 2:5]) / fn
         e_rgb = np.max(np.abs(rec[:, 6:9] - full[:, 6:9]) / np.maximum(1.0, np.abs(full[:, 6:9]))) if m.any() else 0
@@ -107,6 +108,12 @@ def test_project_parity(name, tile):
         G.say(f"  view {v}: visible {vis.sum()} ambiguous {amb.sum()} err uv {e_uv:.2e} z {e_z:.2e} "
               f"factor max {e_fac.max() if m.any() else 0:.2e} p99.9 {np.quantile(e_fac, 0.999) if m.any() else 0:.2e} "
               f"rgb {e_rgb:.2e} sigma {e_sig:.2e} log2sigma {e_ls:.2e}")
+        # the alpha >= 1/255 box is conservative: it contains the oracle's exact box
+        ex, ey = oracle.alpha_extent(pr)
+        xl, xh = oracle.unpack_box(g["splats"][v][m][:, 10])
+        yl, yh = oracle.unpack_box(g["splats"][v][m][:, 11])
+        assert np.all(xl <= np.ceil(pr["u"][m] - ex[m] - 0.5)) and np.all(xh >= np.floor(pr["u"][m] + ex[m] - 0.5))
+        assert np.all(yl <= np.ceil(pr["v"][m] - ey[m] - 0.5)) and np.all(yh >= np.floor(pr["v"][m] + ey[m] - 0.5))
         assert e_uv <= IMG_TOL and e_z <= IMG_TOL and e_rgb <= IMG_TOL
         assert e_sig <= IMG_TOL and e_ls <= IMG_TOL
         assert (e_fac.max() if m.any() else 0) <= 1e-3
@@ -268,3 +275,33 @@ def test_loss_parity():
     L, (dref,) = oracle.l2_loss([img], [tgt])
     assert G.host(loss)[0] == pytest.approx(L, rel=1e-6)
     assert G.rel_max(G.host(d), dref) <= 1e-6
+
+
+BLOCKS = {8: [(8, 1)], 16: [(8, 1), (16, 1), (16, 4)], 32: [(8, 1), (16, 4), (32, 4)]}
+
+
+@pytest.mark.parametrize("name,tile", [("ragged", 16), ("multi", 16), ("ragged", 32), ("multi", 32)])
+def test_raster_blocks_change_only_speed(name, tile):
+    """Every wave-block configuration renders bit-identical images and the
+    same gradients (up to atomic summation order)."""
+    s = scene(name)
+    _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
+    G.say(f"[blocks] {name} tile={tile}")
+    ref = None
+    for blk in BLOCKS[tile]:
+        for persistent in (False, True):
+            img, T, last = G.gpu_raster_fwd(arrs["splats"], vals, ranges, s.sizes, tile, (0.1, 0.2, 0.3),
+                                            persistent, blk)
+            rng = np.random.default_rng(1)
+            dimg = rng.standard_normal(img.shape).astype(np.float32)
+            g = G.gpu_raster_bwd(arrs["splats"], vals, ranges, s.sizes, tile, T, last, dimg, None, (0.1, 0.2, 0.3),
+                                 persistent, blk)
+            if ref is None:
+                ref = (img, T, last, g)
+                continue
+            np.testing.assert_array_equal(img, ref[0])
+            np.testing.assert_array_equal(T, ref[1])
+            np.testing.assert_array_equal(last, ref[2])
+            e = G.rel_l2(g, ref[3])
+            G.say(f"  block {blk} persistent {persistent}: grad2d rel L2 vs first {e:.1e}")
+            assert e <= 1e-6

@@ -541,3 +541,27 @@ def test_record_round_trip_and_factor_definition():
     assert np.all(m[0] > 0) and np.all(m[2] > 0)
     np.testing.assert_allclose(back["conic"][:, vis], pr["conic"][:, vis], rtol=2e-6, atol=1e-9)
     np.testing.assert_allclose(back["u"][vis], pr["u"][vis], rtol=1e-7)
+
+
+def test_alpha_box_contains_every_pixel_with_alpha_above_threshold():
+    # brute force over a pixel window around each splat: every pixel whose
+    # FP64 alpha reaches 1/255 lies inside the record's packed box
+    s, P, pr, keys, vals, ranges = _tiny_setup(seed=18, n=200, W=64, H=48, f=50.0)
+    rec = oracle.to_record(pr)
+    x_lo, x_hi = oracle.unpack_box(rec[:, 10])
+    y_lo, y_hi = oracle.unpack_box(rec[:, 11])
+    inside = 0
+    for g in np.nonzero(pr["visible"])[0]:
+        A, B, C = pr["conic"][:, g]
+        u, v = pr["u"][g], pr["v"][g]
+        ii, jj = np.meshgrid(np.arange(int(u) - 40, int(u) + 41), np.arange(int(v) - 40, int(v) + 41))
+        dx, dy = u - (ii + 0.5), v - (jj + 0.5)
+        a = pr["sigma"][g] * np.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy)
+        hit = a >= oracle.ALPHA_MIN
+        assert np.all(ii[hit] >= x_lo[g]) and np.all(ii[hit] <= x_hi[g])
+        assert np.all(jj[hit] >= y_lo[g]) and np.all(jj[hit] <= y_hi[g])
+        inside += hit.sum()
+        # and the box is tight to within the padding
+        if hit.any():
+            assert x_hi[g] - ii[hit].max() <= 3 and ii[hit].min() - x_lo[g] <= 3
+    assert inside > 0
