@@ -74,6 +74,7 @@ extern "C" {
 #define GS_MAX_VIEWS 64
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD_FLOATS 9
+#define GS_ADAM_MAX_TENSORS 8
 
 /* flags byte per (view, Gaussian) */
 #define GS_FLAG_VISIBLE 0x1u
@@ -283,6 +284,50 @@ size_t gs_loss_workspace_size(int64_t n_elems);
  */
 int gs_loss_l2(const float* images, const float* targets, int64_t n_elems, float* loss,
                float* d_images, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * gs_adam - fused Adam update of up to GS_ADAM_MAX_TENSORS parameter tensors
+ * (paper Section 3.2: the backend's fused Adam; the rule is Kingma and Ba
+ * 2015 with bias correction, as torch.optim.Adam without weight decay):
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *   p -= lr_k / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps),
+ * with t = *step + 1.  params, grads, exp_avg, exp_avg_sq are HOST arrays of
+ * n_tensors DEVICE pointers (16-byte aligned, numel[k] float32 each, host
+ * array); lrs is a host array of per-tensor learning rates.  step (device
+ * int32) is read by the update and then incremented on the stream, so a
+ * captured graph replays consecutive steps.
+ */
+int gs_adam(int n_tensors, float* const* params, const float* const* grads, float* const* exp_avg,
+            float* const* exp_avg_sq, const int64_t* numel, const float* lrs, float beta1, float beta2,
+            float eps, int32_t* step, void* stream);
+
+/*
+ * gs_morton_workspace_size - bytes of device workspace gs_morton_order needs.
+ */
+size_t gs_morton_workspace_size(int64_t n);
+
+/*
+ * gs_morton_order - 3-D Morton order of the Gaussians (paper Section 5.2:
+ * the Gaussians are Morton-sorted in 3-D during densification to improve the
+ * locality of rasterisation).  Each mean is quantised per axis to a 10-bit
+ * cell c_k = clamp(floor((mu_k - origin_k) * inv_cell_k), 0, 1023), computed
+ * in float32 as one subtraction then one multiplication (non-finite values
+ * land in cell 0); the 30-bit code has bit 3b + k equal to bit b of c_k
+ * (x: k = 0, y: 1, z: 2).  order[i] (int32, [N]) is the index of the Gaussian
+ * with the i-th smallest code, equal codes in index order (stable).
+ * origin, inv_cell are host float[3]; means is the planar [3][N] array.
+ */
+int gs_morton_order(const float* means, int64_t n, const float* origin, const float* inv_cell, void* workspace,
+                    size_t workspace_bytes, int32_t* order, void* stream);
+
+/*
+ * gs_gather_columns - dst[c][i] = src[c][order[i]] for a planar [C][N]
+ * float32 array: applies a permutation such as the Morton order to a
+ * parameter (or gradient, or optimiser state) tensor.  src and dst must not
+ * overlap.
+ */
+int gs_gather_columns(const float* src, int channels, int64_t n, const int32_t* order, float* dst,
+                      void* stream);
 
 #ifdef __cplusplus
 }

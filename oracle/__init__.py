@@ -399,3 +399,46 @@ def step(scene, P=None, tile=16, near=0.01, far=1e10, eps2d=0.3, bg=(0.0, 0.0, 0
                               tile, acc)
         out["grads"] = acc
     return out
+
+
+# --------------------------------------------------------------------------
+# optimiser (the paper's Section 3.2 fused Adam; Kingma and Ba 2015)
+# --------------------------------------------------------------------------
+def adam(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step at step number t (1-based), FP64, bias-corrected:
+    returns the new (p, m, v)."""
+    p, g, m, v = _d(p), _d(g), _d(m), _d(v)
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# 3-D Morton order (the paper's Section 5.2 locality pass)
+# --------------------------------------------------------------------------
+def morton_cells(means, origin, inv_cell):
+    """10-bit cell per axis: clamp(floor((mu - origin) * inv_cell), 0, 1023),
+    float32 subtraction then multiplication (non-finite -> 0)."""
+    m = np.asarray(means, np.float32)
+    o = np.asarray(origin, np.float32)[:, None]
+    c = np.asarray(inv_cell, np.float32)[:, None]
+    with np.errstate(invalid="ignore", over="ignore"):
+        t = np.floor((m - o) * c)
+    t = np.where(np.isfinite(t), t, 0.0)
+    return np.clip(t, 0, 1023).astype(np.int64)
+
+
+def morton_codes(means, origin, inv_cell):
+    """30-bit codes: bit 3b + k is bit b of axis k's cell (plain bit loop)."""
+    cells = morton_cells(means, origin, inv_cell)
+    code = np.zeros(cells.shape[1], np.int64)
+    for b in range(10):
+        for k in range(3):
+            code |= ((cells[k] >> b) & 1) << (3 * b + k)
+    return code
+
+
+def morton_order(means, origin, inv_cell):
+    return np.argsort(morton_codes(means, origin, inv_cell), kind="stable").astype(np.int32)

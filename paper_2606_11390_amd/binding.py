@@ -48,6 +48,10 @@ _SIGS = {
     "gs_project_bwd": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
                               _p, _p, _p, _p]),
     "gs_raster_visits": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p]),
+    "gs_adam": (_int, [_int, _p, _p, _p, _p, _p, _p, _f, _f, _f, _p, _p]),
+    "gs_morton_workspace_size": (_sz, [_i64]),
+    "gs_morton_order": (_int, [_p, _i64, _p, _p, _p, _sz, _p, _p]),
+    "gs_gather_columns": (_int, [_p, _int, _i64, _p, _p, _p]),
     "gs_loss_workspace_size": (_sz, [_i64]),
     "gs_loss_l2": (_int, [_p, _p, _i64, _p, _p, _p, _sz, _p]),
 }
@@ -225,3 +229,39 @@ def raster_visits(splats, isect_gid, tile_ranges, n, sizes, tile, images, T_fina
                                 _ptr(images, F32, "images"), _ptr(T_final, F32, "T_final"),
                                 _ptr(n_contrib, I32, "n_contrib"), _ptr(visits, I32, "visits"), _stream())
     _check(rc, "gs_raster_visits")
+
+
+def adam(params, grads, exp_avg, exp_avg_sq, lrs, beta1, beta2, eps, step):
+    """Fused Adam over matching lists of tensors (one launch)."""
+    k = len(params)
+    P = (ctypes.c_void_p * k)(*[_ptr(t, F32, "param") for t in params])
+    G = (ctypes.c_void_p * k)(*[_ptr(t, F32, "grad") for t in grads])
+    M = (ctypes.c_void_p * k)(*[_ptr(t, F32, "exp_avg") for t in exp_avg])
+    V = (ctypes.c_void_p * k)(*[_ptr(t, F32, "exp_avg_sq") for t in exp_avg_sq])
+    n = (ctypes.c_int64 * k)(*[t.numel() for t in params])
+    lr = (ctypes.c_float * k)(*[float(x) for x in lrs])
+    rc = lib().gs_adam(k, P, G, M, V, n, lr, float(beta1), float(beta2), float(eps), _ptr(step, I32, "step"),
+                       _stream())
+    _check(rc, "gs_adam")
+
+
+def morton_order(means, origin, inv_cell, workspace, order):
+    n = means.shape[1]
+    o, op = _host_f32(origin)
+    c, cp = _host_f32(inv_cell)
+    rc = lib().gs_morton_order(_ptr(means, F32, "means"), n, op, cp, _ptr(workspace, U8, "workspace"),
+                               workspace.numel(), _ptr(order, I32, "order"), _stream())
+    _check(rc, "gs_morton_order")
+
+
+def morton_workspace_size(n):
+    return int(lib().gs_morton_workspace_size(n))
+
+
+def gather_columns(src, order, dst):
+    """dst[..., i] = src[..., order[i]] for planar [C][N] (or [N]) tensors."""
+    n = src.shape[-1]
+    C = src.numel() // max(n, 1)
+    rc = lib().gs_gather_columns(_ptr(src, F32, "src"), C, n, _ptr(order, I32, "order"), _ptr(dst, F32, "dst"),
+                                 _stream())
+    _check(rc, "gs_gather_columns")

@@ -36,7 +36,7 @@ constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;     // keys per chunk
 constexpr int RS_WAVE_SPAN = GS_WAVE * RS_ITEMS;     // keys per wave per chunk
 constexpr int RS_MAX_BLOCKS = 1024;
 
-enum Source { SRC_PAIRS = 0, SRC_PROJ = 1, SRC_TILE_LEN = 2 };
+enum Source { SRC_PAIRS = 0, SRC_PROJ = 1, SRC_TILE_LEN = 2, SRC_MORTON = 3 };
 
 struct SortIO {
     const uint32_t* keys_in;   // SRC_PAIRS
@@ -44,6 +44,8 @@ struct SortIO {
     const float* depths;       // SRC_PROJ
     const int* tiles;
     const int2* ranges;        // SRC_TILE_LEN
+    const float* means;        // SRC_MORTON: planar [3][n]
+    float org[3], inv_cell[3];
     uint32_t* keys_out;
     uint32_t* vals_out;
     uint32_t n_const;          // element count when n_dev is NULL
@@ -64,6 +66,34 @@ __device__ __forceinline__ void block_span(uint32_t n, int nb, int b, uint32_t& 
     end = (uint32_t)min((unsigned long long)n, b0 + per);
 }
 
+// 10-bit cell of one coordinate: floor((x - org) * inv_cell) clamped to
+// [0, 1023], float32 without contraction (a non-finite x lands in cell 0)
+__device__ __forceinline__ uint32_t cell10(float x, float org, float inv)
+{
+#pragma clang fp contract(off)
+    const float t = floorf((x - org) * inv);
+    return t >= 1023.0f ? 1023u : (t >= 0.0f ? (uint32_t)t : 0u);
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x)
+{
+    // bit b of x moves to bit 3b
+    x &= 0x3FFu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// 30-bit Morton code: bit 3b + k holds bit b of axis k's cell (x: k = 0)
+__device__ __forceinline__ uint32_t morton30(const float* __restrict__ means, uint32_t n, uint32_t i,
+                                             const float* org, const float* inv)
+{
+    return spread10(cell10(means[i], org[0], inv[0])) | (spread10(cell10(means[n + i], org[1], inv[1])) << 1) |
+           (spread10(cell10(means[2 * (size_t)n + i], org[2], inv[2])) << 2);
+}
+
 template <int SRC>
 __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t end, uint32_t& k,
                                         uint32_t& v)
@@ -76,6 +106,10 @@ __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t e
     } else if (SRC == SRC_PROJ) {
         if (io.tiles[i] <= 0) return false;
         k = __float_as_uint(io.depths[i]);
+        v = i;
+        return true;
+    } else if (SRC == SRC_MORTON) {
+        k = morton30(io.means, io.n_const, i, io.org, io.inv_cell);
         v = i;
         return true;
     } else {
@@ -599,6 +633,66 @@ hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, value, n);
+    return hipGetLastError();
+}
+
+size_t morton_workspace_size(long long n)
+{
+    const size_t t = (size_t)n;
+    return 3 * align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS) + align256(4 * 256);
+}
+
+// order[i] = index of the Gaussian with the i-th smallest Morton code (stable)
+hipError_t launch_morton_order(const float* means, long long n, const float* org, const float* inv_cell,
+                               void* workspace, int* order, hipStream_t st)
+{
+    char* base = (char*)workspace;
+    const size_t t = (size_t)n;
+    uint32_t* ka = (uint32_t*)base;
+    uint32_t* kb = (uint32_t*)(base + align256(4 * t));
+    uint32_t* va = (uint32_t*)(base + 2 * align256(4 * t));
+    uint32_t* hist = (uint32_t*)(base + 3 * align256(4 * t));
+    uint32_t* dtot = (uint32_t*)(base + 3 * align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS));
+    const int nb = sort_blocks(t);
+    // pass 0 computes the codes from the means; passes 1..3 sort the rest of
+    // the 30 bits; the last pass writes the indices into `order`
+    SortIO a{};
+    a.means = means;
+    for (int k = 0; k < 3; k++) { a.org[k] = org[k]; a.inv_cell[k] = inv_cell[k]; }
+    a.keys_out = ka;
+    a.vals_out = va;
+    a.n_const = (uint32_t)t;
+    hipError_t e;
+    if ((e = radix_pass<SRC_MORTON>(a, nb, 0, 8, hist, dtot, nullptr, st)) != hipSuccess) return e;
+    uint32_t *ki = ka, *vi = va, *ko = kb, *vo = (uint32_t*)order;
+    for (int pass = 1; pass < 4; pass++) {
+        SortIO p{};
+        p.keys_in = ki; p.vals_in = vi; p.keys_out = ko; p.vals_out = vo;
+        p.n_const = (uint32_t)t;
+        if ((e = radix_pass<SRC_PAIRS>(p, nb, 8 * pass, pass == 3 ? 6 : 8, hist, dtot, nullptr, st)) != hipSuccess)
+            return e;
+        uint32_t* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+    }
+    // after passes 1 (a->b, vals va->order), 2 (b->a, order->va), 3 (a->b, va->order)
+    return hipSuccess;
+}
+
+namespace {
+__global__ void k_gather_columns(const float* __restrict__ src, int C, long long n, const int* __restrict__ order,
+                                 float* __restrict__ dst)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long j = order[i];
+    for (int c = 0; c < C; c++) dst[c * n + i] = src[c * n + j];
+}
+}  // namespace
+
+hipError_t launch_gather_columns(const float* src, int C, long long n, const int* order, float* dst, hipStream_t st)
+{
+    if (n == 0 || C == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_columns, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, C, n, order, dst);
     return hipGetLastError();
 }
 

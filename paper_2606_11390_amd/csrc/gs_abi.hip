@@ -35,6 +35,14 @@ hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, con
                              const float* dimg, const float* dalpha, float* grad2d, hipStream_t st);
 size_t loss_workspace_size(long long n);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
+size_t morton_workspace_size(long long n);
+hipError_t launch_morton_order(const float* means, long long n, const float* org, const float* inv_cell,
+                               void* workspace, int* order, hipStream_t st);
+hipError_t launch_gather_columns(const float* src, int C, long long n, const int* order, float* dst,
+                                 hipStream_t st);
+hipError_t launch_adam(int n_tensors, float* const* params, const float* const* grads, float* const* exp_avg,
+                       float* const* exp_avg_sq, const int64_t* numel, const float* lrs, float beta1,
+                       float beta2, float eps, int* step_dev, hipStream_t st);
 hipError_t launch_loss_l2(const float* img, const float* tgt, long long n, float* loss, float* dimg,
                           void* ws, hipStream_t st);
 }  // namespace gs
@@ -257,6 +265,49 @@ int gs_loss_l2(const float* images, const float* targets, int64_t n_elems, float
     if (n_elems > 0 && (!images || !targets || !d_images)) return GS_ERR_ARG;
     if (workspace_bytes < gs::loss_workspace_size(n_elems)) return GS_ERR_WORKSPACE;
     return status(gs::launch_loss_l2(images, targets, n_elems, loss, d_images, workspace, as_stream(stream)));
+}
+
+int gs_adam(int n_tensors, float* const* params, const float* const* grads, float* const* exp_avg,
+            float* const* exp_avg_sq, const int64_t* numel, const float* lrs, float beta1, float beta2,
+            float eps, int32_t* step, void* stream)
+{
+    if (n_tensors < 1 || n_tensors > GS_ADAM_MAX_TENSORS || !params || !grads || !exp_avg || !exp_avg_sq ||
+        !numel || !lrs || !step)
+        return GS_ERR_ARG;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) return GS_ERR_ARG;
+    for (int k = 0; k < n_tensors; k++) {
+        if (numel[k] < 0 || !std::isfinite(lrs[k])) return GS_ERR_ARG;
+        if (numel[k] > 0 && (!params[k] || !grads[k] || !exp_avg[k] || !exp_avg_sq[k])) return GS_ERR_ARG;
+        if (numel[k] > 0 && (!aligned16(params[k]) || !aligned16(grads[k]) || !aligned16(exp_avg[k]) ||
+                             !aligned16(exp_avg_sq[k])))
+            return GS_ERR_ARG;
+    }
+    return status(gs::launch_adam(n_tensors, params, grads, exp_avg, exp_avg_sq, numel, lrs, beta1, beta2, eps, step,
+                                  as_stream(stream)));
+}
+
+size_t gs_morton_workspace_size(int64_t n)
+{
+    if (n < 1 || n > 0x7FFFFFFFll) return 0;
+    return gs::morton_workspace_size(n);
+}
+
+int gs_morton_order(const float* means, int64_t n, const float* origin, const float* inv_cell, void* workspace,
+                    size_t workspace_bytes, int32_t* order, void* stream)
+{
+    if (n < 1 || n > 0x7FFFFFFFll || !means || !origin || !inv_cell || !workspace || !order) return GS_ERR_ARG;
+    for (int k = 0; k < 3; k++)
+        if (!std::isfinite(origin[k]) || !std::isfinite(inv_cell[k])) return GS_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return GS_ERR_ARG;
+    if (workspace_bytes < gs::morton_workspace_size(n)) return GS_ERR_WORKSPACE;
+    return status(gs::launch_morton_order(means, n, origin, inv_cell, workspace, order, as_stream(stream)));
+}
+
+int gs_gather_columns(const float* src, int channels, int64_t n, const int32_t* order, float* dst, void* stream)
+{
+    if (channels < 0 || n < 0 || n > 0x7FFFFFFFll) return GS_ERR_ARG;
+    if (channels > 0 && n > 0 && (!src || !order || !dst || src == dst)) return GS_ERR_ARG;
+    return status(gs::launch_gather_columns(src, channels, n, order, dst, as_stream(stream)));
 }
 
 }  // extern "C"

@@ -305,3 +305,63 @@ def test_raster_blocks_change_only_speed(name, tile):
             e = G.rel_l2(g, ref[3])
             G.say(f"  block {blk} persistent {persistent}: grad2d rel L2 vs first {e:.1e}")
             assert e <= 1e-6
+
+
+def test_adam_parity_over_steps_and_graph_replay():
+    """Fused Adam against the FP64 oracle over several steps, on tensors with
+    ragged lengths (vector body + scalar tail), and replayed from a graph."""
+    import torch
+    from paper_2606_11390_amd import binding as B
+    rng = np.random.default_rng(20)
+    sizes = [3 * 1001, 4 * 1001, 1001, 48 * 1001 + 3, 7]
+    lrs = [1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3]
+    p0 = [rng.standard_normal(n).astype(np.float32) for n in sizes]
+    gs = [[rng.standard_normal(n).astype(np.float32) for n in sizes] for _ in range(4)]
+    P = [G.dev(x.copy()) for x in p0]
+    M = [torch.zeros(n, device="cuda") for n in sizes]
+    V = [torch.zeros(n, device="cuda") for n in sizes]
+    Gd = [torch.zeros(n, device="cuda") for n in sizes]
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ref = [(x.astype(np.float64), np.zeros(len(x)), np.zeros(len(x))) for x in p0]
+    graph = None
+    for k in range(4):
+        for d, g in zip(Gd, gs[k]):
+            d.copy_(torch.from_numpy(g))
+        if k < 2:
+            B.adam(P, Gd, M, V, lrs, 0.9, 0.999, 1e-15, step)
+        else:
+            if graph is None:
+                graph = torch.cuda.CUDAGraph()
+                s = torch.cuda.Stream()
+                s.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.graph(graph, stream=s):
+                    B.adam(P, Gd, M, V, lrs, 0.9, 0.999, 1e-15, step)
+            graph.replay()
+        ref = [oracle.adam(p, g, m, v, k + 1, lr, 0.9, 0.999, 1e-15) for (p, m, v), g, lr in zip(ref, gs[k], lrs)]
+        for i in range(len(sizes)):
+            e = G.rel_max(G.host(P[i]) - p0[i], ref[i][0] - p0[i])
+            assert e <= 1e-5, (k, i, e)
+    assert int(G.host(step)[0]) == 4
+
+
+@pytest.mark.parametrize("n", [1, 1000, 200_000])
+def test_morton_order_bit_exact_and_gather(n):
+    import torch
+    from paper_2606_11390_amd import binding as B
+    s = scenes.hd(seed=6, n_gaussians=max(n, 1))
+    means = s.means[:, :n].copy()
+    if n > 1:   # duplicate every other Gaussian: equal codes must keep index order
+        h = n // 2
+        means[:, 1:2 * h:2] = means[:, 0:2 * h:2]
+    lo, hi = means.min(axis=1), means.max(axis=1)
+    org = lo.astype(np.float32)
+    inv = (1024.0 / np.maximum(hi - lo, 1e-6)).astype(np.float32)
+    ws = torch.empty(B.morton_workspace_size(n), dtype=torch.uint8, device="cuda")
+    order = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    md = G.dev(means)
+    B.morton_order(md, org, inv, ws, order)
+    np.testing.assert_array_equal(G.host(order), oracle.morton_order(means, org, inv))
+    sh = G.dev(s.sh[:, :, :n].copy())
+    out = torch.empty_like(sh)
+    B.gather_columns(sh, order, out)
+    np.testing.assert_array_equal(G.host(out), s.sh[:, :, :n][:, :, G.host(order)])

@@ -565,3 +565,45 @@ def test_alpha_box_contains_every_pixel_with_alpha_above_threshold():
         if hit.any():
             assert x_hi[g] - ii[hit].max() <= 3 and ii[hit].min() - x_lo[g] <= 3
     assert inside > 0
+
+
+def test_adam_matches_torch_optim_adam():
+    # library pin: torch.optim.Adam (CPU, float64) over several steps
+    import torch
+    rng = np.random.default_rng(19)
+    p0 = rng.standard_normal(257)
+    grads = [rng.standard_normal(257) for _ in range(5)]
+    t = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([t], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(257), np.zeros(257)
+    for k, g in enumerate(grads, start=1):
+        t.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = oracle.adam(p, g, m, v, k, 3e-3, 0.9, 0.999, 1e-8)
+        np.testing.assert_allclose(p, t.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_morton_codes_interleave_and_visit_octants_contiguously():
+    # decoding the interleaved bits gives back the cells
+    rng = np.random.default_rng(21)
+    means = rng.uniform(-5, 5, (3, 500)).astype(np.float32)
+    org, inv = np.array([-5, -5, -5], np.float32), np.array([102.4, 102.4, 102.4], np.float32)
+    cells = oracle.morton_cells(means, org, inv)
+    codes = oracle.morton_codes(means, org, inv)
+    for k in range(3):
+        dec = np.zeros_like(codes)
+        for b in range(10):
+            dec |= ((codes >> (3 * b + k)) & 1) << b
+        np.testing.assert_array_equal(dec, cells[k])
+    # a 4x4x4 lattice: Morton order visits each 2x2x2 octant in one run of 8,
+    # and the x coordinate varies fastest
+    g = np.stack(np.meshgrid(np.arange(4), np.arange(4), np.arange(4), indexing="ij")).reshape(3, -1)
+    lat = (g.astype(np.float32) + 0.5) * 256
+    order = oracle.morton_order(lat, np.zeros(3, np.float32), np.ones(3, np.float32))
+    pts = g[:, order]
+    octant = (pts[0] // 2) + 2 * (pts[1] // 2) + 4 * (pts[2] // 2)
+    np.testing.assert_array_equal(octant, np.repeat(np.arange(8), 8))
+    np.testing.assert_array_equal(pts[:, 1], [1, 0, 0])
+    # non-finite and out-of-box coordinates clamp into the grid
+    bad = np.array([[np.nan, -1e9, 1e9], [0, 0, 0], [0, 0, 0]], np.float32)
+    np.testing.assert_array_equal(oracle.morton_cells(bad, org, inv)[0], [0, 0, 1023])
