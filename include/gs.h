@@ -302,6 +302,26 @@ int gs_adam(int n_tensors, float* const* params, const float* const* grads, floa
             float eps, int32_t* step, void* stream);
 
 /*
+ * gs_ssim_workspace_size - bytes of device workspace gs_loss_ssim_l1 needs for
+ * the given views (sizes: host [V][2]).
+ */
+size_t gs_ssim_workspace_size(int n_views, const int32_t* sizes);
+
+/*
+ * gs_loss_ssim_l1 - the image-space loss the paper's per-camera fused SSIM
+ * operator computes (Section 4; SSIM of Wang et al. 2004 with the 3D Gaussian
+ * Splatting settings): per channel an 11x11 Gaussian window (std 1.5) applied
+ * as a zero-padded "same" correlation, C1 = 0.01^2, C2 = 0.03^2;
+ *   loss = (1 - lambda) mean|img - target| + lambda (1 - mean SSIM)
+ * over every element of the packed [3][H][W] images of all views, and
+ * d_images = d loss / d images (same layout; sign(0) = 0 for the L1 term).
+ * loss (device float[1]) is reduced in a fixed order.  workspace holds three
+ * partial-derivative maps and per-tile partial sums.
+ */
+int gs_loss_ssim_l1(const float* images, const float* targets, int n_views, const int32_t* sizes, float lambda,
+                    float* loss, float* d_images, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * gs_morton_workspace_size - bytes of device workspace gs_morton_order needs.
  */
 size_t gs_morton_workspace_size(int64_t n);

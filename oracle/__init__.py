@@ -442,3 +442,60 @@ def morton_codes(means, origin, inv_cell):
 
 def morton_order(means, origin, inv_cell):
     return np.argsort(morton_codes(means, origin, inv_cell), kind="stable").astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# SSIM + L1 image loss (the paper's per-camera fused SSIM loss operator,
+# Section 4; SSIM of Wang et al. 2004 with the 3D Gaussian Splatting
+# settings: 11x11 Gaussian window, sigma 1.5, zero padding, C1 = 0.01^2,
+# C2 = 0.03^2, loss = (1 - lam) mean|x - y| + lam (1 - mean SSIM))
+# --------------------------------------------------------------------------
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window(size=11, sigma=1.5):
+    x = np.arange(size) - size // 2
+    w = np.exp(-(x * x) / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+def _blur(img, w):
+    """Separable 'same' convolution with zero padding (rows, then columns).
+    The padding is explicit so that axes shorter than the window keep their
+    length."""
+    r = len(w) // 2
+    a = np.apply_along_axis(lambda q: np.convolve(np.pad(q, r), w, mode="valid"), -1, _d(img))
+    return np.apply_along_axis(lambda q: np.convolve(np.pad(q, r), w, mode="valid"), -2, a)
+
+
+def ssim_map(x, y):
+    w = ssim_window()
+    mx, my = _blur(x, w), _blur(y, w)
+    exx, eyy, exy = _blur(_d(x) * x, w), _blur(_d(y) * y, w), _blur(_d(x) * y, w)
+    A = 2 * mx * my + SSIM_C1
+    Bv = 2 * (exy - mx * my) + SSIM_C2
+    C = mx * mx + my * my + SSIM_C1
+    D = (exx - mx * mx) + (eyy - my * my) + SSIM_C2
+    return A * Bv / (C * D), (mx, my, exx, exy, A, Bv, C, D)
+
+
+def ssim_l1_loss(imgs, targets, lam=0.2):
+    """Loss over all views (each [3][H][W]) and d loss / d img per view.
+    Means are over every element of every view."""
+    count = sum(int(np.asarray(t).size) for t in targets)
+    w = ssim_window()
+    loss, grads = 0.0, []
+    for x, y in zip(imgs, targets):
+        x, y = _d(x), _d(y)
+        S, (mx, my, exx, exy, A, Bv, C, D) = ssim_map(x, y)
+        loss += (1 - lam) * np.abs(x - y).sum() / count + lam * (1.0 - S).sum() / count
+        gS = -lam / count
+        # S = A B / (C D) as a function of (mx, exx, exy) per pixel
+        d_mx = gS * ((2 * my * Bv - 2 * my * A) / (C * D) - S * (2 * mx / C - 2 * mx / D))
+        d_exx = gS * (-S / D)
+        d_exy = gS * (2 * A / (C * D))
+        g = _blur(d_mx, w) + 2 * x * _blur(d_exx, w) + y * _blur(d_exy, w)
+        g += (1 - lam) * np.sign(x - y) / count
+        grads.append(g)
+    return loss, grads

@@ -52,6 +52,8 @@ _SIGS = {
     "gs_morton_workspace_size": (_sz, [_i64]),
     "gs_morton_order": (_int, [_p, _i64, _p, _p, _p, _sz, _p, _p]),
     "gs_gather_columns": (_int, [_p, _int, _i64, _p, _p, _p]),
+    "gs_ssim_workspace_size": (_sz, [_int, _p]),
+    "gs_loss_ssim_l1": (_int, [_p, _p, _int, _p, _f, _p, _p, _p, _sz, _p]),
     "gs_loss_workspace_size": (_sz, [_i64]),
     "gs_loss_l2": (_int, [_p, _p, _i64, _p, _p, _p, _sz, _p]),
 }
@@ -265,3 +267,16 @@ def gather_columns(src, order, dst):
     rc = lib().gs_gather_columns(_ptr(src, F32, "src"), C, n, _ptr(order, I32, "order"), _ptr(dst, F32, "dst"),
                                  _stream())
     _check(rc, "gs_gather_columns")
+
+
+def ssim_workspace_size(sizes):
+    sz, szp = _host_i32(np.asarray(sizes).reshape(-1, 2))
+    return int(lib().gs_ssim_workspace_size(sz.shape[0], szp))
+
+
+def loss_ssim_l1(images, targets, sizes, lam, loss, d_images, workspace):
+    sz, szp = _host_i32(np.asarray(sizes).reshape(-1, 2))
+    rc = lib().gs_loss_ssim_l1(_ptr(images, F32, "images"), _ptr(targets, F32, "targets"), sz.shape[0], szp,
+                               float(lam), _ptr(loss, F32, "loss"), _ptr(d_images, F32, "d_images"),
+                               _ptr(workspace, U8, "workspace"), workspace.numel(), _stream())
+    _check(rc, "gs_loss_ssim_l1")

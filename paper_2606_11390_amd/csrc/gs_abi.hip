@@ -36,6 +36,9 @@ hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, con
 size_t loss_workspace_size(long long n);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
 size_t morton_workspace_size(long long n);
+size_t ssim_workspace_size(const ViewTable& vt);
+hipError_t launch_ssim_l1(const ViewTable& vt, const float* img, const float* tgt, float lam, float* loss,
+                          float* dimg, void* workspace, hipStream_t st);
 hipError_t launch_morton_order(const float* means, long long n, const float* org, const float* inv_cell,
                                void* workspace, int* order, hipStream_t st);
 hipError_t launch_gather_columns(const float* src, int C, long long n, const int* order, float* dst,
@@ -308,6 +311,25 @@ int gs_gather_columns(const float* src, int channels, int64_t n, const int32_t* 
     if (channels < 0 || n < 0 || n > 0x7FFFFFFFll) return GS_ERR_ARG;
     if (channels > 0 && n > 0 && (!src || !order || !dst || src == dst)) return GS_ERR_ARG;
     return status(gs::launch_gather_columns(src, channels, n, order, dst, as_stream(stream)));
+}
+
+size_t gs_ssim_workspace_size(int n_views, const int32_t* sizes)
+{
+    ViewTable vt;
+    if (!make_views(sizes, n_views, 16, vt)) return 0;
+    return gs::ssim_workspace_size(vt);
+}
+
+int gs_loss_ssim_l1(const float* images, const float* targets, int n_views, const int32_t* sizes, float lambda,
+                    float* loss, float* d_images, void* workspace, size_t workspace_bytes, void* stream)
+{
+    ViewTable vt;
+    if (!make_views(sizes, n_views, 16, vt)) return GS_ERR_ARG;
+    if (!images || !targets || !loss || !d_images || !workspace || !(lambda >= 0.0f && lambda <= 1.0f))
+        return GS_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return GS_ERR_ARG;
+    if (workspace_bytes < gs::ssim_workspace_size(vt)) return GS_ERR_WORKSPACE;
+    return status(gs::launch_ssim_l1(vt, images, targets, lambda, loss, d_images, workspace, as_stream(stream)));
 }
 
 }  // extern "C"

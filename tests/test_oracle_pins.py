@@ -607,3 +607,42 @@ def test_morton_codes_interleave_and_visit_octants_contiguously():
     # non-finite and out-of-box coordinates clamp into the grid
     bad = np.array([[np.nan, -1e9, 1e9], [0, 0, 0], [0, 0, 0]], np.float32)
     np.testing.assert_array_equal(oracle.morton_cells(bad, org, inv)[0], [0, 0, 1023])
+
+
+def test_ssim_window_blur_and_closed_forms():
+    import scipy.ndimage as ndi
+    w = oracle.ssim_window()
+    assert w.sum() == pytest.approx(1.0) and np.allclose(w, w[::-1])
+    np.testing.assert_allclose(w / w[5], np.exp(-(np.arange(11) - 5) ** 2 / 4.5), rtol=1e-14)
+    # separable zero-padded blur == 2-D correlation with the outer-product window
+    img = np.random.default_rng(22).uniform(0, 1, (3, 23, 31))
+    ref = np.stack([ndi.correlate(c, np.outer(w, w), mode="constant") for c in img])
+    np.testing.assert_allclose(oracle._blur(img, w), ref, atol=1e-14)
+    # axes shorter than the window (down to 1 x 1) keep their length
+    for shp in [(1, 1, 1), (2, 4, 3), (1, 7, 12)]:
+        small = np.random.default_rng(24).uniform(0, 1, shp)
+        ref = np.stack([ndi.correlate(c, np.outer(w, w), mode="constant") for c in small])
+        np.testing.assert_allclose(oracle._blur(small, w), ref, atol=1e-14)
+    # constant images: interior SSIM = (2ab + C1) / (a^2 + b^2 + C1)
+    a, b = 0.3, 0.7
+    S, _ = oracle.ssim_map(np.full((1, 30, 30), a), np.full((1, 30, 30), b))
+    want = (2 * a * b + oracle.SSIM_C1) / (a * a + b * b + oracle.SSIM_C1)
+    np.testing.assert_allclose(S[0, 5:-5, 5:-5], want, rtol=1e-12)
+    # identical images: SSIM = 1, loss = 0
+    S, _ = oracle.ssim_map(img, img)
+    np.testing.assert_allclose(S, 1.0, rtol=1e-12)
+
+
+def test_ssim_l1_gradient_matches_finite_differences():
+    rng = np.random.default_rng(23)
+    x = rng.uniform(0, 1, (3, 17, 21))
+    y = rng.uniform(0, 1, (3, 17, 21))
+    L, (g,) = oracle.ssim_l1_loss([x], [y])
+    for _ in range(25):
+        idx = tuple(int(rng.integers(0, n)) for n in x.shape)
+        h = 1e-6
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (oracle.ssim_l1_loss([xp], [y])[0] - oracle.ssim_l1_loss([xm], [y])[0]) / (2 * h)
+        assert g[idx] == pytest.approx(fd, rel=1e-5, abs=1e-12)
