@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
 #define GS_MAX_VIEWS 64
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD_FLOATS 9
@@ -81,6 +81,11 @@ extern "C" {
 #define GS_FLAG_CLAMP_R 0x2u
 #define GS_FLAG_CLAMP_G 0x4u
 #define GS_FLAG_CLAMP_B 0x8u
+
+/* radius_mode of gs_project: the screen box that selects a splat's tiles */
+#define GS_RADIUS_3SIGMA 0   /* per-axis 3-sigma box (default) */
+#define GS_RADIUS_OPACITY 1  /* 3-sigma box clipped to the alpha >= 1/255 region */
+#define GS_RADIUS_EIGEN 2    /* square of 3 sqrt(largest eigenvalue) (3D Gaussian Splatting) */
 
 /* gs_bin_sort info words (device int32[4]) */
 #define GS_INFO_VISIBLE 0   /* number of visible (view, Gaussian) pairs */
@@ -122,10 +127,21 @@ const char* gs_strerror(int code);
  *   near_plane, far_plane culling planes on camera z (z <= near or z >= far)
  *   eps2d                 isotropic dilation added to the 2-D covariance (0.3)
  *   tile                  tile edge used to count tiles_touched
+ *   radius_mode           GS_RADIUS_* (densification-oriented variants of the
+ *                         screen box; the paper fixes none):
+ *                         3SIGMA  rx, ry = ceil(3 sqrt(Sigma2_xx)), ceil(3 sqrt(Sigma2_yy));
+ *                         OPACITY min of 3SIGMA and ceil(sqrt(tau' Sigma2_xx)) + 1
+ *                                 (same in y), tau' = 1.001 * 2 ln(255 sigma) + 0.01:
+ *                                 drops only tiles where every pixel has
+ *                                 alpha < 1/255, so images and gradients are
+ *                                 those of 3SIGMA with fewer intersections;
+ *                         EIGEN   rx = ry = ceil(3 sqrt(m + sqrt(max(m^2 - det, 0.1)))),
+ *                                 m = (Sigma2_xx + Sigma2_yy) / 2;
+ *                         any other value is GS_ERR_ARG
  * Method: Sigma = R S S^T R^T; p = R_v mu + t_v; J = Jacobian of the pinhole
  * projection at p with x/z, y/z clamped to +-1.3 * (W/2)/fx, (H/2)/fy;
  * Sigma2 = J R_v Sigma R_v^T J^T + eps2d I; Q = Sigma2^-1; (u, v) = (fx x/z +
- * cx, fy y/z + cy); radii = ceil(3 sqrt(Sigma2_xx)), ceil(3 sqrt(Sigma2_yy));
+ * cx, fy y/z + cy); radii per radius_mode;
  * tile rectangle [floor((u-rx)/tile), floor((u+rx)/tile)+1) x (same in y),
  * clamped to the grid, evaluated in float32.
  * Culled (all outputs zero, record unwritten): non-finite input, z outside
@@ -140,7 +156,7 @@ const char* gs_strerror(int code);
 int gs_project(const float* means, const float* log_scales, const float* quats,
                const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
                const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
-               float near_plane, float far_plane, float eps2d, int tile,
+               float near_plane, float far_plane, float eps2d, int tile, int radius_mode,
                float* splats, float* depths, int32_t* radii, int32_t* tiles_touched,
                uint8_t* flags, void* stream);
 
@@ -257,6 +273,23 @@ int gs_project_bwd(const float* means, const float* log_scales, const float* qua
                    float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
                    float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh,
                    void* stream);
+
+/*
+ * gs_densify_stats - per-Gaussian statistics of the adaptive density control
+ * of 3D Gaussian Splatting (Kerbl et al. 2023; the paper densifies to larger
+ * Gaussian counts with it, Section 5), gathered from one step's 2-D gradients.
+ * For every view v in which Gaussian g is visible (flags & GS_FLAG_VISIBLE):
+ *   grad_accum[g] += || (dL/du * W_v / 2, dL/dv * H_v / 2) ||_2
+ * (the gradient norm with respect to the normalised device coordinates of the
+ * projected mean, u = ((x_ndc + 1) W - 1) / 2), count[g] += 1 and
+ * max_radius[g] = max(max_radius[g], rx, ry).
+ * grad2d [V][N][9] and radii [V][N][2] as written by gs_rasterize_bwd and
+ * gs_project; grad_accum (float), count and max_radius (int32) [N] are
+ * accumulated, never cleared.  Deterministic: one thread per Gaussian walks
+ * the views in order.
+ */
+int gs_densify_stats(const float* grad2d, const uint8_t* flags, const int32_t* radii, int64_t n, int n_views,
+                     const int32_t* sizes, float* grad_accum, int32_t* count, int32_t* max_radius, void* stream);
 
 /*
  * gs_raster_visits - instrumentation for the roofline numerator: runs the

@@ -52,7 +52,7 @@ def lib():
             _b.build()
         L = ctypes.CDLL(_LIB_PATH)
         L.or_project.argtypes = [_i64, _int, _D, _D, _D, _D, _D, _D, _D, _int, _int, _dbl, _dbl, _dbl,
-                                 _int, _D, _D, _D, _D, _D, _D, _D, _I, _I, _U8, _U8, _D]
+                                 _int, _int, _D, _D, _D, _D, _D, _D, _D, _I, _I, _U8, _U8, _D]
         L.or_bin_emit.argtypes = [_i64, _F, _F, _F, _I, _int, _int, _int, _i64, _U64, _I, _i64]
         L.or_bin_emit.restype = _i64
         L.or_sort_pairs.argtypes = [_i64, _U64, _I]
@@ -62,7 +62,7 @@ def lib():
         L.or_raster_bwd.argtypes = [_int, _int, _int, _I, _I, _i64, _D, _D, _D, _D, _D, _D, _D, _D,
                                     _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.or_project_bwd.argtypes = [_i64, _int, _D, _D, _D, _D, _D, _D, _D, _int, _int, _dbl, _dbl,
-                                     _dbl, _int, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+                                     _dbl, _int, _int, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.or_sh_basis.argtypes = [_int, _D, _D]
         L.or_quat_rot.argtypes = [_D, _D]
         L.or_tile_rect.argtypes = [ctypes.c_float, ctypes.c_float, _int, _int, _int, _int, _int, _I]
@@ -129,8 +129,14 @@ class Params:
                       self.opac.copy(), self.sh.copy(), self.deg)
 
 
-def project(P, viewmat, intr, W, H, near=0.01, far=1e10, eps2d=0.3, tile=16):
-    """Projection + SH colour of all Gaussians into one view (FP64)."""
+RADIUS_3SIGMA, RADIUS_OPACITY, RADIUS_EIGEN = 0, 1, 2
+
+
+def project(P, viewmat, intr, W, H, near=0.01, far=1e10, eps2d=0.3, tile=16, radius_mode=RADIUS_3SIGMA):
+    """Projection + SH colour of all Gaussians into one view (FP64).
+    ``radius_mode`` picks the screen box that selects tiles: the per-axis
+    3-sigma box, the opacity-aware box (3-sigma box clipped to the region
+    alpha >= 1/255) or the square of the largest eigenvalue."""
     N = P.n
     vm, it = _d(viewmat).reshape(12), _d(intr).reshape(4)
     out = dict(u=np.zeros(N), v=np.zeros(N), depth=np.zeros(N), cov=np.zeros((3, N)),
@@ -139,7 +145,7 @@ def project(P, viewmat, intr, W, H, near=0.01, far=1e10, eps2d=0.3, tile=16):
                clamp=np.zeros(N, np.uint8), visible=np.zeros(N, np.uint8), margin=np.zeros(N))
     rc = lib().or_project(N, P.deg, _p(P.means, _D), _p(P.log_scales, _D), _p(P.quats, _D),
                           _p(P.opac, _D), _p(P.sh, _D), _p(vm, _D), _p(it, _D), int(W), int(H),
-                          float(near), float(far), float(eps2d), int(tile),
+                          float(near), float(far), float(eps2d), int(tile), int(radius_mode),
                           *[_p(out[k], _D) for k in ("u", "v", "depth", "cov", "conic", "sigma", "rgb")],
                           _p(out["radii"], _I), _p(out["tiles"], _I), _p(out["clamp"], _U8),
                           _p(out["visible"], _U8), _p(out["margin"], _D))
@@ -325,7 +331,8 @@ def raster_bwd(W, H, tile, ranges, vals, sp, d_img, d_alpha=None, bg=(0.0, 0.0, 
     return g
 
 
-def project_bwd(P, viewmat, intr, W, H, g, near=0.01, far=1e10, eps2d=0.3, tile=16, acc=None):
+def project_bwd(P, viewmat, intr, W, H, g, near=0.01, far=1e10, eps2d=0.3, tile=16, acc=None,
+                radius_mode=RADIUS_3SIGMA):
     """Backward of :func:`project` for one view.  ``g`` holds upstream
     gradients u, v, conic [3][N], sigma, rgb [3][N].  Accumulates into ``acc``
     (dict of means, log_scales, quats, opac, sh) and returns it."""
@@ -339,7 +346,7 @@ def project_bwd(P, viewmat, intr, W, H, g, near=0.01, far=1e10, eps2d=0.3, tile=
     gcon, gsig, grgb = _d(g["conic"]), _d(g["sigma"]), _d(g["rgb"])
     rc = lib().or_project_bwd(N, P.deg, _p(P.means, _D), _p(P.log_scales, _D), _p(P.quats, _D),
                               _p(P.opac, _D), _p(P.sh, _D), _p(vm, _D), _p(it, _D), int(W), int(H),
-                              float(near), float(far), float(eps2d), int(tile), _p(guv, _D),
+                              float(near), float(far), float(eps2d), int(tile), int(radius_mode), _p(guv, _D),
                               _p(gcon, _D), _p(gsig, _D), _p(grgb, _D), _p(acc["means"], _D),
                               _p(acc["log_scales"], _D), _p(acc["quats"], _D), _p(acc["opac"], _D),
                               _p(acc["sh"], _D))
@@ -363,7 +370,8 @@ def l2_loss(imgs, targets):
 # --------------------------------------------------------------------------
 # whole step (FP64 end to end)
 # --------------------------------------------------------------------------
-def step(scene, P=None, tile=16, near=0.01, far=1e10, eps2d=0.3, bg=(0.0, 0.0, 0.0), backward=True):
+def step(scene, P=None, tile=16, near=0.01, far=1e10, eps2d=0.3, bg=(0.0, 0.0, 0.0), backward=True,
+         radius_mode=RADIUS_3SIGMA):
     """One forward (+ backward) pass of the whole path in FP64.
 
     Binning takes its decisions on the FP32-rounded mean, radius and depth
@@ -375,7 +383,7 @@ def step(scene, P=None, tile=16, near=0.01, far=1e10, eps2d=0.3, bg=(0.0, 0.0, 0
     projs, views = [], []
     for v in range(scene.n_views):
         W, H = (int(x) for x in scene.sizes[v])
-        pr = project(P, scene.viewmats[v], scene.intrinsics[v], W, H, near, far, eps2d, tile)
+        pr = project(P, scene.viewmats[v], scene.intrinsics[v], W, H, near, far, eps2d, tile, radius_mode)
         projs.append(pr)
         views.append((pr["u"].astype(np.float32), pr["v"].astype(np.float32),
                       pr["depth"].astype(np.float32), pr["radii"]))
@@ -396,9 +404,33 @@ def step(scene, P=None, tile=16, near=0.01, far=1e10, eps2d=0.3, bg=(0.0, 0.0, 0
             W, H = (int(x) for x in scene.sizes[v])
             g2 = raster_bwd(W, H, tile, ranges[offs[v]:offs[v + 1]], vals, projs[v], dimgs[v], None, bg)
             acc = project_bwd(P, scene.viewmats[v], scene.intrinsics[v], W, H, g2, near, far, eps2d,
-                              tile, acc)
+                              tile, acc, radius_mode)
         out["grads"] = acc
     return out
+
+
+# --------------------------------------------------------------------------
+# adaptive density control statistics (3D Gaussian Splatting, Kerbl et al.
+# 2023; the paper densifies with it, Section 5)
+# --------------------------------------------------------------------------
+def densify_stats(g_uv, visible, radii, sizes, acc=None):
+    """Running sums over the views that see each Gaussian: the norm of the
+    gradient with respect to the projected mean in normalised device
+    coordinates (u = ((x_ndc + 1) W - 1) / 2, so d/dx_ndc = W / 2 d/du), the
+    number of such views, and the largest screen radius.  ``g_uv[v]`` is
+    [2][N] (dL/du, dL/dv), ``visible[v]`` [N], ``radii[v]`` [2][N]."""
+    N = np.asarray(visible[0]).shape[0]
+    if acc is None:
+        acc = dict(grad=np.zeros(N), count=np.zeros(N, np.int64), max_radius=np.zeros(N, np.int64))
+    for v, (W, H) in enumerate(np.asarray(sizes).reshape(-1, 2)):
+        vis = np.asarray(visible[v]).astype(bool)
+        gx = _d(g_uv[v][0]) * (W / 2.0)
+        gy = _d(g_uv[v][1]) * (H / 2.0)
+        acc["grad"][vis] += np.hypot(gx, gy)[vis]
+        acc["count"][vis] += 1
+        r = np.max(np.asarray(radii[v]), axis=0)
+        acc["max_radius"][vis] = np.maximum(acc["max_radius"][vis], r[vis])
+    return acc
 
 
 # --------------------------------------------------------------------------

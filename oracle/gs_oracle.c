@@ -17,7 +17,8 @@
  *
  *   projection  Sigma = R S S^T R^T, p = W mu + t, EWA 2-D covariance
  *               Sigma2 = J W Sigma W^T J^T + eps2d I, conic = Sigma2^{-1},
- *               3-sigma radii, tile rectangle;
+ *               radii (3-sigma box; opacity-aware and eigenvalue-square
+ *               variants), tile rectangle;
  *   colour      real spherical harmonics up to degree 3 along the ray from
  *               the camera centre, plus 0.5, clamped at 0;
  *   binning     one (tile | depth) key per (Gaussian, tile) pair, stably
@@ -31,7 +32,7 @@
  * thresholds are the float32 values 1/255f, 0.99f, 1e-4f, 1.3f promoted to
  * double; quaternions are (w, x, y, z); cameras use OpenCV axes; pixel (i, j)
  * has its centre at (i + 0.5, j + 0.5); radii bound the 3-sigma box of each
- * axis; the tile rectangle and the depth key bits are taken in float32
+ * axis by default; the tile rectangle and the depth key bits are taken in float32
  * arithmetic from the float32-rounded mean, radius and depth; SH use the real
  * orthonormal basis with the Condon-Shortley phase.
  *
@@ -224,7 +225,7 @@ typedef struct {
 static void project_one(int64_t g, int64_t N, int K, const double* means, const double* log_scales,
                         const double* quats, const double* opac, const double* sh,
                         const double* vm, const double* intr, int W, int H,
-                        double near_, double far_, double eps2d, int tile, proj_t* P)
+                        double near_, double far_, double eps2d, int tile, int radius_mode, proj_t* P)
 {
     memset(P, 0, sizeof(*P));
     P->margin = INFINITY;
@@ -303,12 +304,33 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
     P->u = fx * p[0] / z + cx;
     P->v = fy * p[1] / z + cy;
 
-    /* 3-sigma radii per axis */
+    /* radii (half-widths of the screen box that selects tiles):
+     *  0: 3-sigma box per axis, ceil(3 sqrt(a)), ceil(3 sqrt(c));
+     *  1: opacity-aware, the smaller of the 3-sigma box and the box of the
+     *     region alpha >= 1/255, i.e. d^T conic d <= tau = 2 ln(255 sigma),
+     *     with tau widened to 1.001 tau + 0.01 and one pixel of padding so
+     *     that float32 evaluation of alpha never reaches outside it;
+     *  2: the square of 3D Gaussian Splatting, 3 sqrt(lambda_max) on both
+     *     axes with lambda_max = m + sqrt(max(m^2 - det, 0.1)), m = (a + c) / 2. */
     double ex = 3.0 * sqrt(a), ey = 3.0 * sqrt(c);
+    if (radius_mode == 2) {
+        double m = 0.5 * (a + c);
+        ex = ey = 3.0 * sqrt(m + sqrt(fmax(m * m - det, 0.1)));
+    }
     P->margin = fmin(P->margin, int_margin(ex));
     P->margin = fmin(P->margin, int_margin(ey));
     P->rx = (int)fmin(ceil(ex), 1073741824.0);   /* radii saturate at 2^30 px */
     P->ry = (int)fmin(ceil(ey), 1073741824.0);
+    if (radius_mode == 1) {
+        double tau = 2.0 * log(255.0 * P->sigma);
+        tau = (tau > 0.0 ? tau : 0.0) * 1.001 + 0.01;
+        double ax = sqrt(tau * a), ay = sqrt(tau * c);
+        P->margin = fmin(P->margin, int_margin(ax));
+        P->margin = fmin(P->margin, int_margin(ay));
+        int qx = (int)fmin(ceil(ax), 1073741823.0) + 1, qy = (int)fmin(ceil(ay), 1073741823.0) + 1;
+        if (qx < P->rx) P->rx = qx;
+        if (qy < P->ry) P->ry = qy;
+    }
 
     /* tile rectangle, float32 arithmetic on float32-rounded values */
     /* a floor decision can change the rectangle only where it is not clamped */
@@ -365,17 +387,19 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
 int or_project(int64_t N, int sh_degree, const double* means, const double* log_scales,
                const double* quats, const double* opac, const double* sh,
                const double* viewmat, const double* intr, int W, int H,
-               double near_, double far_, double eps2d, int tile,
+               double near_, double far_, double eps2d, int tile, int radius_mode,
                double* u, double* v, double* depth, double* cov, double* conic,
                double* sigma, double* rgb, int32_t* radii, int32_t* tiles,
                uint8_t* clamp, uint8_t* visible, double* margin)
 {
-    if (N < 0 || sh_degree < 0 || sh_degree > 3 || W <= 0 || H <= 0 || tile <= 0) return -1;
+    if (N < 0 || sh_degree < 0 || sh_degree > 3 || W <= 0 || H <= 0 || tile <= 0 || radius_mode < 0 ||
+        radius_mode > 2)
+        return -1;
     int K = (sh_degree + 1) * (sh_degree + 1);
     for (int64_t g = 0; g < N; g++) {
         proj_t P;
         project_one(g, N, K, means, log_scales, quats, opac, sh, viewmat, intr, W, H,
-                    near_, far_, eps2d, tile, &P);
+                    near_, far_, eps2d, tile, radius_mode, &P);
         u[g] = P.u; v[g] = P.v; depth[g] = P.z;
         for (int i = 0; i < 3; i++) {
             cov[i * N + g] = P.cov[i];
@@ -648,7 +672,7 @@ static void quat_rot_grad(const double q[4], double dR[4][9])
 int or_project_bwd(int64_t N, int sh_degree, const double* means, const double* log_scales,
                    const double* quats, const double* opac, const double* sh,
                    const double* viewmat, const double* intr, int W, int H,
-                   double near_, double far_, double eps2d, int tile,
+                   double near_, double far_, double eps2d, int tile, int radius_mode,
                    const double* g_uv, const double* g_conic, const double* g_sig,
                    const double* g_rgb, double* d_means, double* d_log_scales,
                    double* d_quats, double* d_opac, double* d_sh)
@@ -659,7 +683,7 @@ int or_project_bwd(int64_t N, int sh_degree, const double* means, const double* 
     for (int64_t g = 0; g < N; g++) {
         proj_t P;
         project_one(g, N, K, means, log_scales, quats, opac, sh, viewmat, intr, W, H,
-                    near_, far_, eps2d, tile, &P);
+                    near_, far_, eps2d, tile, radius_mode, &P);
         if (!P.visible) continue;
         double gmu[3] = {0, 0, 0};
 

@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
-GS_ABI_VERSION = 1
+GS_ABI_VERSION = 2
 GS_MAX_VIEWS = 64
 SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
@@ -36,8 +36,9 @@ _sz = ctypes.c_size_t
 _SIGS = {
     "gs_abi_version": (_int, []),
     "gs_strerror": (ctypes.c_char_p, [_int]),
-    "gs_project": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _f, _f, _int,
+    "gs_project": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _f, _f, _int, _int,
                           _p, _p, _p, _p, _p, _p]),
+    "gs_densify_stats": (_int, [_p, _p, _p, _i64, _int, _p, _p, _p, _p, _p]),
     "gs_bin_sort_workspace_size": (_sz, [_i64, _int, _i64, _i64]),
     "gs_bin_sort": (_int, [_p, _p, _p, _p, _i64, _int, _p, _int, _i64, _p, _sz, _p, _p, _p, _p, _p]),
     "gs_tile_schedule_size": (_sz, [_i64]),
@@ -132,14 +133,14 @@ F32, I32, U8 = torch.float32, torch.int32, torch.uint8
 
 
 def project(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes,
-            near, far, eps2d, tile, splats, depths, radii, tiles_touched, flags):
+            near, far, eps2d, tile, splats, depths, radii, tiles_touched, flags, radius_mode=0):
     n = means.shape[1]
     sz, szp = _host_i32(sizes)
     rc = lib().gs_project(_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
                           _ptr(quats, F32, "quats"), _ptr(opacity_logits, F32, "opacity_logits"),
                           _ptr(sh, F32, "sh"), n, int(sh_degree), _ptr(viewmats, F32, "viewmats"),
                           _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(near), float(far),
-                          float(eps2d), int(tile), _ptr(splats, F32, "splats"), _ptr(depths, F32, "depths"),
+                          float(eps2d), int(tile), int(radius_mode), _ptr(splats, F32, "splats"), _ptr(depths, F32, "depths"),
                           _ptr(radii, I32, "radii"), _ptr(tiles_touched, I32, "tiles_touched"),
                           _ptr(flags, U8, "flags"), _stream())
     _check(rc, "gs_project")
@@ -280,3 +281,11 @@ def loss_ssim_l1(images, targets, sizes, lam, loss, d_images, workspace):
                                float(lam), _ptr(loss, F32, "loss"), _ptr(d_images, F32, "d_images"),
                                _ptr(workspace, U8, "workspace"), workspace.numel(), _stream())
     _check(rc, "gs_loss_ssim_l1")
+
+
+def densify_stats(grad2d, flags, radii, n, sizes, grad_accum, count, max_radius):
+    sz, szp = _host_i32(np.asarray(sizes).reshape(-1, 2))
+    rc = lib().gs_densify_stats(_ptr(grad2d, F32, "grad2d"), _ptr(flags, U8, "flags"), _ptr(radii, I32, "radii"),
+                                int(n), sz.shape[0], szp, _ptr(grad_accum, F32, "grad_accum"),
+                                _ptr(count, I32, "count"), _ptr(max_radius, I32, "max_radius"), _stream())
+    _check(rc, "gs_densify_stats")

@@ -8,8 +8,11 @@ namespace gs {
 hipError_t launch_project(int deg, const float* means, const float* log_scales, const float* quats,
                           const float* opac, const float* sh, long long N, const float* viewmats,
                           const float* intr, const ViewTable& vt, float near_plane, float far_plane,
-                          float eps2d, int tile, float* splats, float* depths, int2* radii,
+                          float eps2d, int tile, int radius_mode, float* splats, float* depths, int2* radii,
                           int* tiles, uint8_t* flags, hipStream_t stream);
+hipError_t launch_densify_stats(const float* grad2d, const uint8_t* flags, const int2* radii, long long N,
+                                const ViewTable& vt, float* grad_accum, int* count, int* max_radius,
+                                hipStream_t st);
 hipError_t launch_project_bwd(int deg, const float* means, const float* log_scales,
                               const float* quats, const float* opac, const float* sh, long long N,
                               const float* viewmats, const float* intr, const ViewTable& vt,
@@ -108,12 +111,14 @@ const char* gs_strerror(int code)
 int gs_project(const float* means, const float* log_scales, const float* quats,
                const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
                const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
-               float near_plane, float far_plane, float eps2d, int tile, float* splats, float* depths,
-               int32_t* radii, int32_t* tiles_touched, uint8_t* flags, void* stream)
+               float near_plane, float far_plane, float eps2d, int tile, int radius_mode, float* splats,
+               float* depths, int32_t* radii, int32_t* tiles_touched, uint8_t* flags, void* stream)
 {
     ViewTable vt;
     if (n < 0 || n > 0x7FFFFFFFll || sh_degree < 0 || sh_degree > 3 || !tile_ok(tile) ||
         !make_views(sizes, n_views, tile, vt))
+        return GS_ERR_ARG;
+    if (radius_mode != GS_RADIUS_3SIGMA && radius_mode != GS_RADIUS_OPACITY && radius_mode != GS_RADIUS_EIGEN)
         return GS_ERR_ARG;
     if ((unsigned long long)n * (unsigned long long)n_views > 0xFFFFFFFFull) return GS_ERR_ARG;
     if (!(eps2d >= 0.0f) || !(near_plane > 0.0f) || !(far_plane > near_plane)) return GS_ERR_ARG;
@@ -122,7 +127,8 @@ int gs_project(const float* means, const float* log_scales, const float* quats,
         !splats || !depths || !radii || !tiles_touched || !flags || !aligned16(splats))
         return GS_ERR_ARG;
     return status(gs::launch_project(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
-                                     intrinsics, vt, near_plane, far_plane, eps2d, tile, splats, depths,
+                                     intrinsics, vt, near_plane, far_plane, eps2d, tile, radius_mode, splats,
+                                     depths,
                                      reinterpret_cast<int2*>(radii), tiles_touched, flags,
                                      as_stream(stream)));
 }
@@ -330,6 +336,18 @@ int gs_loss_ssim_l1(const float* images, const float* targets, int n_views, cons
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return GS_ERR_ARG;
     if (workspace_bytes < gs::ssim_workspace_size(vt)) return GS_ERR_WORKSPACE;
     return status(gs::launch_ssim_l1(vt, images, targets, lambda, loss, d_images, workspace, as_stream(stream)));
+}
+
+int gs_densify_stats(const float* grad2d, const uint8_t* flags, const int32_t* radii, int64_t n, int n_views,
+                     const int32_t* sizes, float* grad_accum, int32_t* count, int32_t* max_radius, void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || !make_views(sizes, n_views, 16, vt)) return GS_ERR_ARG;
+    if ((unsigned long long)n * (unsigned long long)n_views > 0xFFFFFFFFull) return GS_ERR_ARG;
+    if (n == 0) return GS_OK;
+    if (!grad2d || !flags || !radii || !grad_accum || !count || !max_radius) return GS_ERR_ARG;
+    return status(gs::launch_densify_stats(grad2d, flags, reinterpret_cast<const int2*>(radii), n, vt, grad_accum,
+                                           count, max_radius, as_stream(stream)));
 }
 
 }  // extern "C"

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
     long long N, const float* __restrict__ viewmats, const float* __restrict__ intr, ViewTable vt,
-    float near_plane, float far_plane, float eps2d, int tile, float* __restrict__ splats,
+    float near_plane, float far_plane, float eps2d, int tile, int radius_mode, float* __restrict__ splats,
     float* __restrict__ depths, int2* __restrict__ radii, int* __restrict__ tiles,
     uint8_t* __restrict__ flags)
 {
@@ -226,6 +226,9 @@ __global__ __launch_bounds__(256) void k_project(
     finite = finite && qn2 > 0.0f;
     const float sigma = 1.0f / (1.0f + expf(-o));
     const float lsig = log2f(sigma);
+    // widened tau = 2 ln(255 sigma) of the region alpha >= 1/255 (d^T Q d <= tau),
+    // inflated so that float32 rounding of the per-pixel alpha stays inside
+    const float tau = fmaxf(1.38629436f * (7.99435344f + lsig), 0.0f) * 1.001f + 0.01f;
     const float iq = 1.0f / sqrtf(qn2);
     float R[9], M[9];
     quat_to_rot(q[0] * iq, q[1] * iq, q[2] * iq, q[3] * iq, R);
@@ -247,8 +250,20 @@ __global__ __launch_bounds__(256) void k_project(
         if (vis) {
             u = cam.fx * ge.px / ge.pz + cam.cx;
             vv = cam.fy * ge.py / ge.pz + cam.cy;
-            rx = (int)fminf(ceilf(3.0f * sqrtf(ge.a)), 1073741824.0f);
-            ry = (int)fminf(ceilf(3.0f * sqrtf(ge.c)), 1073741824.0f);
+            if (radius_mode == GS_RADIUS_EIGEN) {
+                const float m = 0.5f * (ge.a + ge.c);
+                const float lam = m + sqrtf(fmaxf(m * m - ge.D, 0.1f));
+                rx = ry = (int)fminf(ceilf(3.0f * sqrtf(lam)), 1073741824.0f);
+            } else {
+                rx = (int)fminf(ceilf(3.0f * sqrtf(ge.a)), 1073741824.0f);
+                ry = (int)fminf(ceilf(3.0f * sqrtf(ge.c)), 1073741824.0f);
+            }
+            if (radius_mode == GS_RADIUS_OPACITY) {
+                const int qx = (int)fminf(ceilf(sqrtf(tau * ge.a)), 1073741823.0f) + 1;
+                const int qy = (int)fminf(ceilf(sqrtf(tau * ge.c)), 1073741823.0f) + 1;
+                rx = min(rx, qx);
+                ry = min(ry, qy);
+            }
             int x0, y0, x1, y1;
             tile_rect(u, vv, rx, ry, tile, cam.W, cam.H, x0, y0, x1, y1);
             tt = (x1 - x0) * (y1 - y0);
@@ -290,10 +305,7 @@ __global__ __launch_bounds__(256) void k_project(
             rec[0] = make_float4(u, vv, m00, m10);
             rec[1] = make_float4(m11, lsig, col[0], col[1]);
             // conservative pixel box of the region where alpha >= 1/255:
-            // d^T Q d <= tau = 2 ln(255 sigma) has half-widths sqrt(tau a),
-            // sqrt(tau c); tau is inflated and the box padded by one pixel so
-            // that float32 rounding of the per-pixel alpha cannot reach out of it
-            const float tau = fmaxf(1.38629436f * (7.99435344f + lsig), 0.0f) * 1.001f + 0.01f;
+            // half-widths sqrt(tau a), sqrt(tau c), padded by one pixel
             const float ex = sqrtf(tau * ge.a), ey = sqrtf(tau * ge.c);
             rec[2] = make_float4(col[2], sigma, __int_as_float(pack_range(u, ex)),
                                  __int_as_float(pack_range(vv, ey)));
@@ -456,13 +468,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(
 
 #define GS_PROJ_LAUNCH(DEG)                                                                          \
     hipLaunchKernelGGL(k_project<DEG>, dim3(blocks), dim3(256), 0, stream, means, log_scales, quats, \
-                       opac, sh, N, viewmats, intr, vt, near_plane, far_plane, eps2d, tile, splats,  \
-                       depths, radii, tiles, flags)
+                       opac, sh, N, viewmats, intr, vt, near_plane, far_plane, eps2d, tile,          \
+                       radius_mode, splats, depths, radii, tiles, flags)
 
 hipError_t launch_project(int deg, const float* means, const float* log_scales, const float* quats,
                           const float* opac, const float* sh, long long N, const float* viewmats,
                           const float* intr, const ViewTable& vt, float near_plane, float far_plane,
-                          float eps2d, int tile, float* splats, float* depths, int2* radii,
+                          float eps2d, int tile, int radius_mode, float* splats, float* depths, int2* radii,
                           int* tiles, uint8_t* flags, hipStream_t stream)
 {
     if (N == 0) return hipSuccess;

@@ -24,7 +24,10 @@ from . import binding as B
 
 class Renderer:
     def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
-                 background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda"):
+                 background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda",
+                 radius_mode=0):
+        # screen box rule of the projection (GS_RADIUS_*)
+        self.radius_mode = int(radius_mode)
         # wave pixel blocks (width, pixels per lane) of the forward and backward rasterisers
         self.block = tuple(int(x) for x in block)
         self.block_bwd = self.block if block_bwd is None else tuple(int(x) for x in block_bwd)
@@ -83,7 +86,8 @@ class Renderer:
     def project(self, P, cams):
         B.project(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
                   cams["viewmats"], cams["intrinsics"], self.sizes, self.near, self.far, self.eps2d,
-                  self.tile, self.splats, self.depths, self.radii, self.tiles_touched, self.flags)
+                  self.tile, self.splats, self.depths, self.radii, self.tiles_touched, self.flags,
+                  self.radius_mode)
 
     def bin_sort(self):
         B.bin_sort(self.splats, self.depths, self.radii, self.tiles_touched, self.n, self.sizes, self.tile,

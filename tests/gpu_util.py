@@ -33,7 +33,7 @@ def host(t):
 
 
 # ---------------------------------------------------------------- oracle side
-def oracle_views(scene, tile, near=0.01, far=1e10, eps2d=0.3, P=None):
+def oracle_views(scene, tile, near=0.01, far=1e10, eps2d=0.3, P=None, radius_mode=0):
     """Oracle projection of every view, plus the ABI arrays built from it."""
     P = P or oracle.Params.of(scene)
     V, N = scene.n_views, scene.n
@@ -45,7 +45,7 @@ def oracle_views(scene, tile, near=0.01, far=1e10, eps2d=0.3, P=None):
     flags = np.zeros((V, N), np.uint8)
     for v in range(V):
         W, H = (int(x) for x in scene.sizes[v])
-        pr = oracle.project(P, scene.viewmats[v], scene.intrinsics[v], W, H, near, far, eps2d, tile)
+        pr = oracle.project(P, scene.viewmats[v], scene.intrinsics[v], W, H, near, far, eps2d, tile, radius_mode)
         projs.append(pr)
         rec[v] = oracle.to_record(pr)
         depth[v] = pr["depth"].astype(F32)
@@ -62,7 +62,7 @@ def oracle_binning(arrs, sizes, tile):
 
 
 # ------------------------------------------------------------------- GPU side
-def gpu_project(scene, tile, near=0.01, far=1e10, eps2d=0.3):
+def gpu_project(scene, tile, near=0.01, far=1e10, eps2d=0.3, radius_mode=0):
     V, N = scene.n_views, scene.n
     out = dict(splats=torch.zeros(V * N * 12, device="cuda"), depths=torch.zeros(V * N, device="cuda"),
                radii=torch.zeros(V * N * 2, dtype=torch.int32, device="cuda"),
@@ -70,7 +70,8 @@ def gpu_project(scene, tile, near=0.01, far=1e10, eps2d=0.3):
                flags=torch.zeros(V * N, dtype=torch.uint8, device="cuda"))
     B.project(dev(scene.means), dev(scene.log_scales), dev(scene.quats), dev(scene.opacity_logits),
               dev(scene.sh), scene.sh_degree, dev(scene.viewmats), dev(scene.intrinsics), scene.sizes, near,
-              far, eps2d, tile, out["splats"], out["depths"], out["radii"], out["tiles"], out["flags"])
+              far, eps2d, tile, out["splats"], out["depths"], out["radii"], out["tiles"], out["flags"],
+              radius_mode)
     h = {k: host(v) for k, v in out.items()}
     return dict(splats=h["splats"].reshape(V, N, 12), depths=h["depths"].reshape(V, N),
                 radii=h["radii"].reshape(V, N, 2), tiles=h["tiles"].reshape(V, N),

@@ -567,6 +567,75 @@ def test_alpha_box_contains_every_pixel_with_alpha_above_threshold():
     assert inside > 0
 
 
+def test_eigen_square_radius_matches_largest_eigenvalue():
+    # the 3D Gaussian Splatting square: 3 sqrt(lambda_max) on both axes, the
+    # eigenvalue cross-checked with numpy's symmetric eigensolver
+    z0, f, th = 3.0, 60.0, 0.4
+    s1, s2 = 0.08, 0.02
+    q = [math.cos(th / 2), 0, 0, math.sin(th / 2)]
+    P = _params([0, 0, z0], np.log([s1, s2, 0.5]), q, [2.0], np.zeros((1, 3, 1)), 0)
+    pr = oracle.project(P, IDENT, [f, f, 32, 32], 64, 64, radius_mode=oracle.RADIUS_EIGEN)
+    a, b, c = pr["cov"][:, 0]
+    lam = np.linalg.eigvalsh(np.array([[a, b], [b, c]])).max()
+    assert tuple(pr["radii"][:, 0]) == (math.ceil(3 * math.sqrt(lam)),) * 2
+    # never smaller than the per-axis 3-sigma box
+    p0 = oracle.project(P, IDENT, [f, f, 32, 32], 64, 64)
+    assert np.all(pr["radii"] >= p0["radii"])
+
+
+def test_opacity_aware_radius_changes_work_not_images():
+    # the opacity-aware box drops only tiles where every pixel has
+    # alpha < 1/255: images and gradients are identical to the 3-sigma box,
+    # with fewer intersections; opaque splats (tau >= 9) keep the 3-sigma box
+    s = scenes.tiny(seed=31, n_gaussians=400, width=64, height=48, focal=50.0)
+    s.opacity_logits[:] = np.linspace(-5.5, 4.0, 400).astype(np.float32)
+    s.log_scales[:] += np.float32(1.0)
+    o0 = oracle.step(s, tile=8)
+    o1 = oracle.step(s, tile=8, radius_mode=oracle.RADIUS_OPACITY)
+    r0, r1 = o0["projs"][0]["radii"], o1["projs"][0]["radii"]
+    assert np.all(r1 <= r0)
+    assert len(o1["vals"]) < 0.9 * len(o0["vals"])
+    assert np.array_equal(o0["imgs"][0], o1["imgs"][0])
+    for k in o0["grads"]:
+        assert np.array_equal(o0["grads"][k], o1["grads"][k]), k
+    pr = o1["projs"][0]
+    tau = 2 * np.log(255 * pr["sigma"]) * 1.001 + 0.01
+    opaque = pr["visible"].astype(bool) & (tau >= 9.0)
+    assert opaque.any() and np.array_equal(r1[:, opaque], r0[:, opaque])
+    # brute force: an axis the opacity rule clipped still holds every pixel
+    # centre whose alpha reaches 1/255, and is within three pixels of the
+    # tightest such half-width
+    clipped = 0
+    for g in np.nonzero(pr["visible"])[0]:
+        A, B, C = pr["conic"][:, g]
+        u, v = pr["u"][g], pr["v"][g]
+        ii, jj = np.meshgrid(np.arange(int(u) - 60, int(u) + 61), np.arange(int(v) - 60, int(v) + 61))
+        dx, dy = ii + 0.5 - u, jj + 0.5 - v
+        hit = pr["sigma"][g] * np.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy) >= oracle.ALPHA_MIN
+        for ax, d in ((0, dx), (1, dy)):
+            if r1[ax, g] < r0[ax, g]:
+                clipped += 1
+                ext = np.abs(d[hit]).max() if hit.any() else 0.0
+                assert ext <= r1[ax, g] <= ext + 3
+    assert clipped > 100
+
+
+def test_densify_stats_hand_example():
+    # two views (4 x 6 and 2 x 2 pixels, so d/dx_ndc = (2, 3) and (1, 1) times
+    # d/du, d/dv), three Gaussians; the third is never visible
+    g_uv = [np.array([[1.5, 0.0, 9.0], [1.0, 2.0, 9.0]]), np.array([[3.0, 0.5, 9.0], [4.0, 0.0, 9.0]])]
+    visible = [np.array([1, 1, 0]), np.array([1, 0, 0])]
+    radii = [np.array([[3, 7, 50], [5, 2, 50]]), np.array([[9, 1, 50], [4, 1, 50]])]
+    acc = oracle.densify_stats(g_uv, visible, radii, [(4, 6), (2, 2)])
+    # G0: |(3, 3)| + |(3, 4)| = 3 sqrt 2 + 5; G1: |(0, 6)| = 6
+    np.testing.assert_allclose(acc["grad"], [3 * math.sqrt(2) + 5, 6.0, 0.0], rtol=1e-15)
+    np.testing.assert_array_equal(acc["count"], [2, 1, 0])
+    np.testing.assert_array_equal(acc["max_radius"], [9, 7, 0])
+    # accumulation continues from a previous call
+    acc = oracle.densify_stats(g_uv[:1], visible[:1], radii[:1], [(4, 6)], acc)
+    np.testing.assert_array_equal(acc["count"], [3, 2, 0])
+
+
 def test_adam_matches_torch_optim_adam():
     # library pin: torch.optim.Adam (CPU, float64) over several steps
     import torch
