@@ -180,9 +180,9 @@ def main():
     gauss = scene.n * scene.n_views
     result = {}
 
-    def run_path(persistent, graph, tile=None, block=(0, 0), block_bwd=None):
+    def run_path(persistent, graph, tile=None, block=(0, 0), block_bwd=None, radius_mode=0):
         r = R.Renderer(scene.n, scene.sh_degree, scene.sizes, tile=tile or args.tile, capacity=1 << 22,
-                       persistent=persistent, block=block, block_bwd=block_bwd)
+                       persistent=persistent, block=block, block_bwd=block_bwd, radius_mode=radius_mode)
         m = r.fit_capacity(P, cams)
         if graph:
             r.capture(P, cams, tg, grads, warmup=max(1, args.warmup))
@@ -250,6 +250,15 @@ def main():
                                            "ms_per_step": ms16, "mp_per_s": pixels / ms16 / 1e3}
             del r16
             torch.cuda.empty_cache()
+        # the same step with the opacity-aware screen box: identical images and
+        # gradients from fewer intersections (reported beside the headline)
+        ro, mo, mso = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]),
+                               radius_mode=B.RADIUS_OPACITY)
+        result["batched_opacity_radius"] = {"ms_per_step": mso, "mp_per_s": pixels / mso / 1e3,
+                                            "intersections": int(mo)}
+        log(f"batched, opacity-aware radius: {mso:.3f} ms/step, {pixels / mso / 1e3:.1f} MP/s, M={mo}")
+        del ro
+        torch.cuda.empty_cache()
         r_main, m, ms_main = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]))
         log(f"batched (tile {tuned['tile']}, blocks {tuned['block']} / {tuned['block_bwd']}): {ms_main:.3f} ms/step, "
             f"{pixels / ms_main / 1e3:.1f} MP/s, M={m}")
@@ -314,6 +323,8 @@ def main():
         "gaussians_per_s": round(gauss / ms_main * 1e3, 1),
         "plain": {k: round(v, 4) for k, v in result.get("plain", {}).items()},
         "batched_same_tile": result.get("batched_same_tile"),
+        "batched_opacity_radius": ({k: round(v, 4) for k, v in result["batched_opacity_radius"].items()}
+                                   if "batched_opacity_radius" in result else None),
         "autotuned": tuned,
         "stage_ms": {k: round(v, 4) for k, v in st.items()},
         "visits": {"forward": fwd_visits, "backward": bwd_visits},

@@ -23,6 +23,7 @@ SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
 FLAG_VISIBLE = 1
 INFO_VISIBLE, INFO_ISECT, INFO_OVERFLOW = 0, 1, 2
+RADIUS_3SIGMA, RADIUS_OPACITY, RADIUS_EIGEN = 0, 1, 2
 
 _lib = None
 
