@@ -87,6 +87,38 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
     return out
 
 
+def algorithmic_bytes(scene, visible, isect, total_tiles):
+    """HBM bytes each HBM-bound call of the step must move at minimum, from
+    the workload's counts (N Gaussians, V views, visible (view, Gaussian)
+    pairs, M intersections, T tiles, P pixels).
+
+    project      every parameter read once (236 B at SH degree 3); per pair
+                 depth, radii, tile count and flags written (17 B); the 48-byte
+                 splat record written for visible pairs only
+    bin_sort     LSD radix sort, 16 B (key + value, read + write) per element
+                 per pass: 4 depth passes over visible pairs (the first reads
+                 depth and tile count, 8 B per pair), emission (24 B read per
+                 visible pair, 8 B written per intersection), ceil(tile bits /
+                 8) passes over the intersections, ranges (4 B read per
+                 intersection, 8 B written per tile)
+    loss         image and target read, image gradient written: 12 B per
+                 element
+    project_bwd  parameters read and their gradients written (2 x 236 B),
+                 flags read per pair, the 36-byte 2-D gradient per visible pair
+    """
+    N, V = scene.n, scene.n_views
+    K = (scene.sh_degree + 1) ** 2
+    param = 4 * (3 + 3 + 4 + 1 + 3 * K)
+    tbits = max(1, int(total_tiles - 1).bit_length())
+    tpasses = (tbits + 7) // 8
+    sort = (8 * V * N + 8 * visible + 3 * 16 * visible + 24 * visible + 8 * isect + tpasses * 16 * isect +
+            4 * isect + 8 * total_tiles)
+    return {"project": N * param + 17 * V * N + 48 * visible,
+            "bin_sort": sort,
+            "loss": 12 * 3 * scene.pixels,
+            "project_bwd": 2 * N * param + V * N + 36 * visible}
+
+
 def cpu_baseline(scene, tile, seed=0, frac=0.05, crop_frac=0.25):
     """FP64 oracle on a bounded sample of the same step, scaled to the frame.
 
@@ -277,16 +309,16 @@ def main():
     fwd_visits = int(vis.to(torch.int64).sum())
     bwd_visits = int(r_main.n_contrib.to(torch.int64).sum())
     info = r_main.info.cpu().numpy()
-    K = (scene.sh_degree + 1) ** 2
-    param_bytes = 4 * (3 + 3 + 4 + 1 + 3 * K)
-    proj_bytes = scene.n * param_bytes + gauss * (4 * 12 + 4 + 8 + 4 + 1)
+    work = algorithmic_bytes(scene, int(info[B.INFO_VISIBLE]), int(info[B.INFO_ISECT]), r_main.total_tiles)
+    gbs = lambda k: work[k] / (st[k] * 1e-3) / 1e9
     rooflines = {
         "raster_fwd": ("alu", FWD_FLOPS_PER_VISIT * fwd_visits / (st["raster_fwd"] * 1e-3) / 1e12,
                        PEAK_FP32_TFLOPS, "TFLOP/s"),
         "raster_bwd": ("alu", BWD_FLOPS_PER_VISIT * bwd_visits / (st["raster_bwd"] * 1e-3) / 1e12,
                        PEAK_FP32_TFLOPS, "TFLOP/s"),
-        "project": ("hbm", proj_bytes / (st["project"] * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"),
     }
+    for k in ("project", "bin_sort", "loss", "project_bwd"):
+        rooflines[k] = ("hbm", gbs(k), PEAK_HBM_GBS, "GB/s")
     dom = max((k for k in st if k in rooflines), key=lambda k: st[k])
     bound, ach, peak, unit = rooflines[dom]
     roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
