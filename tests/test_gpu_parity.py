@@ -167,19 +167,19 @@ def test_bin_sort_overflow_and_empty():
 def test_radius_modes_projection_and_binning(name, tile, mode):
     """Opacity-aware and eigenvalue-square screen boxes: radii, tile counts and
     visibility equal the oracle's away from decision boundaries, and binning
-    of the GPU's own projection is bit-exact against the oracle's."""
+    of the oracle's float32 projection is bit-exact on the GPU."""
     s = scene(name)
     g = G.gpu_project(s, tile, radius_mode=mode)
-    _, projs, _ = G.oracle_views(s, tile, radius_mode=mode)
+    _, projs, arrs = G.oracle_views(s, tile, radius_mode=mode)
     for v, pr in enumerate(projs):
         ok = pr["margin"] >= PROJ_MARGIN
         assert (~ok).sum() <= 2e-3 * s.n + 5
         np.testing.assert_array_equal((g["flags"][v] & 1).astype(bool)[ok], pr["visible"].astype(bool)[ok])
         np.testing.assert_array_equal(g["radii"][v][ok], pr["radii"].T[ok])
         np.testing.assert_array_equal(g["tiles"][v][ok], pr["tiles"][ok])
-    keys, vals, ranges, offs = G.oracle_binning(g, s.sizes, tile)
+    keys, vals, ranges, offs = G.oracle_binning(arrs, s.sizes, tile)
     M = len(keys)
-    it, ig, rg, info = G.gpu_bin_sort(g, s.sizes, tile, M + 100)
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, tile, M + 100)
     G.say(f"[radius mode {mode}] {name} tile={tile} M={M}")
     assert info[1] == M and info[2] == 0
     np.testing.assert_array_equal(ig[:M], vals)
@@ -188,12 +188,12 @@ def test_radius_modes_projection_and_binning(name, tile, mode):
 
 def test_densify_stats_parity():
     """Densification statistics of two accumulated steps against the oracle,
-    on the GPU's own visibility and radii and seeded 2-D gradients."""
+    on the oracle's visibility and radii and seeded 2-D gradients."""
     import torch
     from paper_2606_11390_amd import binding as B
     s = scene("multi")
     V, N = s.n_views, s.n
-    g = G.gpu_project(s, 16)
+    _, _, arrs = G.oracle_views(s, 16)
     rng = np.random.default_rng(12)
     acc_g = torch.zeros(N, device="cuda")
     cnt = torch.zeros(N, dtype=torch.int32, device="cuda")
@@ -201,10 +201,10 @@ def test_densify_stats_parity():
     acc = None
     for _ in range(2):
         grad2d = rng.standard_normal((V, N, 9)).astype(np.float32)
-        B.densify_stats(G.dev(grad2d.reshape(-1)), G.dev(g["flags"].reshape(-1)), G.dev(g["radii"].reshape(-1)),
-                        N, s.sizes, acc_g, cnt, mr)
-        acc = oracle.densify_stats([grad2d[v, :, :2].T for v in range(V)], [g["flags"][v] & 1 for v in range(V)],
-                                   [g["radii"][v].T for v in range(V)], s.sizes, acc)
+        B.densify_stats(G.dev(grad2d.reshape(-1)), G.dev(arrs["flags"].reshape(-1)),
+                        G.dev(arrs["radii"].reshape(-1)), N, s.sizes, acc_g, cnt, mr)
+        acc = oracle.densify_stats([grad2d[v, :, :2].T for v in range(V)], [arrs["flags"][v] & 1 for v in range(V)],
+                                   [arrs["radii"][v].T for v in range(V)], s.sizes, acc)
     np.testing.assert_array_equal(G.host(cnt), acc["count"])
     np.testing.assert_array_equal(G.host(mr), acc["max_radius"])
     assert G.rel_max(G.host(acc_g), acc["grad"]) <= 1e-6
