@@ -40,8 +40,10 @@ __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, fl
     const long long total = L.chunk_off[L.count];
     const long long stride = (long long)gridDim.x * blockDim.x;
     const float t = (float)(*step_dev + 1);
-    const float bc1 = 1.0f - exp2f(t * log2f(b1));
-    const float rbc2 = 1.0f / sqrtf(1.0f - exp2f(t * log2f(b2)));
+    // 1 - b^t = -expm1(t log1p(b - 1)): b - 1 is exact for b in [0.5, 1], and
+    // the form keeps full relative precision for b close to 1 (b2 = 0.999)
+    const float bc1 = -expm1f(t * log1pf(b1 - 1.0f));
+    const float rbc2 = 1.0f / sqrtf(-expm1f(t * log1pf(b2 - 1.0f)));
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
         int k = 0;
         while (k + 1 < L.count && L.chunk_off[k + 1] <= c) k++;

@@ -75,6 +75,9 @@ def test_opacity_radius_changes_work_not_images():
     as the 3-sigma box, bit for bit, from fewer intersections, and its
     gradients agree to float32 accumulation order."""
     s = scenes.tiny(seed=21, n_gaussians=1500, width=100, height=75, focal=90.0)
+    # wide splats across the whole opacity range, so that many are clipped
+    s.opacity_logits[:] = np.linspace(-5.5, 4.0, s.n).astype(np.float32)
+    s.log_scales[:] += np.float32(1.0)
     out = []
     for mode in (0, 1):
         r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=16, capacity=1 << 16, radius_mode=mode)
