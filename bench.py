@@ -291,6 +291,17 @@ def main():
         log(f"batched, opacity-aware radius: {mso:.3f} ms/step, {pixels / mso / 1e3:.1f} MP/s, M={mo}")
         del ro
         torch.cuda.empty_cache()
+        # the same step on the parameters in 3-D Morton order (the paper's
+        # densification-time locality pass; the permutation is not timed)
+        Pm, _ = R.morton_permute(P)
+        P_orig = P
+        P = Pm
+        rm, mm, msm = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]))
+        result["batched_morton_order"] = {"ms_per_step": msm, "mp_per_s": pixels / msm / 1e3}
+        log(f"batched, Morton-ordered Gaussians: {msm:.3f} ms/step, {pixels / msm / 1e3:.1f} MP/s, M={mm}")
+        P = P_orig
+        del rm, Pm
+        torch.cuda.empty_cache()
         r_main, m, ms_main = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]))
         log(f"batched (tile {tuned['tile']}, blocks {tuned['block']} / {tuned['block_bwd']}): {ms_main:.3f} ms/step, "
             f"{pixels / ms_main / 1e3:.1f} MP/s, M={m}")
@@ -355,6 +366,8 @@ def main():
         "gaussians_per_s": round(gauss / ms_main * 1e3, 1),
         "plain": {k: round(v, 4) for k, v in result.get("plain", {}).items()},
         "batched_same_tile": result.get("batched_same_tile"),
+        "batched_morton_order": ({k: round(v, 4) for k, v in result["batched_morton_order"].items()}
+                                 if "batched_morton_order" in result else None),
         "batched_opacity_radius": ({k: round(v, 4) for k, v in result["batched_opacity_radius"].items()}
                                    if "batched_opacity_radius" in result else None),
         "autotuned": tuned,

@@ -339,9 +339,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     bool any = false;
     for (int v = 0; v < vt.n_views; v++) any |= (flags[(long long)v * N + g] & GS_FLAG_VISIBLE) != 0;
 
-    const float mu[3] = {means[g], means[N + g], means[2 * N + g]};
-    const float ls[3] = {log_scales[g], log_scales[N + g], log_scales[2 * N + g]};
-    const float q[4] = {quats[g], quats[N + g], quats[2 * N + g], quats[3 * N + g]};
+    // a Gaussian no view sees gets zero gradients without reading its
+    // parameters (whole cache lines are skipped when such Gaussians are
+    // contiguous, e.g. in Morton order)
+    float mu[3] = {0.0f, 0.0f, 0.0f}, ls[3] = {0.0f, 0.0f, 0.0f}, q[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+    if (any) {
+        for (int i = 0; i < 3; i++) mu[i] = means[i * N + g];
+        for (int i = 0; i < 3; i++) ls[i] = log_scales[i * N + g];
+        for (int i = 0; i < 4; i++) q[i] = quats[i * N + g];
+    }
     const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     const float iq = any ? 1.0f / sqrtf(qn2) : 0.0f;
     const float qh[4] = {q[0] * iq, q[1] * iq, q[2] * iq, q[3] * iq};
@@ -454,7 +460,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     gq[3] = 2.0f * (-2.0f * zq * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0f * zq * gR[4] +
                     y * gR[5] + x * gR[6] + y * gR[7]);
     const float qd = w * gq[0] + x * gq[1] + y * gq[2] + zq * gq[3];
-    const float sigma = 1.0f / (1.0f + expf(-opac[g]));
+    const float sigma = any ? 1.0f / (1.0f + expf(-opac[g])) : 0.0f;
 
     for (int i = 0; i < 3; i++) d_means[i * N + g] = any ? gmu[i] : 0.0f;
     for (int i = 0; i < 3; i++) d_log_scales[i * N + g] = any ? gl[i] : 0.0f;

@@ -178,6 +178,26 @@ def params_to_device(scene, device="cuda"):
     return P, cams
 
 
+def morton_permute(P, bits=10):
+    """The paper's locality pass (Section 5, run at densification time):
+    reorder every parameter tensor by the 3-D Morton code of the means on a
+    2^bits grid over their bounding box.  Returns the permuted copies and the
+    order (new index i holds old Gaussian order[i])."""
+    means = P["means"]
+    n = means.shape[1]
+    lo = means.min(dim=1).values.cpu().numpy().astype(np.float64)
+    hi = means.max(dim=1).values.cpu().numpy().astype(np.float64)
+    inv = (1 << bits) / np.maximum(hi - lo, 1e-30)
+    ws = torch.empty(max(1, B.morton_workspace_size(n)), dtype=torch.uint8, device=means.device)
+    order = torch.empty(n, dtype=torch.int32, device=means.device)
+    B.morton_order(means, lo.astype(np.float32), inv.astype(np.float32), ws, order)
+    out = {}
+    for k, t in P.items():
+        out[k] = torch.empty_like(t)
+        B.gather_columns(t, order, out[k])
+    return out, order
+
+
 def packed_targets(scene, device="cuda"):
     return torch.from_numpy(np.concatenate([t.reshape(-1) for t in scene.targets])).to(device)
 
