@@ -8,35 +8,37 @@
 //   stop before T would drop below 1e-4, C += alpha T c, T *= 1 - alpha.
 //
 // GPU organisation.  A work unit is one wavefront on a BW x BH block of a
-// tile; lane l owns P horizontally adjacent pixels of one row.  Every lane of
-// a wave walks the same list position at the same time, so each splat index
-// and record has a wave-uniform address: the compiler issues scalar (SMEM)
-// loads through the scalar cache and the VALU reads the record from SGPRs.
-// This replaces the usual LDS staging (a broadcast LDS read still returns 64
-// copies of the data through the LDS return path; an SGPR operand is free).
-// Each record carries a conservative pixel box of its alpha >= 1/255 region;
-// a wave whose block misses the box skips the record with scalar-ALU compares
-// only, which cannot change any result since every pixel outside the box
-// would have skipped the entry anyway.  Waves of a tile never synchronise;
-// each stops as soon as all of its pixels have terminated (ballot).  The
-// backward walks the same list from the back, recovers T before each entry by
-// dividing by (1 - alpha), and pre-reduces the nine per-Gaussian gradient
-// values across the wave with DPP before nine lanes issue one float atomic.
+// tile; lane l owns P horizontally adjacent pixels of one row.  The wave walks
+// its tile's list in batches of 64 entries: lane l gathers entry k0 + l (its
+// splat index, then its 48-byte record) with vector loads, so a batch puts 64
+// independent gathers in flight, and the next batch is requested before the
+// current one is composited.  Each record carries a conservative pixel box of
+// its alpha >= 1/255 region; every lane tests its own entry against the
+// wave's block and a ballot leaves the entries that can touch it, which
+// cannot change any result since every pixel outside the box would have
+// skipped the entry anyway.  The wave then composites the surviving entries
+// in list order, broadcasting each record from its lane (readlane) so that
+// the per-pixel arithmetic takes it as uniform operands.  Waves of a tile
+// never synchronise; each stops as soon as all of its pixels have terminated
+// (ballot).  The backward walks the same list from the back in the same
+// batches, recovers T before each entry by dividing by (1 - alpha), and
+// pre-reduces the nine per-Gaussian gradient values across the wave with DPP
+// before nine lanes issue one float atomic.
 #include "gs_device.h"
 
 namespace gs {
 namespace {
 
+// One list entry per lane: the 48-byte record of its splat, fetched with
+// vector loads so that a whole batch of gathers is in flight at once.
 struct Rec {
-    float u, v, m00, m10, m11, ls, r, g, b, sigma;
-    int bx, by;
+    float4 a, b, c;   // u, v, m00, m10 | m11, log2 sigma, r, g | b, sigma, box x, box y
 };
 
 __device__ __forceinline__ Rec load_rec(const float* __restrict__ base, int gid)
 {
     const float4* p = reinterpret_cast<const float4*>(base + (size_t)gid * GS_SPLAT_FLOATS);
-    const float4 a = p[0], b = p[1], c = p[2];
-    return Rec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, __float_as_int(c.z), __float_as_int(c.w)};
+    return Rec{p[0], p[1], p[2]};
 }
 
 // does the packed [lo, hi] int16 range miss [b0, b1]?
@@ -45,6 +47,11 @@ __device__ __forceinline__ bool misses(int packed, int b0, int b1)
     const int lo = (int)(short)(packed & 0xFFFF);
     const int hi = packed >> 16;
     return hi < b0 || lo > b1;
+}
+
+__device__ __forceinline__ float lane_f(float x, int j)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
 
 // A wave covers a BW x BH pixel block; BW / P lanes per pixel row.
@@ -108,37 +115,60 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
     }
     const int2 r = ranges[gt];
     const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
-    // software pipeline: record k+1 and index k+2 are requested before entry
-    // k is composited, so the scalar-load latency overlaps the VALU work
-    Rec nxt = r.x < r.y ? load_rec(base, gids[r.x]) : Rec{};
-    int gnext = r.x + 1 < r.y ? gids[r.x + 1] : 0;
-    for (int k = r.x; k < r.y; k++) {
-        const Rec s = nxt;
-        if (k + 1 < r.y) nxt = load_rec(base, gnext);
-        if (k + 2 < r.y) gnext = gids[k + 2];
-        bool all_done = true;
+    const int lane = __lane_id();
+    // batches of GS_WAVE list entries, one per lane.  Loads run ahead: while
+    // batch b is composited, the records of batch b + 1 and the splat indices
+    // of batch b + 2 are in flight.  Indices past the list end are clamped to
+    // its last entry, so every load is unconditional and in bounds.
+    if (r.y > r.x) {
+        const int kl = r.y - 1;
+        int g_nxt = gids[min(r.x + GS_WAVE + lane, kl)];
+        Rec cur = load_rec(base, gids[min(r.x + lane, kl)]);
+        bool alive = true;
+        for (int kb = r.x; alive && kb < r.y; kb += GS_WAVE) {
+            const Rec nxt = load_rec(base, g_nxt);
+            const int g_nn = gids[min(kb + 2 * GS_WAVE + lane, kl)];
+            // lane-parallel cull: entries whose alpha box misses this wave's
+            // block cannot change any of its pixels
+            const bool hit = kb + lane < r.y && !misses(__float_as_int(cur.c.z), U.bx0, bx1) &&
+                             !misses(__float_as_int(cur.c.w), U.by0, by1);
+            unsigned long long mask = __ballot(hit);
+            while (mask) {
+                bool all_done = true;
 #pragma unroll
-        for (int p = 0; p < P; p++) all_done = all_done && done[p];
-        if (__ballot(!all_done) == 0ull) break;
-        if (misses(s.bx, U.bx0, bx1) || misses(s.by, U.by0, by1)) continue;
-        const float dy = s.v - fy;
-        const int k1 = k - r.x + 1;
+                for (int p = 0; p < P; p++) all_done = all_done && done[p];
+                if (__ballot(!all_done) == 0ull) {
+                    alive = false;
+                    break;
+                }
+                const int j = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const float su = lane_f(cur.a.x, j), sv = lane_f(cur.a.y, j);
+                const float m00 = lane_f(cur.a.z, j), m10 = lane_f(cur.a.w, j);
+                const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
+                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
+                const float dy = sv - fy;
+                const int k1 = kb + j - r.x + 1;
 #pragma unroll
-        for (int p = 0; p < P; p++) {
-            const Falloff f = falloff(s.u - fx[p], dy, s.m00, s.m10, s.m11, s.ls);
-            const float al = fminf(f.araw, kAlphaMax);
-            bool ok = !done[p] && al >= kAlphaMin;
-            const float Tn = __builtin_fmaf(-T[p], al, T[p]);
-            const bool stop = ok && Tn < kTMin;
-            if (COUNT) stopk[p] = stop ? k1 : stopk[p];
-            done[p] = done[p] || stop;
-            ok = ok && !stop;
-            const float wgt = ok ? al * T[p] : 0.0f;
-            C0[p] = __builtin_fmaf(wgt, s.r, C0[p]);
-            C1[p] = __builtin_fmaf(wgt, s.g, C1[p]);
-            C2[p] = __builtin_fmaf(wgt, s.b, C2[p]);
-            T[p] = ok ? Tn : T[p];
-            last[p] = ok ? k1 : last[p];
+                for (int p = 0; p < P; p++) {
+                    const Falloff f = falloff(su - fx[p], dy, m00, m10, m11, ls);
+                    const float al = fminf(f.araw, kAlphaMax);
+                    bool ok = !done[p] && al >= kAlphaMin;
+                    const float Tn = __builtin_fmaf(-T[p], al, T[p]);
+                    const bool stop = ok && Tn < kTMin;
+                    if (COUNT) stopk[p] = stop ? k1 : stopk[p];
+                    done[p] = done[p] || stop;
+                    ok = ok && !stop;
+                    const float wgt = ok ? al * T[p] : 0.0f;
+                    C0[p] = __builtin_fmaf(wgt, cr, C0[p]);
+                    C1[p] = __builtin_fmaf(wgt, cg, C1[p]);
+                    C2[p] = __builtin_fmaf(wgt, cb, C2[p]);
+                    T[p] = ok ? Tn : T[p];
+                    last[p] = ok ? k1 : last[p];
+                }
+            }
+            cur = nxt;
+            g_nxt = g_nn;
         }
     }
     const long long po = U.v < 0 ? 0 : vt.pix_off[U.v];
@@ -197,68 +227,84 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
         kmax = max(kmax, last[p]);
     }
     // the wave maximum is uniform; readfirstlane lets the compiler know, so the
-    // loop stays scalar and the record fetches stay scalar loads
+    // batch loop's control stays scalar
     kmax = __builtin_amdgcn_readfirstlane(wave_max_i(kmax));
     const int2 r = ranges[gt];
     kmax = min(kmax, r.y - r.x);
     const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
     float* gbase = grad2d + (size_t)U.v * (size_t)N * GS_GRAD_FLOATS;
     const int lane = __lane_id();
-    const int kend = r.x + kmax - 1;
-    int gcur = kend >= r.x ? gids[kend] : 0;
-    Rec nxt = kend >= r.x ? load_rec(base, gcur) : Rec{};
-    int gnext = kend - 1 >= r.x ? gids[kend - 1] : 0;
-    for (int k = kend; k >= r.x; k--) {
-        const int gid = gcur;
-        const Rec s = nxt;
-        if (k - 1 >= r.x) {
-            nxt = load_rec(base, gnext);
-            gcur = gnext;
-        }
-        if (k - 2 >= r.x) gnext = gids[k - 2];
-        if (misses(s.bx, U.bx0, bx1) || misses(s.by, U.by0, by1)) continue;
-        const float inv_sig = __builtin_amdgcn_rcpf(s.sigma);
-        const float dy = s.v - fy;
-        const int kk = k - r.x;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
-        bool any = false;
+    // batches walk the list from its last contributing entry backwards: lane
+    // l of the batch starting at kb holds entry kb - l.  As in the forward,
+    // the next batch's records and the one after's indices are in flight
+    // while a batch is processed; indices before the list start are clamped.
+    if (kmax > 0) {
+        const int kend = r.x + kmax - 1;
+        int g_cur = gids[max(kend - lane, r.x)];
+        int g_nxt = gids[max(kend - GS_WAVE - lane, r.x)];
+        Rec cur = load_rec(base, g_cur);
+        for (int kb = kend; kb >= r.x; kb -= GS_WAVE) {
+            const Rec nxt = load_rec(base, g_nxt);
+            const int g_nn = gids[max(kb - 2 * GS_WAVE - lane, r.x)];
+            const bool hit = kb - lane >= r.x && !misses(__float_as_int(cur.c.z), U.bx0, bx1) &&
+                             !misses(__float_as_int(cur.c.w), U.by0, by1);
+            unsigned long long mask = __ballot(hit);
+            while (mask) {
+                const int j = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int gid = __builtin_amdgcn_readlane(g_cur, j);
+                const float su = lane_f(cur.a.x, j), sv = lane_f(cur.a.y, j);
+                const float m00 = lane_f(cur.a.z, j), m10 = lane_f(cur.a.w, j);
+                const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
+                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
+                const float inv_sig = __builtin_amdgcn_rcpf(lane_f(cur.c.y, j));
+                const float dy = sv - fy;
+                const int kk = kb - j - r.x;
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
+                bool any = false;
 #pragma unroll
-        for (int p = 0; p < P; p++) {
-            const float dx = s.u - fx[p];
-            const Falloff f = falloff(dx, dy, s.m00, s.m10, s.m11, s.ls);
-            const float al = fminf(f.araw, kAlphaMax);
-            const bool ok = kk < last[p] && al >= kAlphaMin;
-            any = any || ok;
-            const float om = 1.0f - al;
-            const float rom = __builtin_amdgcn_rcpf(om);
-            const float Tk = T[p] * rom;
-            const float wgt = al * Tk;
-            const float d0 = s.r - S0[p], d1 = s.g - S1[p], d2 = s.b - S2[p];
-            float ga = Tk * (d0 * g0[p] + d1 * g1[p] + d2 * g2[p]);
-            if (HAS_DA) ga = __builtin_fmaf(gA[p], rom, ga);
-            const bool unc = ok && f.araw < kAlphaMax;
-            const float gq = unc ? -kLn2 * al * ga : 0.0f;
-            a6 += ok ? wgt * g0[p] : 0.0f;
-            a7 += ok ? wgt * g1[p] : 0.0f;
-            a8 += ok ? wgt * g2[p] : 0.0f;
-            a5 += unc ? f.araw * inv_sig * ga : 0.0f;
-            // q' = |M^T d|^2:  dq'/du = 2 (M w)_x, dq'/dv = 2 (M w)_y
-            a0 += 2.0f * gq * (s.m00 * f.w0);
-            a1 += 2.0f * gq * (s.m10 * f.w0 + s.m11 * f.w1);
-            // q' = c0 (A dx^2 + 2 B dx dy + C dy^2)
-            a2 += gq * kC0 * dx * dx;
-            a3 += gq * (2.0f * kC0) * dx * dy;
-            a4 += gq * kC0 * dy * dy;
-            S0[p] = ok ? __builtin_fmaf(al, d0, S0[p]) : S0[p];
-            S1[p] = ok ? __builtin_fmaf(al, d1, S1[p]) : S1[p];
-            S2[p] = ok ? __builtin_fmaf(al, d2, S2[p]) : S2[p];
-            T[p] = ok ? Tk : T[p];
+                for (int p = 0; p < P; p++) {
+                    const float dx = su - fx[p];
+                    const Falloff f = falloff(dx, dy, m00, m10, m11, ls);
+                    const float al = fminf(f.araw, kAlphaMax);
+                    const bool ok = kk < last[p] && al >= kAlphaMin;
+                    any = any || ok;
+                    const float om = 1.0f - al;
+                    const float rom = __builtin_amdgcn_rcpf(om);
+                    const float Tk = T[p] * rom;
+                    const float wgt = al * Tk;
+                    const float d0 = cr - S0[p], d1 = cg - S1[p], d2 = cb - S2[p];
+                    float ga = Tk * (d0 * g0[p] + d1 * g1[p] + d2 * g2[p]);
+                    if (HAS_DA) ga = __builtin_fmaf(gA[p], rom, ga);
+                    const bool unc = ok && f.araw < kAlphaMax;
+                    const float gq = unc ? -kLn2 * al * ga : 0.0f;
+                    a6 += ok ? wgt * g0[p] : 0.0f;
+                    a7 += ok ? wgt * g1[p] : 0.0f;
+                    a8 += ok ? wgt * g2[p] : 0.0f;
+                    a5 += unc ? f.araw * inv_sig * ga : 0.0f;
+                    // q' = |M^T d|^2:  dq'/du = 2 (M w)_x, dq'/dv = 2 (M w)_y
+                    a0 += 2.0f * gq * (m00 * f.w0);
+                    a1 += 2.0f * gq * (m10 * f.w0 + m11 * f.w1);
+                    // q' = c0 (A dx^2 + 2 B dx dy + C dy^2)
+                    a2 += gq * kC0 * dx * dx;
+                    a3 += gq * (2.0f * kC0) * dx * dy;
+                    a4 += gq * kC0 * dy * dy;
+                    S0[p] = ok ? __builtin_fmaf(al, d0, S0[p]) : S0[p];
+                    S1[p] = ok ? __builtin_fmaf(al, d1, S1[p]) : S1[p];
+                    S2[p] = ok ? __builtin_fmaf(al, d2, S2[p]) : S2[p];
+                    T[p] = ok ? Tk : T[p];
+                }
+                if (__ballot(any) == 0ull) continue;
+                const float acc[GS_GRAD_FLOATS] = {a0, a1, a2, a3, a4, a5, a6, a7, a8};
+                int jj;
+                const float x = wave_sum9_scatter(acc, jj);
+                if (lane < 16 && jj < GS_GRAD_FLOATS)
+                    unsafeAtomicAdd(gbase + (size_t)gid * GS_GRAD_FLOATS + jj, x);
+            }
+            cur = nxt;
+            g_cur = g_nxt;
+            g_nxt = g_nn;
         }
-        if (__ballot(any) == 0ull) continue;
-        const float acc[GS_GRAD_FLOATS] = {a0, a1, a2, a3, a4, a5, a6, a7, a8};
-        int j;
-        const float x = wave_sum9_scatter(acc, j);
-        if (lane < 16 && j < GS_GRAD_FLOATS) unsafeAtomicAdd(gbase + (size_t)gid * GS_GRAD_FLOATS + j, x);
     }
 }
 
