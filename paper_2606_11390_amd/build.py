@@ -20,6 +20,12 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include")]
 
 
+# per-file additions: the rasterisers' work-queue atomics are issued by one
+# lane and their result is read a whole tile later; the atomic optimizer would
+# rewrite them into a wave-aggregated form that reads the result at once
+FILE_FLAGS = {"raster.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
@@ -31,7 +37,7 @@ def build(verbose=False, jobs=8):
     objs, procs = [], []
     for src in sources():
         obj = os.path.join(outdir, os.path.basename(src)[:-4] + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), src))

@@ -308,6 +308,22 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
     }
 }
 
+// claim the next work item of a persistent wave: lane 0 takes a ticket; the
+// ticket is read (made wave-uniform) only when it is needed
+__device__ __forceinline__ int claim(int* queue)
+{
+    int item = 0;
+    if (__lane_id() == 0) item = atomicAdd(queue, 1);
+    return item;
+}
+
+__device__ __forceinline__ int ticket(int pending)
+{
+    // keeps the read (and the wait for the atomic's return) where it is written
+    asm volatile("" : "+v"(pending));
+    return __builtin_amdgcn_readfirstlane(pending);
+}
+
 template <int TS, int BW, int P, bool COUNT>
 __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_fwd(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
@@ -329,14 +345,15 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
 {
     using L = Layout<TS, BW, P>;
     const int n_items = vt.total_tiles * L::WPT;
-    for (;;) {
-        int item = 0;
-        if (__lane_id() == 0) item = atomicAdd(queue, 1);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= n_items) break;
+    // the next item is claimed before the current one is processed, so the
+    // queue atomic's round trip overlaps the compositing
+    int item = ticket(claim(queue));
+    while (item < n_items) {
+        const int next = claim(queue);
         const int gt = order[item / L::WPT];
         fwd_unit<TS, BW, P, false>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, img,
                                    Tout, lastout, nullptr);
+        item = ticket(next);
     }
 }
 
@@ -362,14 +379,13 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
 {
     using L = Layout<TS, BW, P>;
     const int n_items = vt.total_tiles * L::WPT;
-    for (;;) {
-        int item = 0;
-        if (__lane_id() == 0) item = atomicAdd(queue, 1);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= n_items) break;
+    int item = ticket(claim(queue));
+    while (item < n_items) {
+        const int next = claim(queue);
         const int gt = order[item / L::WPT];
         bwd_unit<TS, BW, P, HAS_DA>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, Tfin,
                                     nlast, dimg, dalpha, grad2d);
+        item = ticket(next);
     }
 }
 
