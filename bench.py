@@ -8,9 +8,12 @@ backward to every parameter.  Inputs are seeded and synthetic and resident in
 HBM before timing starts.
 
 Two paths are timed on the same inputs:
-  plain   - one workgroup per tile, every call launched eagerly;
-  batched - persistent rasterisers fed by a heavy-first (view, tile) queue and
-            the whole step replayed from one captured HIP graph.
+  plain   - one workgroup per tile in tile order, every call launched eagerly
+            (per view, for several views);
+  batched - all views in one launch per call, the rasterisers' tile order
+            (band per XCD, heavy-first dispatch or a persistent heavy-first
+            queue), tile edge and wave blocks autotuned, and the whole step
+            replayed from one captured HIP graph.
 The reported ``value`` is the batched path's megapixels/s; the plain path's
 figure is reported beside it.  The roofline object covers the kernel with the
 largest share of the step, timed with HIP events on the launch stream.  The
@@ -78,7 +81,7 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
     out["raster_fwd"] = timed(r.raster_fwd, steps, torch)
     out["loss"] = timed(lambda: r.loss_l2(tg), steps, torch)
     from paper_2606_11390_amd import binding as B
-    s, q = r._sched()
+    s, q = r._sched(r.order_bwd)
     out["raster_bwd"] = timed(lambda: B.rasterize_bwd(r.splats, r.isect_gid, r.ranges, r.n, r.sizes, r.tile,
                                                       r.background, s, q, r.T_final, r.n_contrib, r.d_images,
                                                       None, r.grad2d, accumulate=True, block=r.block_bwd),
@@ -212,9 +215,15 @@ def main():
     gauss = scene.n * scene.n_views
     result = {}
 
-    def run_path(persistent, graph, tile=None, block=(0, 0), block_bwd=None, radius_mode=0):
-        r = R.Renderer(scene.n, scene.sh_degree, scene.sizes, tile=tile or args.tile, capacity=1 << 22,
-                       persistent=persistent, block=block, block_bwd=block_bwd, radius_mode=radius_mode)
+    def run_path(cfg, graph, radius_mode=0):
+        """cfg: None for the plain path (tile order, default wave block, tile
+        edge --tile), else an autotuned configuration."""
+        if cfg is None:
+            r = R.Renderer(scene.n, scene.sh_degree, scene.sizes, tile=args.tile, capacity=1 << 22)
+        else:
+            r = R.Renderer(scene.n, scene.sh_degree, scene.sizes, tile=cfg["tile"], capacity=1 << 22,
+                           block=tuple(cfg["block"]), block_bwd=tuple(cfg["block_bwd"]), order=cfg["order"],
+                           order_bwd=cfg["order_bwd"], radius_mode=radius_mode)
         m = r.fit_capacity(P, cams)
         if graph:
             r.capture(P, cams, tg, grads, warmup=max(1, args.warmup))
@@ -259,7 +268,7 @@ def main():
         if scene.n_views > 1:
             r_plain, m, ms_plain = run_plain_per_view()
         else:
-            r_plain, m, ms_plain = run_path(False, False)
+            r_plain, m, ms_plain = run_path(None, False)
         result["plain"] = {"ms_per_step": ms_plain, "mp_per_s": pixels / ms_plain / 1e3}
         log(f"plain: {ms_plain:.3f} ms/step, {pixels / ms_plain / 1e3:.1f} MP/s, M={m}")
         if args.only == "plain":
@@ -274,18 +283,18 @@ def main():
         tuned = R.autotune(P, cams, tg, scene.sh_degree, scene.sizes, tiles=tiles, steps=max(3, args.steps // 4),
                            log=log)
         tuned.pop("trials", None)
-        if args.tile in tiles and tuned["tile"] != args.tile:
+        per_tile = tuned.pop("per_tile", {})
+        if str(args.tile) in per_tile and tuned["tile"] != args.tile:
             # like-for-like figure at the plain path's tile edge
-            t16 = R.autotune(P, cams, tg, scene.sh_degree, scene.sizes, tiles=(args.tile,), steps=3)
-            r16, _, ms16 = run_path(True, True, args.tile, tuple(t16["block"]), tuple(t16["block_bwd"]))
-            result["batched_same_tile"] = {"tile": args.tile, "block": t16["block"], "block_bwd": t16["block_bwd"],
-                                           "ms_per_step": ms16, "mp_per_s": pixels / ms16 / 1e3}
+            t16 = per_tile[str(args.tile)]
+            r16, _, ms16 = run_path(t16, True)
+            result["batched_same_tile"] = dict(t16, ms_per_step=ms16, mp_per_s=pixels / ms16 / 1e3)
+            result["batched_same_tile"].pop("step_ms", None)
             del r16
             torch.cuda.empty_cache()
         # the same step with the opacity-aware screen box: identical images and
         # gradients from fewer intersections (reported beside the headline)
-        ro, mo, mso = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]),
-                               radius_mode=B.RADIUS_OPACITY)
+        ro, mo, mso = run_path(tuned, True, radius_mode=B.RADIUS_OPACITY)
         result["batched_opacity_radius"] = {"ms_per_step": mso, "mp_per_s": pixels / mso / 1e3,
                                             "intersections": int(mo)}
         log(f"batched, opacity-aware radius: {mso:.3f} ms/step, {pixels / mso / 1e3:.1f} MP/s, M={mo}")
@@ -296,14 +305,15 @@ def main():
         Pm, _ = R.morton_permute(P)
         P_orig = P
         P = Pm
-        rm, mm, msm = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]))
+        rm, mm, msm = run_path(tuned, True)
         result["batched_morton_order"] = {"ms_per_step": msm, "mp_per_s": pixels / msm / 1e3}
         log(f"batched, Morton-ordered Gaussians: {msm:.3f} ms/step, {pixels / msm / 1e3:.1f} MP/s, M={mm}")
         P = P_orig
         del rm, Pm
         torch.cuda.empty_cache()
-        r_main, m, ms_main = run_path(True, True, tuned["tile"], tuple(tuned["block"]), tuple(tuned["block_bwd"]))
-        log(f"batched (tile {tuned['tile']}, blocks {tuned['block']} / {tuned['block_bwd']}): {ms_main:.3f} ms/step, "
+        r_main, m, ms_main = run_path(tuned, True)
+        log(f"batched (tile {tuned['tile']}, orders {tuned['order']} / {tuned['order_bwd']}, blocks {tuned['block']} / "
+            f"{tuned['block_bwd']}): {ms_main:.3f} ms/step, "
             f"{pixels / ms_main / 1e3:.1f} MP/s, M={m}")
 
     # per-call durations on the main path, HIP events on the launch stream
@@ -358,7 +368,8 @@ def main():
                                f"{scene.n_views} view(s) {'+'.join(f'{w}x{h}' for w, h in scene.sizes)}, "
                                f"FP32 forward + L2 loss + backward",
                    "tile": r_main.tile, "wave_block_fwd": list(r_main.block),
-                   "wave_block_bwd": list(r_main.block_bwd),
+                   "wave_block_bwd": list(r_main.block_bwd), "tile_order_fwd": r_main.order,
+                   "tile_order_bwd": r_main.order_bwd,
                    "path": "batched" if args.only != "plain" else "plain",
                    "gaussians": scene.n, "views": scene.n_views, "pixels": pixels,
                    "intersections": int(info[B.INFO_ISECT]), "visible": int(info[B.INFO_VISIBLE]),

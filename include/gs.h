@@ -205,11 +205,22 @@ size_t gs_tile_schedule_size(int64_t total_tiles);
 
 /*
  * gs_tile_schedule - order tiles by decreasing list length (ties by tile
- * id) for the persistent rasterisers, so that long tiles start first.
- * Writes order[T_total] (int32 global tile ids) at the start of `schedule`.
+ * id), so that long tiles start first.  Writes order[T_total] (int32 global
+ * tile ids) at the start of `schedule` (256-byte aligned).
  */
 int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* schedule,
                      size_t schedule_bytes, void* stream);
+
+/*
+ * gs_tile_order_xcd - a static tile order for grid launches on a GPU whose
+ * workgroups are handed round-robin to n_xcd dies with private L2 caches
+ * (MI355X: 8 XCDs): workgroup b gets tile x * (T/n_xcd) + min(x, T mod n_xcd)
+ * + b / n_xcd with x = b mod n_xcd, so each die renders one contiguous band of
+ * tiles and neighbouring tiles, which share most of their splats, share an
+ * L2.  Writes order[T_total] at the start of `schedule` (same size and
+ * alignment as for gs_tile_schedule).
+ */
+int gs_tile_order_xcd(int64_t total_tiles, int n_xcd, void* schedule, size_t schedule_bytes, void* stream);
 
 /*
  * gs_rasterize_fwd - front-to-back alpha compositing (paper Section 4: the
@@ -225,10 +236,16 @@ int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* sche
  *   0, 0 selects the default (8, 1).  Valid pairs: tile 8: (8, 1); tile 16:
  *   (8, 1), (16, 1), (16, 4); tile 32: (8, 1), (16, 4), (32, 4).  The choice
  *   changes only speed, never a result bit.
- * schedule: NULL for one workgroup per tile, or a gs_tile_schedule buffer
- *   for the persistent kernel that pulls (view, tile) items from a global
- *   queue; queue (device int32[1]) is the persistent kernel's counter (reset
- *   by this call; unused when schedule is NULL).
+ * schedule, queue: how tiles are assigned to workgroups.
+ *   schedule NULL: one workgroup per tile, in tile order (queue must be NULL).
+ *   schedule set, queue NULL: one workgroup per tile, workgroup b renders
+ *     tile order[b] of the schedule buffer (gs_tile_schedule: longest lists
+ *     first; gs_tile_order_xcd: one band of tiles per XCD).
+ *   schedule and queue set: a persistent grid whose waves pull (view, tile)
+ *     items in schedule order from the global counter *queue (device int32,
+ *     reset by this call), eight items per atomic.
+ *   The order entries must be tile ids in [0, T_total); others are skipped.
+ *   None of this changes a result bit.
  * Outputs: images (packed [3][H][W] per view), T_final and n_contrib (packed
  *   [H][W] per view): final transmittance and one past the list position of
  *   the last composited entry.

@@ -44,6 +44,7 @@ _SIGS = {
     "gs_bin_sort": (_int, [_p, _p, _p, _p, _i64, _int, _p, _int, _i64, _p, _sz, _p, _p, _p, _p, _p]),
     "gs_tile_schedule_size": (_sz, [_i64]),
     "gs_tile_schedule": (_int, [_p, _i64, _p, _sz, _p]),
+    "gs_tile_order_xcd": (_int, [_i64, _int, _p, _sz, _p]),
     "gs_rasterize_fwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p]),
     "gs_rasterize_bwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p,
                                 _int, _p]),
@@ -171,6 +172,12 @@ def tile_schedule(tile_ranges, total_tiles, schedule):
     rc = lib().gs_tile_schedule(_ptr(tile_ranges, I32, "tile_ranges"), int(total_tiles),
                                 _ptr(schedule, U8, "schedule"), schedule.numel(), _stream())
     _check(rc, "gs_tile_schedule")
+
+
+def tile_order_xcd(total_tiles, n_xcd, schedule):
+    rc = lib().gs_tile_order_xcd(int(total_tiles), int(n_xcd), _ptr(schedule, U8, "schedule"), schedule.numel(),
+                                 _stream())
+    _check(rc, "gs_tile_order_xcd")
 
 
 def rasterize_fwd(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, queue, images,

@@ -629,6 +629,25 @@ hipError_t launch_tile_schedule(const int2* ranges, long long total_tiles, void*
     return radix_pass<SRC_PAIRS>(b, nb, 8, 8, hist, dtot, nullptr, st);
 }
 
+// order[b] for workgroup b of a grid launch: workgroups are handed to the
+// n_xcd XCDs round-robin (b mod n_xcd), so XCD x runs workgroups x, x + n_xcd,
+// ...; giving them consecutive tiles keeps neighbouring tiles, which share
+// most of their splats, in one XCD's L2
+__global__ void k_tile_order_xcd(uint32_t t, int n_xcd, int* __restrict__ order)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= t) return;
+    const uint32_t x = b % (uint32_t)n_xcd, q = t / (uint32_t)n_xcd, rem = t % (uint32_t)n_xcd;
+    order[b] = (int)(x * q + min(x, rem) + b / (uint32_t)n_xcd);
+}
+
+hipError_t launch_tile_order_xcd(long long total_tiles, int n_xcd, void* schedule, hipStream_t st)
+{
+    const uint32_t t = (uint32_t)total_tiles;
+    hipLaunchKernelGGL(k_tile_order_xcd, dim3((t + 255) / 256), dim3(256), 0, st, t, n_xcd, (int*)schedule);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;

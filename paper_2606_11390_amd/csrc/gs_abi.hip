@@ -39,6 +39,7 @@ hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, con
 size_t loss_workspace_size(long long n);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
 size_t morton_workspace_size(long long n);
+hipError_t launch_tile_order_xcd(long long total_tiles, int n_xcd, void* schedule, hipStream_t st);
 size_t ssim_workspace_size(const ViewTable& vt);
 hipError_t launch_ssim_l1(const ViewTable& vt, const float* img, const float* tgt, float lam, float* loss,
                           float* dimg, void* workspace, hipStream_t st);
@@ -179,6 +180,14 @@ int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* sche
                                            as_stream(stream)));
 }
 
+int gs_tile_order_xcd(int64_t total_tiles, int n_xcd, void* schedule, size_t schedule_bytes, void* stream)
+{
+    if (total_tiles < 1 || total_tiles > 0x3FFFFFFFll || n_xcd < 1 || n_xcd > 64 || !schedule) return GS_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(schedule) & 255u) != 0) return GS_ERR_ARG;
+    if (schedule_bytes < gs::tile_schedule_size(total_tiles)) return GS_ERR_WORKSPACE;
+    return status(gs::launch_tile_order_xcd(total_tiles, n_xcd, schedule, as_stream(stream)));
+}
+
 int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
                      int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
                      const float* background, const void* schedule, int32_t* queue, float* images,
@@ -190,7 +199,7 @@ int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_
     if (!gs::raster_cfg_ok(tile, block_w, px_per_lane)) return GS_ERR_ARG;
     if (!tile_ranges || !images || !T_final || !n_contrib || !background) return GS_ERR_ARG;
     if (!isect_gid || (n > 0 && (!splats || !aligned16(splats)))) return GS_ERR_ARG;
-    if (schedule && !queue) return GS_ERR_ARG;
+    if (queue && !schedule) return GS_ERR_ARG;
     for (int c = 0; c < 3; c++)
         if (!std::isfinite(background[c])) return GS_ERR_ARG;
     return status(gs::launch_raster_fwd(tile, block_w, px_per_lane, vt, splats, isect_gid,
@@ -212,7 +221,7 @@ int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_
         return GS_ERR_ARG;
     if (!gs::raster_cfg_ok(tile, block_w, px_per_lane)) return GS_ERR_ARG;
     if (n > 0 && (!splats || !aligned16(splats))) return GS_ERR_ARG;
-    if (schedule && !queue) return GS_ERR_ARG;
+    if (queue && !schedule) return GS_ERR_ARG;
     for (int c = 0; c < 3; c++)
         if (!std::isfinite(background[c])) return GS_ERR_ARG;
     if (!accumulate) {

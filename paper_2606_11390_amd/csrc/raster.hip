@@ -308,8 +308,14 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
     }
 }
 
-// claim the next work item of a persistent wave: lane 0 takes a ticket; the
-// ticket is read (made wave-uniform) only when it is needed
+// Persistent waves take work in chunks of QCHUNK items from one global
+// counter (one atomic per chunk keeps the counter off the critical path);
+// chunk c holds items c, c + n_chunks, c + 2 n_chunks, ..., so every chunk
+// mixes long and short tiles of the heavy-first order.
+constexpr int QCHUNK = 8;
+
+// claim the next chunk: lane 0 takes a ticket; the ticket is read (made
+// wave-uniform) only when it is needed
 __device__ __forceinline__ int claim(int* queue)
 {
     int item = 0;
@@ -324,16 +330,28 @@ __device__ __forceinline__ int ticket(int pending)
     return __builtin_amdgcn_readfirstlane(pending);
 }
 
+// tile of a grid workgroup: the workgroup index itself, or its entry in a
+// dispatch order (workgroups start in index order, so the order decides which
+// tiles start first and, since consecutive workgroups go to different XCDs,
+// which tiles share an L2); out-of-range entries are skipped
+__device__ __forceinline__ int tile_of_block(const int* __restrict__ order, int total_tiles)
+{
+    const int b = blockIdx.x;
+    const int gt = order ? order[b] : b;
+    return (unsigned)gt < (unsigned)total_tiles ? gt : -1;
+}
+
 template <int TS, int BW, int P, bool COUNT>
 __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_fwd(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
-    float* __restrict__ img, float* __restrict__ Tout, int* __restrict__ lastout,
-    int* __restrict__ visits)
+    const int* __restrict__ order, float* __restrict__ img, float* __restrict__ Tout,
+    int* __restrict__ lastout, int* __restrict__ visits)
 {
+    const int gt = tile_of_block(order, vt.total_tiles);
+    if (gt < 0) return;
     const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
-    fwd_unit<TS, BW, P, COUNT>(vt, blockIdx.x, wit, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout, lastout,
-                               visits);
+    fwd_unit<TS, BW, P, COUNT>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout, lastout, visits);
 }
 
 template <int TS, int BW, int P>
@@ -345,15 +363,19 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
 {
     using L = Layout<TS, BW, P>;
     const int n_items = vt.total_tiles * L::WPT;
-    // the next item is claimed before the current one is processed, so the
+    const int n_chunks = (n_items + QCHUNK - 1) / QCHUNK;
+    // the next chunk is claimed before the current one is processed, so the
     // queue atomic's round trip overlaps the compositing
-    int item = ticket(claim(queue));
-    while (item < n_items) {
+    int c = ticket(claim(queue));
+    while (c < n_chunks) {
         const int next = claim(queue);
-        const int gt = order[item / L::WPT];
-        fwd_unit<TS, BW, P, false>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, img,
-                                   Tout, lastout, nullptr);
-        item = ticket(next);
+        for (int item = c; item < n_items; item += n_chunks) {
+            const int gt = order[item / L::WPT];
+            if ((unsigned)gt < (unsigned)vt.total_tiles)
+                fwd_unit<TS, BW, P, false>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, img,
+                                           Tout, lastout, nullptr);
+        }
+        c = ticket(next);
     }
 }
 
@@ -361,12 +383,14 @@ template <int TS, int BW, int P, bool HAS_DA>
 __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_bwd(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
-    const float* __restrict__ Tfin, const int* __restrict__ nlast, const float* __restrict__ dimg,
-    const float* __restrict__ dalpha, float* __restrict__ grad2d)
+    const int* __restrict__ order, const float* __restrict__ Tfin, const int* __restrict__ nlast,
+    const float* __restrict__ dimg, const float* __restrict__ dalpha, float* __restrict__ grad2d)
 {
+    const int gt = tile_of_block(order, vt.total_tiles);
+    if (gt < 0) return;
     const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
-    bwd_unit<TS, BW, P, HAS_DA>(vt, blockIdx.x, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, dimg,
-                                dalpha, grad2d);
+    bwd_unit<TS, BW, P, HAS_DA>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, dimg, dalpha,
+                                grad2d);
 }
 
 template <int TS, int BW, int P, bool HAS_DA>
@@ -379,13 +403,17 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
 {
     using L = Layout<TS, BW, P>;
     const int n_items = vt.total_tiles * L::WPT;
-    int item = ticket(claim(queue));
-    while (item < n_items) {
+    const int n_chunks = (n_items + QCHUNK - 1) / QCHUNK;
+    int c = ticket(claim(queue));
+    while (c < n_chunks) {
         const int next = claim(queue);
-        const int gt = order[item / L::WPT];
-        bwd_unit<TS, BW, P, HAS_DA>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, Tfin,
-                                    nlast, dimg, dalpha, grad2d);
-        item = ticket(next);
+        for (int item = c; item < n_items; item += n_chunks) {
+            const int gt = order[item / L::WPT];
+            if ((unsigned)gt < (unsigned)vt.total_tiles)
+                bwd_unit<TS, BW, P, HAS_DA>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, Tfin,
+                                            nlast, dimg, dalpha, grad2d);
+        }
+        c = ticket(next);
     }
 }
 
@@ -413,15 +441,16 @@ hipError_t fwd_cfg(const ViewTable& vt, const float* splats, const int* gids, co
     using L = Layout<TS, BW, P>;
     if (visits) {
         hipLaunchKernelGGL((k_raster_fwd<TS, BW, P, true>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st,
-                           vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], img, Tout, lastout, visits);
-    } else if (order) {
+                           vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], nullptr, img, Tout, lastout, visits);
+    } else if (order && queue) {
         hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, queue);
         hipLaunchKernelGGL((k_raster_fwd_persistent<TS, BW, P>), dim3(persistent_blocks()), dim3(GS_WAVE), 0,
                            st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, queue, img, Tout,
                            lastout);
     } else {
         hipLaunchKernelGGL((k_raster_fwd<TS, BW, P, false>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0,
-                           st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], img, Tout, lastout, nullptr);
+                           st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, img, Tout, lastout,
+                           nullptr);
     }
     return hipGetLastError();
 }
@@ -432,7 +461,7 @@ hipError_t bwd_cfg(const ViewTable& vt, const float* splats, const int* gids, co
                    const float* dimg, const float* dalpha, float* grad2d, hipStream_t st)
 {
     using L = Layout<TS, BW, P>;
-    if (order) {
+    if (order && queue) {
         hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, queue);
         if (dalpha)
             hipLaunchKernelGGL((k_raster_bwd_persistent<TS, BW, P, true>), dim3(persistent_blocks()),
@@ -445,11 +474,11 @@ hipError_t bwd_cfg(const ViewTable& vt, const float* splats, const int* gids, co
     } else {
         if (dalpha)
             hipLaunchKernelGGL((k_raster_bwd<TS, BW, P, true>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT),
-                               0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], Tfin, nlast, dimg,
+                               0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, Tfin, nlast, dimg,
                                dalpha, grad2d);
         else
             hipLaunchKernelGGL((k_raster_bwd<TS, BW, P, false>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT),
-                               0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], Tfin, nlast, dimg,
+                               0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, Tfin, nlast, dimg,
                                dalpha, grad2d);
     }
     return hipGetLastError();

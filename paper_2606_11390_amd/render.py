@@ -7,6 +7,12 @@ current stream:
     gs_project -> gs_bin_sort -> [gs_tile_schedule] -> gs_rasterize_fwd
     -> gs_loss_l2 -> gs_rasterize_bwd -> gs_project_bwd
 
+The rasterisers' tile order is chosen per pass (``order``, ``order_bwd``):
+"tile" (one workgroup per tile in tile order), "xcd" (a static order giving
+each XCD one band of neighbouring tiles), "heavy" (longest lists dispatched
+first, recomputed every step) or "queue" (persistent waves pulling the heavy-
+first order from a global counter).  None of them changes a result bit.
+
 ``render()`` exposes the differentiable part as a ``torch.autograd.Function``;
 ``Renderer.step()`` runs forward + L2 loss + backward without autograd and
 without any host synchronisation, so it can be captured in a HIP graph
@@ -22,10 +28,15 @@ import torch
 from . import binding as B
 
 
+ORDERS = ("tile", "xcd", "heavy", "queue")
+# dies with private L2 caches that a grid launch is spread over round-robin
+N_XCD = 8
+
+
 class Renderer:
     def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
                  background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda",
-                 radius_mode=0):
+                 radius_mode=0, order=None, order_bwd=None):
         # screen box rule of the projection (GS_RADIUS_*)
         self.radius_mode = int(radius_mode)
         # wave pixel blocks (width, pixels per lane) of the forward and backward rasterisers
@@ -40,7 +51,12 @@ class Renderer:
         self.tile = int(tile)
         self.near, self.far, self.eps2d = float(near), float(far), float(eps2d)
         self.background = np.asarray(background, np.float32)
-        self.persistent = bool(persistent)
+        # tile order of each rasteriser pass; persistent=True selects the queue
+        self.order = order if order is not None else ("queue" if persistent else "tile")
+        self.order_bwd = order_bwd if order_bwd is not None else self.order
+        for o in (self.order, self.order_bwd):
+            if o not in ORDERS:
+                raise ValueError(f"unknown tile order {o!r}")
         self.device = torch.device(device)
         self.tiles_x, self.tile_off, self.pix_off = B.tile_grid(self.sizes, self.tile)
         self.total_tiles = int(self.tile_off[-1])
@@ -63,6 +79,8 @@ class Renderer:
         self.loss_ws = e(max(1, B.loss_workspace_size(3 * self.pixels)), dt=torch.uint8)
         self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
         self.schedule = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
+        self.schedule_xcd = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
+        B.tile_order_xcd(self.total_tiles, N_XCD, self.schedule_xcd)
         self.capacity = 0
         self.set_capacity(capacity)
         self.graph = None
@@ -92,11 +110,22 @@ class Renderer:
     def bin_sort(self):
         B.bin_sort(self.splats, self.depths, self.radii, self.tiles_touched, self.n, self.sizes, self.tile,
                    self.capacity, self.workspace, self.isect_tile, self.isect_gid, self.ranges, self.info)
-        if self.persistent:
+        if "heavy" in (self.order, self.order_bwd) or "queue" in (self.order, self.order_bwd):
             B.tile_schedule(self.ranges, self.total_tiles, self.schedule)
 
-    def _sched(self):
-        return (self.schedule, self.queue) if self.persistent else (None, None)
+    @property
+    def persistent(self):
+        return self.order == "queue"
+
+    def _sched(self, order=None):
+        order = order or self.order
+        if order == "tile":
+            return None, None
+        if order == "xcd":
+            return self.schedule_xcd, None
+        if order == "heavy":
+            return self.schedule, None
+        return self.schedule, self.queue
 
     def raster_fwd(self):
         s, q = self._sched()
@@ -104,7 +133,7 @@ class Renderer:
                         self.background, s, q, self.images, self.T_final, self.n_contrib, block=self.block)
 
     def raster_bwd(self, d_images, d_alpha=None):
-        s, q = self._sched()
+        s, q = self._sched(self.order_bwd)
         B.rasterize_bwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
                         self.background, s, q, self.T_final, self.n_contrib, d_images, d_alpha, self.grad2d,
                         block=self.block_bwd)
@@ -289,34 +318,42 @@ def autotune(P, cams, targets, sh_degree, sizes, tiles=(8, 16, 32), steps=5, cac
         if key in cache:
             return cache[key]
     grads = zeros_like_params(P)
-    trials, best = {}, None
+    trials, best, per_tile = {}, None, {}
     for tile in tiles:
-        r = Renderer(n, sh_degree, sizes, tile=tile, capacity=1 << 20, persistent=True)
+        r = Renderer(n, sh_degree, sizes, tile=tile, capacity=1 << 20, order="heavy", order_bwd="queue")
         r.fit_capacity(P, cams)
         r.step(P, cams, targets, grads)
         fwd_ms, bwd_ms = {}, {}
-        for blk in BLOCKS[tile]:
-            r.block = r.block_bwd = blk
-            r.raster_fwd()
-            fwd_ms[blk] = _time_ms(r.raster_fwd, steps)
-            r.raster_bwd(r.d_images)
-            bwd_ms[blk] = _time_ms(lambda: r.raster_bwd(r.d_images), steps)
-        r.block = min(fwd_ms, key=fwd_ms.get)
-        r.block_bwd = min(bwd_ms, key=bwd_ms.get)
+        for order in ORDERS:
+            for blk in BLOCKS[tile]:
+                r.block = r.block_bwd = blk
+                r.order = r.order_bwd = order
+                r.raster_fwd()
+                fwd_ms[(order, blk)] = _time_ms(r.raster_fwd, steps)
+                r.raster_bwd(r.d_images)
+                bwd_ms[(order, blk)] = _time_ms(lambda: r.raster_bwd(r.d_images), steps)
+        r.order, r.block = min(fwd_ms, key=fwd_ms.get)
+        r.order_bwd, r.block_bwd = min(bwd_ms, key=bwd_ms.get)
         r.raster_fwd()
         r.capture(P, cams, targets, grads, warmup=1)
         ms = _time_ms(r.replay, steps)
-        trials[f"tile{tile}"] = {"step_ms": ms, "fwd_ms": {f"{b[0]}x{b[1]}": v for b, v in fwd_ms.items()},
-                                 "bwd_ms": {f"{b[0]}x{b[1]}": v for b, v in bwd_ms.items()}}
+        trials[f"tile{tile}"] = {"step_ms": ms,
+                                 "fwd_ms": {f"{o}/{b[0]}x{b[1]}": v for (o, b), v in fwd_ms.items()},
+                                 "bwd_ms": {f"{o}/{b[0]}x{b[1]}": v for (o, b), v in bwd_ms.items()}}
         if log:
-            log(f"autotune tile {tile}: fwd block {r.block} bwd block {r.block_bwd} step {ms:.3f} ms; fwd " +
-                ", ".join(f"{b}: {v:.3f}" for b, v in fwd_ms.items()) + "; bwd " +
-                ", ".join(f"{b}: {v:.3f}" for b, v in bwd_ms.items()))
+            log(f"autotune tile {tile}: fwd {r.order} {r.block} ({fwd_ms[(r.order, r.block)]:.3f} ms), bwd "
+                f"{r.order_bwd} {r.block_bwd} ({bwd_ms[(r.order_bwd, r.block_bwd)]:.3f} ms), step {ms:.3f} ms; "
+                "fwd " + ", ".join(f"{o}/{b[0]}x{b[1]}: {v:.3f}" for (o, b), v in fwd_ms.items()) + "; bwd " +
+                ", ".join(f"{o}/{b[0]}x{b[1]}: {v:.3f}" for (o, b), v in bwd_ms.items()))
+        cfg = {"tile": tile, "block": list(r.block), "block_bwd": list(r.block_bwd), "order": r.order,
+               "order_bwd": r.order_bwd, "step_ms": ms}
+        per_tile[str(tile)] = cfg
         if best is None or ms < best["step_ms"]:
-            best = {"tile": tile, "block": list(r.block), "block_bwd": list(r.block_bwd), "step_ms": ms}
+            best = dict(cfg)
         del r
         torch.cuda.empty_cache()
     best["trials"] = trials
+    best["per_tile"] = per_tile
     if cache_path:
         cache[key] = best
         os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)

@@ -93,6 +93,20 @@ def gpu_bin_sort(arrs, sizes, tile, capacity):
     return host(it), host(ig), host(rg).reshape(T, 2), host(info)
 
 
+def _order(order, rg, T):
+    """Schedule buffer and queue of a rasteriser tile order (see render.py):
+    False / "tile", "xcd", "heavy", True / "queue"."""
+    order = {False: "tile", True: "queue"}.get(order, order)
+    if order == "tile":
+        return None, None
+    sched = torch.empty(B.tile_schedule_size(T), dtype=torch.uint8, device="cuda")
+    if order == "xcd":
+        B.tile_order_xcd(T, 8, sched)
+        return sched, None
+    B.tile_schedule(rg, T, sched)
+    return sched, (torch.zeros(1, dtype=torch.int32, device="cuda") if order == "queue" else None)
+
+
 def gpu_raster_fwd(splats, gids, ranges, sizes, tile, bg=(0, 0, 0), persistent=False, block=(0, 0)):
     V, N = splats.shape[:2]
     _, toff, poff = B.tile_grid(sizes, tile)
@@ -100,12 +114,8 @@ def gpu_raster_fwd(splats, gids, ranges, sizes, tile, bg=(0, 0, 0), persistent=F
     img = torch.full((3 * P,), float("nan"), device="cuda")
     T = torch.full((P,), float("nan"), device="cuda")
     last = torch.full((P,), -7, dtype=torch.int32, device="cuda")
-    sched, q = None, None
     rg = dev(np.asarray(ranges, np.int32).reshape(-1))
-    if persistent:
-        sched = torch.empty(B.tile_schedule_size(int(toff[-1])), dtype=torch.uint8, device="cuda")
-        q = torch.zeros(1, dtype=torch.int32, device="cuda")
-        B.tile_schedule(rg, int(toff[-1]), sched)
+    sched, q = _order(persistent, rg, int(toff[-1]))
     B.rasterize_fwd(dev(splats.reshape(-1)), dev(np.asarray(gids, np.int32)), rg, N, sizes, tile, bg, sched, q,
                     img, T, last, block=block)
     return host(img), host(T), host(last)
@@ -116,12 +126,8 @@ def gpu_raster_bwd(splats, gids, ranges, sizes, tile, T_final, last, d_img, d_al
     V, N = splats.shape[:2]
     _, toff, poff = B.tile_grid(sizes, tile)
     g = torch.zeros(V * N * 9, device="cuda")
-    sched, q = None, None
     rg = dev(np.asarray(ranges, np.int32).reshape(-1))
-    if persistent:
-        sched = torch.empty(B.tile_schedule_size(int(toff[-1])), dtype=torch.uint8, device="cuda")
-        q = torch.zeros(1, dtype=torch.int32, device="cuda")
-        B.tile_schedule(rg, int(toff[-1]), sched)
+    sched, q = _order(persistent, rg, int(toff[-1]))
     B.rasterize_bwd(dev(splats.reshape(-1)), dev(np.asarray(gids, np.int32)), rg, N, sizes, tile, bg, sched, q,
                     dev(T_final, F32), dev(last, np.int32), dev(d_img, F32),
                     None if d_alpha is None else dev(d_alpha, F32), g, block=block)

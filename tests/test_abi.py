@@ -66,11 +66,11 @@ def test_host_side_argument_checks():
     assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 100, aligned, ws - 1, p, p, p, p, None) == -4
     assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 0, aligned, ws, p, p, p, p, None) == -1
     assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 100, ctypes.c_void_p(260), ws, p, p, p, p, None) == -1
-    # rasterisers: bad tile, missing outputs, persistent mode without a queue
+    # rasterisers: bad tile, missing outputs, a queue without a schedule
     bg = (ctypes.c_float * 3)(0, 0, 0)
     assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 24, 0, 0, bg, None, None, p, p, p, None) == -1
     assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 16, 0, 0, bg, None, None, None, p, p, None) == -1
-    assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 16, 0, 0, bg, p, None, p, p, p, None) == -1
+    assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 16, 0, 0, bg, None, p, p, p, p, None) == -1
     assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 16, 32, 4, bg, None, None, p, p, p, None) == -1
     assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 8, 16, 4, bg, None, None, p, p, p, None) == -1
     nan = (ctypes.c_float * 3)(float("nan"), 0, 0)
@@ -80,6 +80,8 @@ def test_host_side_argument_checks():
     assert L.gs_project_bwd(p, p, p, p, p, 10, 5, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, None) == -1
     assert L.gs_loss_l2(p, p, 10, p, p, p, 0, None) == -4
     assert L.gs_tile_schedule(p, 0, p, 0, None) == -1
+    assert L.gs_tile_order_xcd(100, 0, aligned, 4096, None) == -1
+    assert L.gs_tile_order_xcd(100, 8, aligned, 8, None) == -4
     assert L.gs_tile_schedule_size(0) == 0
 
 

@@ -216,7 +216,7 @@ FWD_CASES = [("tiny", 16, (0.0, 0.0, 0.0)), ("tiny", 8, (0.0, 0.0, 0.0)), ("ragg
 
 
 @pytest.mark.parametrize("name,tile,bg", FWD_CASES)
-@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("persistent", ["tile", "xcd", "heavy", "queue"])
 def test_raster_fwd_parity(name, tile, bg, persistent):
     s = scene(name)
     _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
@@ -261,7 +261,7 @@ def _bwd_inputs(name, tile, with_alpha, seed=3):
 
 
 @pytest.mark.parametrize("name,tile,with_alpha", BWD_CASES)
-@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("persistent", ["tile", "xcd", "heavy", "queue"])
 def test_raster_bwd_parity(name, tile, with_alpha, persistent):
     s, bg, fw = _bwd_inputs(name, tile, with_alpha)
     _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
@@ -365,7 +365,7 @@ def test_raster_blocks_change_only_speed(name, tile):
     G.say(f"[blocks] {name} tile={tile}")
     ref = None
     for blk in BLOCKS[tile]:
-        for persistent in (False, True):
+        for persistent in ("tile", "xcd", "heavy", "queue"):
             img, T, last = G.gpu_raster_fwd(arrs["splats"], vals, ranges, s.sizes, tile, (0.1, 0.2, 0.3),
                                             persistent, blk)
             rng = np.random.default_rng(1)

@@ -22,8 +22,9 @@ pytestmark = pytest.mark.gpu
 EPS32 = 2.0 ** -24
 
 
-def _run_step(s, tile=16, persistent=False, capacity=1 << 16):
-    r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=tile, capacity=capacity, persistent=persistent)
+def _run_step(s, tile=16, persistent=False, capacity=1 << 16, order=None, order_bwd=None):
+    r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=tile, capacity=capacity, persistent=persistent, order=order,
+                   order_bwd=order_bwd)
     P, cams = R.params_to_device(s)
     r.fit_capacity(P, cams)
     tg = R.packed_targets(s)
@@ -160,22 +161,23 @@ def test_batched_equals_plain_views():
         assert e <= 1e-5
 
 
-def test_persistent_equals_grid():
+@pytest.mark.parametrize("order,order_bwd", [("queue", "queue"), ("xcd", "heavy"), ("heavy", "xcd")])
+def test_tile_orders_equal_grid(order, order_bwd):
     s = _multi()
-    G.say("[persistent == grid]")
+    G.say(f"[{order}/{order_bwd} == grid]")
     ra, *_, ga = _run_step(s, persistent=False)
-    rp, *_, gp = _run_step(s, persistent=True)
+    rp, *_, gp = _run_step(s, order=order, order_bwd=order_bwd)
     np.testing.assert_array_equal(G.host(ra.images), G.host(rp.images))
     np.testing.assert_array_equal(G.host(ra.n_contrib), G.host(rp.n_contrib))
     for k in ga:
         assert G.rel_l2(G.host(gp[k]), G.host(ga[k])) <= 1e-5
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_graph_replay_matches_eager(persistent):
+@pytest.mark.parametrize("order", ["tile", "heavy", "queue"])
+def test_graph_replay_matches_eager(order):
     s = _multi()
-    G.say(f"[graph replay] persistent={persistent}")
-    r, P, cams, tg, grads = _run_step(s, persistent=persistent)
+    G.say(f"[graph replay] order={order}")
+    r, P, cams, tg, grads = _run_step(s, order=order)
     eager = {k: G.host(v).copy() for k, v in grads.items()}
     eager_img = G.host(r.images).copy()
     eager_loss = float(G.host(r.loss)[0])
