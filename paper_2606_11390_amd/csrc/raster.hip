@@ -262,6 +262,8 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                 const int kk = kb - j - r.x;
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
                 bool any = false;
+                // per-entry constants of the conic terms (q' = c0 (A dx^2 + 2 B dx dy + C dy^2))
+                const float dyc = kC0 * dy, dyc2 = 2.0f * kC0 * dy;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
                     const float dx = su - fx[p];
@@ -269,31 +271,38 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                     const float al = fminf(f.araw, kAlphaMax);
                     const bool ok = kk < last[p] && al >= kAlphaMin;
                     any = any || ok;
-                    const float om = 1.0f - al;
-                    const float rom = __builtin_amdgcn_rcpf(om);
+                    // an entry a pixel skipped contributes nothing and changes
+                    // nothing: zero its alpha and upstream terms once instead
+                    // of selecting every accumulated product
+                    const float alo = ok ? al : 0.0f;
+                    const float rom = __builtin_amdgcn_rcpf(1.0f - alo);
                     const float Tk = T[p] * rom;
-                    const float wgt = al * Tk;
+                    const float wgt = alo * Tk;
                     const float d0 = cr - S0[p], d1 = cg - S1[p], d2 = cb - S2[p];
                     float ga = Tk * (d0 * g0[p] + d1 * g1[p] + d2 * g2[p]);
                     if (HAS_DA) ga = __builtin_fmaf(gA[p], rom, ga);
-                    const bool unc = ok && f.araw < kAlphaMax;
-                    const float gq = unc ? -kLn2 * al * ga : 0.0f;
-                    a6 += ok ? wgt * g0[p] : 0.0f;
-                    a7 += ok ? wgt * g1[p] : 0.0f;
-                    a8 += ok ? wgt * g2[p] : 0.0f;
-                    a5 += unc ? f.araw * inv_sig * ga : 0.0f;
+                    // d alpha / d(sigma, q') vanish where alpha is clamped at 0.99
+                    const float gu = (ok && f.araw < kAlphaMax) ? ga : 0.0f;
+                    const float gq = -kLn2 * al * gu;
+                    a6 = __builtin_fmaf(wgt, g0[p], a6);
+                    a7 = __builtin_fmaf(wgt, g1[p], a7);
+                    a8 = __builtin_fmaf(wgt, g2[p], a8);
+                    a5 = __builtin_fmaf(f.araw * inv_sig, gu, a5);
                     // q' = |M^T d|^2:  dq'/du = 2 (M w)_x, dq'/dv = 2 (M w)_y
-                    a0 += 2.0f * gq * (m00 * f.w0);
-                    a1 += 2.0f * gq * (m10 * f.w0 + m11 * f.w1);
-                    // q' = c0 (A dx^2 + 2 B dx dy + C dy^2)
-                    a2 += gq * kC0 * dx * dx;
-                    a3 += gq * (2.0f * kC0) * dx * dy;
-                    a4 += gq * kC0 * dy * dy;
-                    S0[p] = ok ? __builtin_fmaf(al, d0, S0[p]) : S0[p];
-                    S1[p] = ok ? __builtin_fmaf(al, d1, S1[p]) : S1[p];
-                    S2[p] = ok ? __builtin_fmaf(al, d2, S2[p]) : S2[p];
-                    T[p] = ok ? Tk : T[p];
+                    a0 = __builtin_fmaf(gq, m00 * f.w0, a0);
+                    a1 = __builtin_fmaf(gq, __builtin_fmaf(m10, f.w0, m11 * f.w1), a1);
+                    const float gqx = gq * dx;
+                    a2 = __builtin_fmaf(gqx * kC0, dx, a2);
+                    a3 = __builtin_fmaf(gqx, dyc2, a3);
+                    a4 = __builtin_fmaf(gq, dyc * dy, a4);
+                    S0[p] = __builtin_fmaf(alo, d0, S0[p]);
+                    S1[p] = __builtin_fmaf(alo, d1, S1[p]);
+                    S2[p] = __builtin_fmaf(alo, d2, S2[p]);
+                    T[p] = Tk;
                 }
+                // dq'/du, dq'/dv carry a factor 2
+                a0 *= 2.0f;
+                a1 *= 2.0f;
                 if (__ballot(any) == 0ull) continue;
                 const float acc[GS_GRAD_FLOATS] = {a0, a1, a2, a3, a4, a5, a6, a7, a8};
                 int jj;
