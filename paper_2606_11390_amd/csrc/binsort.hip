@@ -174,12 +174,22 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortIO io, int shift, in
     block_span(n, nb, b, beg, end);
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt = lanemask_lt();
-    for (uint32_t base = beg; base < end; base += RS_THREADS) {
-        uint32_t k = 0, v = 0;
-        const bool valid = load_kv<SRC>(io, base + t, end, k, v);
-        const uint32_t d = (k >> shift) & mask;
-        const uint64_t peers = match_digit(d, valid, bits);
-        if (valid && (peers & lt) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+    for (uint32_t base = beg; base < end; base += RS_CHUNK) {
+        // all RS_ITEMS loads of a thread are issued before any is used
+        uint32_t k[RS_ITEMS];
+        bool valid[RS_ITEMS];
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
+            uint32_t v = 0;
+            k[r] = 0;
+            valid[r] = load_kv<SRC>(io, base + (uint32_t)(r * RS_THREADS + t), end, k[r], v);
+        }
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
+            const uint32_t d = (k[r] >> shift) & mask;
+            const uint64_t peers = match_digit(d, valid[r], bits);
+            if (valid[r] && (peers & lt) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+        }
     }
     __syncthreads();
     if (t < 256) {
@@ -305,7 +315,19 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __re
     uint32_t beg, end;
     block_span(*n_dev, nb, b, beg, end);
     uint32_t s = 0;
-    for (uint32_t i = beg + t; i < end; i += SC_THREADS) s += (uint32_t)tiles[pids[i]];
+    for (uint32_t cb = beg; cb < end; cb += SC_THREADS * SC_ITEMS) {
+        uint32_t x[SC_ITEMS];
+#pragma unroll
+        for (int r = 0; r < SC_ITEMS; r++) {
+            const uint32_t i = cb + (uint32_t)(r * SC_THREADS + t);
+            x[r] = i < end ? pids[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < SC_ITEMS; r++) {
+            const uint32_t i = cb + (uint32_t)(r * SC_THREADS + t);
+            s += i < end ? (uint32_t)tiles[x[r]] : 0u;
+        }
+    }
     uint32_t tot;
     block_excl_scan_256(s, s_tmp, tot);
     if (t == 0) part[b] = tot;
@@ -341,25 +363,37 @@ __global__ __launch_bounds__(1024) void k_scan_spine(const uint32_t* __restrict_
     }
 }
 
+constexpr int EMIT_SPAN = 2048;   // output slots per emission workgroup
+
+// Writes offs[i] (first output slot of source i, clamped to the capacity) and,
+// for every emission workgroup k, bsrc[k] = the source whose slots contain
+// slot k * EMIT_SPAN (each source has at least one slot, so exactly one does);
+// bsrc[last] = the source holding the last emitted slot m - 1, where m
+// (m_dev) is the intersection count clamped to the capacity.
 __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __restrict__ pids,
                                                           const int* __restrict__ tiles,
                                                           const uint32_t* __restrict__ n_dev,
                                                           const unsigned long long* __restrict__ part_ex,
-                                                          uint32_t capacity,
-                                                          uint32_t* __restrict__ offs)
+                                                          uint32_t capacity, const uint32_t* __restrict__ m_dev,
+                                                          uint32_t* __restrict__ offs,
+                                                          uint32_t* __restrict__ bsrc, uint32_t last)
 {
+    const unsigned long long m = *m_dev;
     __shared__ uint32_t s_tmp[RS_WAVES];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
     uint32_t beg, end;
     block_span(*n_dev, nb, b, beg, end);
     unsigned long long carry = part_ex[b];
     for (uint32_t cb = beg; cb < end; cb += SC_THREADS * SC_ITEMS) {
-        // thread t owns SC_ITEMS consecutive elements
+        // thread t owns SC_ITEMS consecutive elements; all index loads are
+        // issued before the dependent tile-count loads
         uint32_t x[SC_ITEMS], s = 0;
         const uint32_t i0 = cb + (uint32_t)t * SC_ITEMS;
+#pragma unroll
+        for (int r = 0; r < SC_ITEMS; r++) x[r] = i0 + r < end ? pids[i0 + r] : 0u;
+#pragma unroll
         for (int r = 0; r < SC_ITEMS; r++) {
-            const uint32_t i = i0 + r;
-            x[r] = i < end ? (uint32_t)tiles[pids[i]] : 0u;
+            x[r] = i0 + r < end ? (uint32_t)tiles[x[r]] : 0u;
             s += x[r];
         }
         uint32_t tot;
@@ -369,6 +403,11 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __rest
             if (i < end) {
                 const unsigned long long o = carry + run;
                 offs[i] = (uint32_t)(o < capacity ? o : capacity);
+                // emission workgroups whose first slot lies in [o, o + x) below the capacity
+                const unsigned long long lim = min(o + x[r], (unsigned long long)capacity);
+                for (unsigned long long k = (o + EMIT_SPAN - 1) / EMIT_SPAN; k * EMIT_SPAN < lim; k++)
+                    bsrc[k] = i;
+                if (m > 0 && o <= m - 1 && m - 1 < o + x[r]) bsrc[last] = i;
             }
             run += x[r];
         }
@@ -380,10 +419,10 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __rest
 // load-balanced emission: one block per EMIT_SPAN consecutive output slots
 // ---------------------------------------------------------------------------
 constexpr int EMIT_THREADS = 256;
-constexpr int EMIT_SPAN = 2048;
 
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restrict__ pids,
                                                        const uint32_t* __restrict__ offs,
+                                                       const uint32_t* __restrict__ bsrc, uint32_t last,
                                                        const uint32_t* __restrict__ cnt,
                                                        const float* __restrict__ splats,
                                                        const int2* __restrict__ radii,
@@ -396,24 +435,17 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     __shared__ uint32_t s_base[EMIT_SPAN + 1];
     __shared__ uint32_t s_wt[EMIT_SPAN + 1];    // rect width << 16 | tiles_x... kept separate
     __shared__ uint32_t s_tx[EMIT_SPAN + 1];
-    __shared__ uint32_t s_src[2];
-    const uint32_t n_src = cnt[0], m = cnt[1];
+    const uint32_t m = cnt[1];
     const uint32_t start = blockIdx.x * (uint32_t)EMIT_SPAN;
     if (start >= m) return;
     const uint32_t end = min(m, start + (uint32_t)EMIT_SPAN);
     const int t = threadIdx.x;
-    if (t < 2) {
-        // last source whose offset is <= target
-        const uint32_t target = t == 0 ? start : end - 1;
-        uint32_t lo = 0, hi = n_src - 1;
-        while (lo < hi) {
-            const uint32_t mid = lo + (hi - lo + 1) / 2;
-            if (offs[mid] <= target) lo = mid; else hi = mid - 1;
-        }
-        s_src[t] = lo;
-    }
-    __syncthreads();
-    const uint32_t s0 = s_src[0], ns = s_src[1] - s0 + 1;
+    // sources of this workgroup's slots: from the one holding its first slot
+    // to the one holding the next workgroup's first slot (which may start
+    // exactly there; its slots then lie outside and are never selected)
+    const uint32_t s0 = bsrc[blockIdx.x];
+    const uint32_t s1 = end < m ? bsrc[blockIdx.x + 1] : bsrc[last];
+    const uint32_t ns = s1 - s0 + 1;
     for (uint32_t k = t; k < ns; k += EMIT_THREADS) {
         const uint32_t s = s0 + k;
         const uint32_t pid = pids[s];
@@ -488,8 +520,12 @@ hipError_t radix_pass(const SortIO& io, int nb, int shift, int bits, uint32_t* h
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// bsrc slot of the source holding the last emitted intersection (after the
+// per-workgroup slots 0 .. ceil(cap / EMIT_SPAN) - 1)
+uint32_t bsrc_last(unsigned long long cap) { return (uint32_t)((cap + EMIT_SPAN - 1) / EMIT_SPAN); }
+
 struct BinWs {
-    uint32_t *dk0, *dv0, *dk1, *dv1, *offs, *tk, *tv, *hist, *dtot, *part, *cnt;
+    uint32_t *dk0, *dv0, *dk1, *dv1, *offs, *tk, *tv, *hist, *dtot, *part, *cnt, *bsrc;
     unsigned long long* part_ex;
     size_t bytes;
 };
@@ -515,6 +551,7 @@ BinWs bin_layout(char* base, unsigned long long vn, unsigned long long cap)
     w.part = (uint32_t*)take(4 * RS_MAX_BLOCKS);
     w.part_ex = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
     w.cnt = (uint32_t*)take(4 * 16);
+    w.bsrc = (uint32_t*)take(4 * ((size_t)bsrc_last(cap) + 1));
     w.bytes = o;
     return w;
 }
@@ -567,7 +604,7 @@ hipError_t launch_bin_sort(const float* splats, const float* depths, const int2*
     hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, st, w.part, nb_d, w.part_ex, (uint32_t)cap,
                        w.cnt, info);
     hipLaunchKernelGGL(k_scan_down, dim3(nb_d), dim3(SC_THREADS), 0, st, pids, tiles, w.cnt + 0,
-                       w.part_ex, (uint32_t)cap, w.offs);
+                       w.part_ex, (uint32_t)cap, w.cnt + 1, w.offs, w.bsrc, bsrc_last(cap));
 
     // 3. emission; 4. tile passes (the last one lands in the caller's arrays)
     const int tbits = bits_for((unsigned long long)vt.total_tiles);
@@ -575,8 +612,8 @@ hipError_t launch_bin_sort(const float* splats, const float* depths, const int2*
     uint32_t *ek = (tpasses % 2 == 0) ? isect_tile : w.tk;
     uint32_t *ev = (tpasses % 2 == 0) ? isect_gid : w.tv;
     const unsigned emit_blocks = (unsigned)((cap + EMIT_SPAN - 1) / EMIT_SPAN);
-    hipLaunchKernelGGL(k_emit, dim3(emit_blocks), dim3(EMIT_THREADS), 0, st, pids, w.offs, w.cnt, splats,
-                       radii, N, vt, tile, ek, ev);
+    hipLaunchKernelGGL(k_emit, dim3(emit_blocks), dim3(EMIT_THREADS), 0, st, pids, w.offs, w.bsrc,
+                       bsrc_last(cap), w.cnt, splats, radii, N, vt, tile, ek, ev);
     const int nb_t = sort_blocks(cap);
     uint32_t *tki = ek, *tvi = ev;
     uint32_t *tko = (ek == isect_tile) ? w.tk : isect_tile, *tvo = (ev == isect_gid) ? w.tv : isect_gid;
