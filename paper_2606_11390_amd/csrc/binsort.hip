@@ -104,10 +104,11 @@ __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t e
         v = io.vals_in[i];
         return true;
     } else if (SRC == SRC_PROJ) {
-        if (io.tiles[i] <= 0) return false;
+        // both loads are issued before the visibility test
+        const int tt = io.tiles[i];
         k = __float_as_uint(io.depths[i]);
         v = i;
-        return true;
+        return tt > 0;
     } else if (SRC == SRC_MORTON) {
         k = morton30(io.means, io.n_const, i, io.org, io.inv_cell);
         v = i;
@@ -446,17 +447,35 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     const uint32_t s0 = bsrc[blockIdx.x];
     const uint32_t s1 = end < m ? bsrc[blockIdx.x + 1] : bsrc[last];
     const uint32_t ns = s1 - s0 + 1;
-    for (uint32_t k = t; k < ns; k += EMIT_THREADS) {
-        const uint32_t s = s0 + k;
-        const uint32_t pid = pids[s];
-        const uint32_t v = (uint32_t)(pid / (unsigned long long)N);
-        const uint32_t g = pid - v * (uint32_t)N;
-        const float* rec = splats + (size_t)pid * GS_SPLAT_FLOATS;
-        const int2 r = radii[pid];
+    // at most EMIT_SPAN + 1 sources: each thread stages up to EMIT_SRC of
+    // them, issuing every gather before using any
+    constexpr int EMIT_SRC = (EMIT_SPAN + 1 + EMIT_THREADS - 1) / EMIT_THREADS;
+    uint32_t pid[EMIT_SRC], off[EMIT_SRC];
+    float2 uv[EMIT_SRC];
+    int2 rr[EMIT_SRC];
+#pragma unroll
+    for (int q = 0; q < EMIT_SRC; q++) {
+        const uint32_t k = (uint32_t)(t + q * EMIT_THREADS);
+        pid[q] = k < ns ? pids[s0 + k] : 0u;
+        off[q] = k < ns ? offs[s0 + k] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < EMIT_SRC; q++) {
+        const uint32_t k = (uint32_t)(t + q * EMIT_THREADS);
+        uv[q] = k < ns ? *reinterpret_cast<const float2*>(splats + (size_t)pid[q] * GS_SPLAT_FLOATS)
+                       : make_float2(0.0f, 0.0f);
+        rr[q] = k < ns ? radii[pid[q]] : make_int2(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < EMIT_SRC; q++) {
+        const uint32_t k = (uint32_t)(t + q * EMIT_THREADS);
+        if (k >= ns) continue;
+        const uint32_t v = (uint32_t)(pid[q] / (unsigned long long)N);
+        const uint32_t g = pid[q] - v * (uint32_t)N;
         int x0, y0, x1, y1;
-        tile_rect(rec[0], rec[1], r.x, r.y, tile, vt.W[v], vt.H[v], x0, y0, x1, y1);
+        tile_rect(uv[q].x, uv[q].y, rr[q].x, rr[q].y, tile, vt.W[v], vt.H[v], x0, y0, x1, y1);
         const int TX = vt.tiles_x[v];
-        s_off[k] = offs[s];
+        s_off[k] = off[q];
         s_gid[k] = g;
         s_base[k] = (uint32_t)(vt.tile_off[v] + y0 * TX + x0);
         s_wt[k] = (uint32_t)(x1 - x0);

@@ -146,14 +146,23 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                 const float su = lane_f(cur.a.x, j), sv = lane_f(cur.a.y, j);
                 const float m00 = lane_f(cur.a.z, j), m10 = lane_f(cur.a.w, j);
                 const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
-                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
                 const float dy = sv - fy;
                 const int k1 = kb + j - r.x + 1;
+                // alpha first: an entry no pixel of the wave takes costs no more
+                float alp[P];
+                bool okp[P], any = false;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
-                    const Falloff f = falloff(su - fx[p], dy, m00, m10, m11, ls);
-                    const float al = fminf(f.araw, kAlphaMax);
-                    bool ok = !done[p] && al >= kAlphaMin;
+                    alp[p] = fminf(falloff(su - fx[p], dy, m00, m10, m11, ls).araw, kAlphaMax);
+                    okp[p] = !done[p] && alp[p] >= kAlphaMin;
+                    any = any || okp[p];
+                }
+                if (__ballot(any) == 0ull) continue;
+                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
+#pragma unroll
+                for (int p = 0; p < P; p++) {
+                    const float al = alp[p];
+                    bool ok = okp[p];
                     const float Tn = __builtin_fmaf(-T[p], al, T[p]);
                     const bool stop = ok && Tn < kTMin;
                     if (COUNT) stopk[p] = stop ? k1 : stopk[p];
@@ -252,25 +261,33 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
             while (mask) {
                 const int j = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                const int gid = __builtin_amdgcn_readlane(g_cur, j);
                 const float su = lane_f(cur.a.x, j), sv = lane_f(cur.a.y, j);
                 const float m00 = lane_f(cur.a.z, j), m10 = lane_f(cur.a.w, j);
                 const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
-                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
-                const float inv_sig = __builtin_amdgcn_rcpf(lane_f(cur.c.y, j));
                 const float dy = sv - fy;
                 const int kk = kb - j - r.x;
+                // alpha first: an entry no pixel of the wave composited costs no more
+                Falloff fp[P];
+                bool okp[P], any = false;
+#pragma unroll
+                for (int p = 0; p < P; p++) {
+                    fp[p] = falloff(su - fx[p], dy, m00, m10, m11, ls);
+                    okp[p] = kk < last[p] && fminf(fp[p].araw, kAlphaMax) >= kAlphaMin;
+                    any = any || okp[p];
+                }
+                if (__ballot(any) == 0ull) continue;
+                const int gid = __builtin_amdgcn_readlane(g_cur, j);
+                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
+                const float inv_sig = __builtin_amdgcn_rcpf(lane_f(cur.c.y, j));
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
-                bool any = false;
                 // per-entry constants of the conic terms (q' = c0 (A dx^2 + 2 B dx dy + C dy^2))
                 const float dyc = kC0 * dy, dyc2 = 2.0f * kC0 * dy;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
                     const float dx = su - fx[p];
-                    const Falloff f = falloff(dx, dy, m00, m10, m11, ls);
+                    const Falloff f = fp[p];
                     const float al = fminf(f.araw, kAlphaMax);
-                    const bool ok = kk < last[p] && al >= kAlphaMin;
-                    any = any || ok;
+                    const bool ok = okp[p];
                     // an entry a pixel skipped contributes nothing and changes
                     // nothing: zero its alpha and upstream terms once instead
                     // of selecting every accumulated product
@@ -303,7 +320,6 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                 // dq'/du, dq'/dv carry a factor 2
                 a0 *= 2.0f;
                 a1 *= 2.0f;
-                if (__ballot(any) == 0ull) continue;
                 const float acc[GS_GRAD_FLOATS] = {a0, a1, a2, a3, a4, a5, a6, a7, a8};
                 int jj;
                 const float x = wave_sum9_scatter(acc, jj);
