@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batched path at --tile instead of the autotuned tile edge")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON file for the autotuner's choice: written on first use, reused after")
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all",
                     help="restrict to one path (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -281,7 +283,8 @@ def main():
     if args.only in ("all", "batched"):
         tiles = (8, 16, 32) if args.autotune else (args.tile,)
         tuned = R.autotune(P, cams, tg, scene.sh_degree, scene.sizes, tiles=tiles, steps=max(3, args.steps // 4),
-                           log=log)
+                           cache_path=args.autotune_cache, log=log)
+        tuned = dict(tuned)
         tuned.pop("trials", None)
         per_tile = tuned.pop("per_tile", {})
         if str(args.tile) in per_tile and tuned["tile"] != args.tile:
