@@ -303,12 +303,14 @@ def autotune(P, cams, targets, sh_degree, sizes, tiles=(8, 16, 32), steps=5, cac
     fixed tile pass a single value in ``tiles``.  Returns a dict with the
     chosen ``tile``, ``block`` (forward), ``block_bwd`` and the measured
     milliseconds per candidate;
-    with ``cache_path`` the result is stored in a JSON file keyed by the GPU
-    name and the workload shape and reused."""
+    with ``cache_path`` the result is stored in a JSON file keyed by the
+    workload shape and reused."""
     import json
     import os
     n = int(P["means"].shape[1])
-    key = f"{torch.cuda.get_device_name()}|n={n}|deg={sh_degree}|sizes={np.asarray(sizes).tolist()}|tiles={list(tiles)}"
+    # keyed by the workload shape only (a profiler can change what the device
+    # reports as its name); keep one cache file per GPU model
+    key = f"n={n}|deg={sh_degree}|sizes={np.asarray(sizes).tolist()}|tiles={list(tiles)}"
     cache = {}
     if cache_path and os.path.exists(cache_path):
         try:
