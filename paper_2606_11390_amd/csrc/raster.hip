@@ -49,9 +49,43 @@ __device__ __forceinline__ bool misses(int packed, int b0, int b1)
     return hi < b0 || lo > b1;
 }
 
+__device__ __forceinline__ float sq(float x) { return x * x; }
+
 __device__ __forceinline__ float lane_f(float x, int j)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+}
+
+// Can the splat of record e reach alpha >= 1/255 at any pixel centre of the
+// block [bx0, bx1] x [by0, by1]?  A pixel at offset d = (u, v) - centre gets
+// alpha = sigma 2^-q' with q' = w0^2 + w1^2, w0 = m00 dx + m10 dy, w1 = m11 dy
+// (the record's factor of the scaled conic), so it is reached only where
+// q' <= log2(255 sigma).  q' is convex, so its minimum over the rectangle of
+// pixel centres is 0 when the rectangle holds d = 0 and otherwise lies on an
+// edge, where it is a one-dimensional quadratic minimised in closed form.
+// The threshold is widened by 0.02 (in log2 units) so that float32 rounding
+// here and in the per-pixel alpha cannot drop a pixel the alpha test keeps;
+// a wave skipping an entry that fails this test changes no result bit.
+__device__ __forceinline__ bool block_may_take(const Rec& e, int bx0, int bx1, int by0, int by1)
+{
+    const float m00 = e.a.z, m10 = e.a.w, m11 = e.b.x;
+    const float X0 = e.a.x - ((float)bx1 + 0.5f), X1 = e.a.x - ((float)bx0 + 0.5f);
+    const float Y0 = e.a.y - ((float)by1 + 0.5f), Y1 = e.a.y - ((float)by0 + 0.5f);
+    const bool inside = X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f;
+    // edges dx = X: the minimising dy is -m00 m10 X / (m10^2 + m11^2)
+    const float ra = __builtin_amdgcn_rcpf(m10 * m10 + m11 * m11);
+    const float dya = fminf(fmaxf(-m00 * m10 * X0 * ra, Y0), Y1);
+    const float dyb = fminf(fmaxf(-m00 * m10 * X1 * ra, Y0), Y1);
+    // edges dy = Y: the minimising dx is -m10 Y / m00
+    const float rm = __builtin_amdgcn_rcpf(m00);
+    const float dxa = fminf(fmaxf(-m10 * Y0 * rm, X0), X1);
+    const float dxb = fminf(fmaxf(-m10 * Y1 * rm, X0), X1);
+    const float qa = sq(m00 * X0 + m10 * dya) + sq(m11 * dya);
+    const float qb = sq(m00 * X1 + m10 * dyb) + sq(m11 * dyb);
+    const float qc = sq(m00 * dxa + m10 * Y0) + sq(m11 * Y0);
+    const float qd = sq(m00 * dxb + m10 * Y1) + sq(m11 * Y1);
+    const float qmin = fminf(fminf(qa, qb), fminf(qc, qd));
+    return inside || qmin <= e.b.y + (7.99435344f + 0.02f);
 }
 
 // A wave covers a BW x BH pixel block; BW / P lanes per pixel row.
@@ -131,7 +165,8 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
             // lane-parallel cull: entries whose alpha box misses this wave's
             // block cannot change any of its pixels
             const bool hit = kb + lane < r.y && !misses(__float_as_int(cur.c.z), U.bx0, bx1) &&
-                             !misses(__float_as_int(cur.c.w), U.by0, by1);
+                             !misses(__float_as_int(cur.c.w), U.by0, by1) &&
+                             block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
             while (mask) {
                 bool all_done = true;
@@ -256,7 +291,8 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
             const Rec nxt = load_rec(base, g_nxt);
             const int g_nn = gids[max(kb - 2 * GS_WAVE - lane, r.x)];
             const bool hit = kb - lane >= r.x && !misses(__float_as_int(cur.c.z), U.bx0, bx1) &&
-                             !misses(__float_as_int(cur.c.w), U.by0, by1);
+                             !misses(__float_as_int(cur.c.w), U.by0, by1) &&
+                             block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
             while (mask) {
                 const int j = __builtin_ctzll(mask);
