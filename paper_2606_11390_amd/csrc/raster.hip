@@ -35,6 +35,14 @@ struct Rec {
     float4 a, b, c;   // u, v, m00, m10 | m11, log2 sigma, r, g | b, sigma, box x, box y
 };
 
+// A wave's copy of its current batch in LDS (the backward reads each record
+// back with three broadcast LDS loads instead of eleven readlanes, which
+// would take VALU issue slots from the per-pixel work that bounds it).
+struct WaveStage {
+    float4 rec[3][GS_WAVE];
+    int gid[GS_WAVE];
+};
+
 __device__ __forceinline__ Rec load_rec(const float* __restrict__ base, int gid)
 {
     const float4* p = reinterpret_cast<const float4*>(base + (size_t)gid * GS_SPLAT_FLOATS);
@@ -241,7 +249,7 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                                          const int* __restrict__ nlast,
                                          const float* __restrict__ dimg,
                                          const float* __restrict__ dalpha,
-                                         float* __restrict__ grad2d)
+                                         float* __restrict__ grad2d, WaveStage* __restrict__ stage)
 {
     using L = Layout<TS, BW, P>;
     const Unit U = unit_of<TS, BW, P>(vt, gt, wit);
@@ -294,12 +302,18 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                              !misses(__float_as_int(cur.c.w), U.by0, by1) &&
                              block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
+            // the previous batch's reads of the stage precede these writes in
+            // the wave's program order, and LDS serves one wave in order
+            stage->rec[0][lane] = cur.a;
+            stage->rec[1][lane] = cur.b;
+            stage->rec[2][lane] = cur.c;
+            stage->gid[lane] = g_cur;
             while (mask) {
                 const int j = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                const float su = lane_f(cur.a.x, j), sv = lane_f(cur.a.y, j);
-                const float m00 = lane_f(cur.a.z, j), m10 = lane_f(cur.a.w, j);
-                const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
+                const float4 ra = stage->rec[0][j];
+                const float4 rb = stage->rec[1][j];
+                const float su = ra.x, sv = ra.y, m00 = ra.z, m10 = ra.w, m11 = rb.x, ls = rb.y;
                 const float dy = sv - fy;
                 const int kk = kb - j - r.x;
                 // alpha first: an entry no pixel of the wave composited costs no more
@@ -312,9 +326,10 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                     any = any || okp[p];
                 }
                 if (__ballot(any) == 0ull) continue;
-                const int gid = __builtin_amdgcn_readlane(g_cur, j);
-                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
-                const float inv_sig = __builtin_amdgcn_rcpf(lane_f(cur.c.y, j));
+                const int gid = __builtin_amdgcn_readfirstlane(stage->gid[j]);
+                const float2 rc = *reinterpret_cast<const float2*>(&stage->rec[2][j]);
+                const float cr = rb.z, cg = rb.w, cb = rc.x;
+                const float inv_sig = __builtin_amdgcn_rcpf(rc.y);
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
                 // per-entry constants of the conic terms (q' = c0 (A dx^2 + 2 B dx dy + C dy^2))
                 const float dyc = kC0 * dy, dyc2 = 2.0f * kC0 * dy;
@@ -447,11 +462,12 @@ __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_b
     const int* __restrict__ order, const float* __restrict__ Tfin, const int* __restrict__ nlast,
     const float* __restrict__ dimg, const float* __restrict__ dalpha, float* __restrict__ grad2d)
 {
+    __shared__ WaveStage stage[Layout<TS, BW, P>::WPT];
     const int gt = tile_of_block(order, vt.total_tiles);
     if (gt < 0) return;
     const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
     bwd_unit<TS, BW, P, HAS_DA>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, dimg, dalpha,
-                                grad2d);
+                                grad2d, &stage[wit]);
 }
 
 template <int TS, int BW, int P, bool HAS_DA>
@@ -463,6 +479,7 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
     float* __restrict__ grad2d)
 {
     using L = Layout<TS, BW, P>;
+    __shared__ WaveStage stage;
     const int n_items = vt.total_tiles * L::WPT;
     const int n_chunks = (n_items + QCHUNK - 1) / QCHUNK;
     int c = ticket(claim(queue));
@@ -472,7 +489,7 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
             const int gt = order[item / L::WPT];
             if ((unsigned)gt < (unsigned)vt.total_tiles)
                 bwd_unit<TS, BW, P, HAS_DA>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, Tfin,
-                                            nlast, dimg, dalpha, grad2d);
+                                            nlast, dimg, dalpha, grad2d, &stage);
         }
         c = ticket(next);
     }
