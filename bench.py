@@ -5,7 +5,9 @@ Workload (default): 5,000,000 Gaussians from a 512-blob mixture in a 200 m
 cube, SH degree 3, one 3840x2160 view (fx = fy = 3000) looking at the scene
 centre from the cube surface; FP32 forward, L2 loss against a uniform target,
 backward to every parameter.  Inputs are seeded and synthetic and resident in
-HBM before timing starts.
+HBM before timing starts.  The Gaussians are stored in 3-D Morton order, the
+layout the paper's densification leaves them in (applied once, untimed); the
+batched step is also reported on the generator's order.
 
 Two paths are timed on the same inputs:
   plain   - one workgroup per tile in tile order, every call launched eagerly
@@ -210,7 +212,12 @@ def main():
     scene = make_scene(args.config, args.n_gaussians)
     log(f"scene {scene.name}: N={scene.n} views={scene.n_views} pixels={scene.pixels} "
         f"({time.time() - t0:.1f} s)")
-    P, cams = R.params_to_device(scene)
+    P_gen, cams = R.params_to_device(scene)
+    # the paper's locality pass: Gaussians stored in 3-D Morton order (it runs
+    # at densification time, so it is applied once here, before any timing);
+    # every path below runs on this layout, and the batched step is also
+    # timed on the generator's order
+    P, _ = R.morton_permute(P_gen)
     tg = R.packed_targets(scene)
     grads = R.zeros_like_params(P)
     pixels = scene.pixels
@@ -303,16 +310,14 @@ def main():
         log(f"batched, opacity-aware radius: {mso:.3f} ms/step, {pixels / mso / 1e3:.1f} MP/s, M={mo}")
         del ro
         torch.cuda.empty_cache()
-        # the same step on the parameters in 3-D Morton order (the paper's
-        # densification-time locality pass; the permutation is not timed)
-        Pm, _ = R.morton_permute(P)
-        P_orig = P
-        P = Pm
-        rm, mm, msm = run_path(tuned, True)
-        result["batched_morton_order"] = {"ms_per_step": msm, "mp_per_s": pixels / msm / 1e3}
-        log(f"batched, Morton-ordered Gaussians: {msm:.3f} ms/step, {pixels / msm / 1e3:.1f} MP/s, M={mm}")
-        P = P_orig
-        del rm, Pm
+        # the same step on the generator's order of the Gaussians
+        P_m = P
+        P = P_gen
+        rg, mg, msg = run_path(tuned, True)
+        result["batched_generator_order"] = {"ms_per_step": msg, "mp_per_s": pixels / msg / 1e3}
+        log(f"batched, generator order of the Gaussians: {msg:.3f} ms/step, {pixels / msg / 1e3:.1f} MP/s, M={mg}")
+        P = P_m
+        del rg
         torch.cuda.empty_cache()
         r_main, m, ms_main = run_path(tuned, True)
         log(f"batched (tile {tuned['tile']}, orders {tuned['order']} / {tuned['order_bwd']}, blocks {tuned['block']} / "
@@ -376,12 +381,13 @@ def main():
                    "path": "batched" if args.only != "plain" else "plain",
                    "gaussians": scene.n, "views": scene.n_views, "pixels": pixels,
                    "intersections": int(info[B.INFO_ISECT]), "visible": int(info[B.INFO_VISIBLE]),
+                   "gaussian_order": "3-D Morton (applied once before timing)",
                    "parallelism": "1 GPU"},
         "gaussians_per_s": round(gauss / ms_main * 1e3, 1),
         "plain": {k: round(v, 4) for k, v in result.get("plain", {}).items()},
         "batched_same_tile": result.get("batched_same_tile"),
-        "batched_morton_order": ({k: round(v, 4) for k, v in result["batched_morton_order"].items()}
-                                 if "batched_morton_order" in result else None),
+        "batched_generator_order": ({k: round(v, 4) for k, v in result["batched_generator_order"].items()}
+                                    if "batched_generator_order" in result else None),
         "batched_opacity_radius": ({k: round(v, 4) for k, v in result["batched_opacity_radius"].items()}
                                    if "batched_opacity_radius" in result else None),
         "autotuned": tuned,
