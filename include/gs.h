@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 2
+#define GS_ABI_VERSION 3
 #define GS_MAX_VIEWS 64
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD_FLOATS 9
@@ -151,6 +151,9 @@ const char* gs_strerror(int code);
  *   depths                camera-space z (float32; sort key)
  *   radii[V][N][2]        rx, ry in pixels (int32)
  *   tiles_touched         number of tiles in the rectangle (int32)
+ *   tile_rects[V][N][2]   the tile rectangle [x0, x1) x [y0, y1) in the view's tile
+ *                         grid, packed as x0 | y0 << 16, x1 | y1 << 16 (int32);
+ *                         all zero when culled
  *   flags                 GS_FLAG_* bits (uint8)
  */
 int gs_project(const float* means, const float* log_scales, const float* quats,
@@ -158,7 +161,7 @@ int gs_project(const float* means, const float* log_scales, const float* quats,
                const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
                float near_plane, float far_plane, float eps2d, int tile, int radius_mode,
                float* splats, float* depths, int32_t* radii, int32_t* tiles_touched,
-               uint8_t* flags, void* stream);
+               int32_t* tile_rects, uint8_t* flags, void* stream);
 
 /*
  * gs_bin_sort_workspace_size - bytes of device workspace gs_bin_sort needs
@@ -176,9 +179,10 @@ size_t gs_bin_sort_workspace_size(int64_t n, int n_views, int64_t capacity, int6
  * enumerated per view, Gaussian index ascending and tiles row-major within
  * each rectangle; equal keys therefore keep Gaussian order.  (Depth is
  * positive, so its bit pattern orders like its value.)
- * Inputs: splats (fields u, v), depths, radii, tiles_touched as written by
- *   gs_project for the same n, V, sizes and tile; capacity = entries
- *   available in isect_tile / isect_gid (1 <= capacity < 2^31).
+ * Inputs: tile_rects and depths as written by gs_project for the same n, V,
+ *   sizes and tile (a pair is binned when its rectangle is not empty);
+ *   capacity = entries available in isect_tile / isect_gid
+ *   (1 <= capacity < 2^31).
  * Outputs:
  *   isect_tile[capacity]  global tile id of each sorted intersection
  *   isect_gid[capacity]   Gaussian index (0..N-1) of each sorted intersection
@@ -191,8 +195,7 @@ size_t gs_bin_sort_workspace_size(int64_t n, int n_views, int64_t capacity, int6
  * workspace: >= gs_bin_sort_workspace_size() bytes, 256-byte aligned,
  *   contents need not be initialised and are clobbered.
  */
-int gs_bin_sort(const float* splats, const float* depths, const int32_t* radii,
-                const int32_t* tiles_touched, int64_t n, int n_views, const int32_t* sizes,
+int gs_bin_sort(const int32_t* tile_rects, const float* depths, int64_t n, int n_views, const int32_t* sizes,
                 int tile, int64_t capacity, void* workspace, size_t workspace_bytes,
                 int32_t* isect_tile, int32_t* isect_gid, int32_t* tile_ranges, int32_t* info,
                 void* stream);

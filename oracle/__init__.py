@@ -66,6 +66,7 @@ def lib():
         L.or_sh_basis.argtypes = [_int, _D, _D]
         L.or_quat_rot.argtypes = [_D, _D]
         L.or_tile_rect.argtypes = [ctypes.c_float, ctypes.c_float, _int, _int, _int, _int, _int, _I]
+        L.or_tile_rects.argtypes = [_i64, _F, _F, _I, _int, _int, _int, _I]
         _lib = L
     return _lib
 
@@ -99,6 +100,18 @@ def tile_rect(u, v, rx, ry, tile, W, H):
     r = np.zeros(4, np.int32)
     lib().or_tile_rect(float(u), float(v), int(rx), int(ry), tile, W, H, _p(r, _I))
     return tuple(int(x) for x in r)
+
+
+def tile_rects(u32, v32, radii, tile, W, H):
+    """Tile rectangles [n][4] = (x0, y0, x1, y1) of n Gaussians from their
+    float32 means and radii [2][n] (reading R8); zero rows where culled."""
+    u32 = np.ascontiguousarray(u32, np.float32)
+    v32 = np.ascontiguousarray(v32, np.float32)
+    radii = np.ascontiguousarray(radii, np.int32)
+    n = u32.shape[0]
+    out = np.zeros((n, 4), np.int32)
+    lib().or_tile_rects(n, _p(u32, _F), _p(v32, _F), _p(radii, _I), int(tile), int(W), int(H), _p(out, _I))
+    return out
 
 
 # --------------------------------------------------------------------------

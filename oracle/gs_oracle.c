@@ -201,6 +201,18 @@ void or_tile_rect(float u, float v, int rx, int ry, int tile, int W, int H, int3
     for (int i = 0; i < 4; i++) r[i] = rr[i];
 }
 
+/* tile rectangles of n Gaussians: radii [2][n]; out [n][4] = x0, y0, x1, y1
+ * (all zero where the radii are zero, i.e. culled) */
+void or_tile_rects(int64_t n, const float* u, const float* v, const int32_t* radii, int tile, int W, int H,
+                   int32_t* out)
+{
+    for (int64_t g = 0; g < n; g++) {
+        int rr[4] = {0, 0, 0, 0};
+        if (radii[g] > 0 || radii[n + g] > 0) tile_rect(u[g], v[g], radii[g], radii[n + g], tile, W, H, rr);
+        for (int i = 0; i < 4; i++) out[4 * g + i] = rr[i];
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Projection + SH colour, forward, one view.                                  */
 /* ------------------------------------------------------------------------- */

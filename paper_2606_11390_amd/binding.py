@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
-GS_ABI_VERSION = 2
+GS_ABI_VERSION = 3
 GS_MAX_VIEWS = 64
 SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
@@ -38,10 +38,10 @@ _SIGS = {
     "gs_abi_version": (_int, []),
     "gs_strerror": (ctypes.c_char_p, [_int]),
     "gs_project": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _f, _f, _int, _int,
-                          _p, _p, _p, _p, _p, _p]),
+                          _p, _p, _p, _p, _p, _p, _p]),
     "gs_densify_stats": (_int, [_p, _p, _p, _i64, _int, _p, _p, _p, _p, _p]),
     "gs_bin_sort_workspace_size": (_sz, [_i64, _int, _i64, _i64]),
-    "gs_bin_sort": (_int, [_p, _p, _p, _p, _i64, _int, _p, _int, _i64, _p, _sz, _p, _p, _p, _p, _p]),
+    "gs_bin_sort": (_int, [_p, _p, _i64, _int, _p, _int, _i64, _p, _sz, _p, _p, _p, _p, _p]),
     "gs_tile_schedule_size": (_sz, [_i64]),
     "gs_tile_schedule": (_int, [_p, _i64, _p, _sz, _p]),
     "gs_tile_order_xcd": (_int, [_i64, _int, _p, _sz, _p]),
@@ -135,7 +135,7 @@ F32, I32, U8 = torch.float32, torch.int32, torch.uint8
 
 
 def project(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes,
-            near, far, eps2d, tile, splats, depths, radii, tiles_touched, flags, radius_mode=0):
+            near, far, eps2d, tile, splats, depths, radii, tiles_touched, tile_rects, flags, radius_mode=0):
     n = means.shape[1]
     sz, szp = _host_i32(sizes)
     rc = lib().gs_project(_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
@@ -144,7 +144,7 @@ def project(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, i
                           _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(near), float(far),
                           float(eps2d), int(tile), int(radius_mode), _ptr(splats, F32, "splats"), _ptr(depths, F32, "depths"),
                           _ptr(radii, I32, "radii"), _ptr(tiles_touched, I32, "tiles_touched"),
-                          _ptr(flags, U8, "flags"), _stream())
+                          _ptr(tile_rects, I32, "tile_rects"), _ptr(flags, U8, "flags"), _stream())
     _check(rc, "gs_project")
 
 
@@ -152,11 +152,9 @@ def bin_sort_workspace_size(n, n_views, capacity, total_tiles):
     return int(lib().gs_bin_sort_workspace_size(n, n_views, capacity, total_tiles))
 
 
-def bin_sort(splats, depths, radii, tiles_touched, n, sizes, tile, capacity, workspace, isect_tile,
-             isect_gid, tile_ranges, info):
+def bin_sort(tile_rects, depths, n, sizes, tile, capacity, workspace, isect_tile, isect_gid, tile_ranges, info):
     sz, szp = _host_i32(sizes)
-    rc = lib().gs_bin_sort(_ptr(splats, F32, "splats"), _ptr(depths, F32, "depths"),
-                           _ptr(radii, I32, "radii"), _ptr(tiles_touched, I32, "tiles_touched"), n,
+    rc = lib().gs_bin_sort(_ptr(tile_rects, I32, "tile_rects"), _ptr(depths, F32, "depths"), n,
                            sz.shape[0], szp, int(tile), int(capacity), _ptr(workspace, U8, "workspace"),
                            workspace.numel(), _ptr(isect_tile, I32, "isect_tile"),
                            _ptr(isect_gid, I32, "isect_gid"), _ptr(tile_ranges, I32, "tile_ranges"),

@@ -9,9 +9,12 @@
 // An LSD radix sort processes the low (depth) digits first.  All intersections
 // of one (view, Gaussian) pair share its depth, so the depth passes are run
 // once per visible pair instead of once per intersection:
-//   1. depth passes (4 x 8 bits) over the visible (view, Gaussian) pairs,
-//      the first pass compacting them out of the projection outputs;
-//   2. exclusive scan of tiles_touched in that order;
+//   1. depth passes (4 x 8 bits) over the visible (view, Gaussian) pairs
+//      (those with a non-empty tile rectangle), the first pass compacting
+//      them out of the projection outputs;
+//   2. the pairs' tile rectangles gathered into that order (the only random
+//      access of the binning after the sort) and an exclusive scan of their
+//      tile counts;
 //   3. load-balanced emission of (global tile id, Gaussian) pairs, each
 //      pair's tiles in row-major order;
 //   4. stable passes over the tile-id bits;
@@ -42,7 +45,7 @@ struct SortIO {
     const uint32_t* keys_in;   // SRC_PAIRS
     const uint32_t* vals_in;
     const float* depths;       // SRC_PROJ
-    const int* tiles;
+    const int2* rects;
     const int2* ranges;        // SRC_TILE_LEN
     const float* means;        // SRC_MORTON: planar [3][n]
     float org[3], inv_cell[3];
@@ -104,11 +107,13 @@ __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t e
         v = io.vals_in[i];
         return true;
     } else if (SRC == SRC_PROJ) {
-        // both loads are issued before the visibility test
-        const int tt = io.tiles[i];
+        // both loads are issued before the visibility test: a pair is binned
+        // when its tile rectangle is not empty
+        const int2 rc = io.rects[i];
         k = __float_as_uint(io.depths[i]);
         v = i;
-        return tt > 0;
+        const int w = (rc.y & 0xFFFF) - (rc.x & 0xFFFF), h = (int)((uint32_t)rc.y >> 16) - (int)((uint32_t)rc.x >> 16);
+        return w > 0 && h > 0;
     } else if (SRC == SRC_MORTON) {
         k = morton30(io.means, io.n_const, i, io.org, io.inv_cell);
         v = i;
@@ -301,21 +306,57 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
 }
 
 // ---------------------------------------------------------------------------
-// scan of tiles_touched in depth order, intersection count, overflow
+// tile rectangles in depth order, scan of their tile counts, intersection
+// count, overflow
 // ---------------------------------------------------------------------------
 constexpr int SC_THREADS = 256;
 constexpr int SC_ITEMS = 8;
 
-__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ pids,
-                                                            const int* __restrict__ tiles,
-                                                            const uint32_t* __restrict__ n_dev,
-                                                            uint32_t* __restrict__ part)
+// tiles of a packed rectangle (x0 | y0 << 16, x1 | y1 << 16); zero when empty
+__device__ __forceinline__ uint32_t rect_count(int2 r)
 {
-    __shared__ uint32_t s_tmp[RS_WAVES];
+    const int w = (r.y & 0xFFFF) - (r.x & 0xFFFF), h = (int)((uint32_t)r.y >> 16) - (int)((uint32_t)r.x >> 16);
+    return (w > 0 && h > 0) ? (uint32_t)w * (uint32_t)h : 0u;
+}
+
+// exclusive scan of one uint64 per thread over a 256-thread block
+__device__ __forceinline__ unsigned long long block_excl_scan_256_u64(unsigned long long x,
+                                                                       unsigned long long* s_tmp,
+                                                                       unsigned long long& total)
+{
+    const int lane = __lane_id(), w = threadIdx.x / GS_WAVE;
+    unsigned long long inc = x;
+    for (int o = 1; o < GS_WAVE; o <<= 1) {
+        const unsigned long long y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == GS_WAVE - 1) s_tmp[w] = inc;
+    __syncthreads();
+    unsigned long long before = 0;
+    total = 0;
+    for (int i = 0; i < RS_WAVES; i++) {
+        const unsigned long long t = s_tmp[i];
+        if (i < w) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + inc - x;
+}
+
+// gathers each visible pair's tile rectangle into depth order (the only
+// random access of the scan) and sums their tile counts per block (64-bit:
+// a pair may cover up to 2^32 - 1 tiles)
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ pids,
+                                                            const int2* __restrict__ rects,
+                                                            const uint32_t* __restrict__ n_dev,
+                                                            int2* __restrict__ srect,
+                                                            unsigned long long* __restrict__ part)
+{
+    __shared__ unsigned long long s_tmp[RS_WAVES];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
     uint32_t beg, end;
     block_span(*n_dev, nb, b, beg, end);
-    uint32_t s = 0;
+    unsigned long long s = 0;
     for (uint32_t cb = beg; cb < end; cb += SC_THREADS * SC_ITEMS) {
         uint32_t x[SC_ITEMS];
 #pragma unroll
@@ -326,15 +367,19 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __re
 #pragma unroll
         for (int r = 0; r < SC_ITEMS; r++) {
             const uint32_t i = cb + (uint32_t)(r * SC_THREADS + t);
-            s += i < end ? (uint32_t)tiles[x[r]] : 0u;
+            if (i < end) {
+                const int2 rc = rects[x[r]];
+                srect[i] = rc;
+                s += rect_count(rc);
+            }
         }
     }
-    uint32_t tot;
-    block_excl_scan_256(s, s_tmp, tot);
+    unsigned long long tot;
+    block_excl_scan_256_u64(s, s_tmp, tot);
     if (t == 0) part[b] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_spine(const uint32_t* __restrict__ part, int nb,
+__global__ __launch_bounds__(1024) void k_scan_spine(const unsigned long long* __restrict__ part, int nb,
                                                      unsigned long long* __restrict__ part_ex,
                                                      uint32_t capacity, uint32_t* __restrict__ cnt,
                                                      int* __restrict__ info)
@@ -371,8 +416,7 @@ constexpr int EMIT_SPAN = 2048;   // output slots per emission workgroup
 // slot k * EMIT_SPAN (each source has at least one slot, so exactly one does);
 // bsrc[last] = the source holding the last emitted slot m - 1, where m
 // (m_dev) is the intersection count clamped to the capacity.
-__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __restrict__ pids,
-                                                          const int* __restrict__ tiles,
+__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const int2* __restrict__ srect,
                                                           const uint32_t* __restrict__ n_dev,
                                                           const unsigned long long* __restrict__ part_ex,
                                                           uint32_t capacity, const uint32_t* __restrict__ m_dev,
@@ -380,25 +424,23 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __rest
                                                           uint32_t* __restrict__ bsrc, uint32_t last)
 {
     const unsigned long long m = *m_dev;
-    __shared__ uint32_t s_tmp[RS_WAVES];
+    __shared__ unsigned long long s_tmp[RS_WAVES];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
     uint32_t beg, end;
     block_span(*n_dev, nb, b, beg, end);
     unsigned long long carry = part_ex[b];
     for (uint32_t cb = beg; cb < end; cb += SC_THREADS * SC_ITEMS) {
-        // thread t owns SC_ITEMS consecutive elements; all index loads are
-        // issued before the dependent tile-count loads
-        uint32_t x[SC_ITEMS], s = 0;
+        // thread t owns SC_ITEMS consecutive elements
+        uint32_t x[SC_ITEMS];
+        unsigned long long s = 0;
         const uint32_t i0 = cb + (uint32_t)t * SC_ITEMS;
 #pragma unroll
-        for (int r = 0; r < SC_ITEMS; r++) x[r] = i0 + r < end ? pids[i0 + r] : 0u;
-#pragma unroll
         for (int r = 0; r < SC_ITEMS; r++) {
-            x[r] = i0 + r < end ? (uint32_t)tiles[x[r]] : 0u;
+            x[r] = i0 + r < end ? rect_count(srect[i0 + r]) : 0u;
             s += x[r];
         }
-        uint32_t tot;
-        uint32_t run = block_excl_scan_256(s, s_tmp, tot);
+        unsigned long long tot;
+        unsigned long long run = block_excl_scan_256_u64(s, s_tmp, tot);
         for (int r = 0; r < SC_ITEMS; r++) {
             const uint32_t i = i0 + r;
             if (i < end) {
@@ -425,16 +467,14 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
                                                        const uint32_t* __restrict__ offs,
                                                        const uint32_t* __restrict__ bsrc, uint32_t last,
                                                        const uint32_t* __restrict__ cnt,
-                                                       const float* __restrict__ splats,
-                                                       const int2* __restrict__ radii,
-                                                       long long N, ViewTable vt, int tile,
-                                                       uint32_t* __restrict__ keys_out,
+                                                       const int2* __restrict__ srect, long long N,
+                                                       ViewTable vt, uint32_t* __restrict__ keys_out,
                                                        uint32_t* __restrict__ vals_out)
 {
     __shared__ uint32_t s_off[EMIT_SPAN + 1];
     __shared__ uint32_t s_gid[EMIT_SPAN + 1];
     __shared__ uint32_t s_base[EMIT_SPAN + 1];
-    __shared__ uint32_t s_wt[EMIT_SPAN + 1];    // rect width << 16 | tiles_x... kept separate
+    __shared__ uint32_t s_wt[EMIT_SPAN + 1];
     __shared__ uint32_t s_tx[EMIT_SPAN + 1];
     const uint32_t m = cnt[1];
     const uint32_t start = blockIdx.x * (uint32_t)EMIT_SPAN;
@@ -446,25 +486,20 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     // exactly there; its slots then lie outside and are never selected)
     const uint32_t s0 = bsrc[blockIdx.x];
     const uint32_t s1 = end < m ? bsrc[blockIdx.x + 1] : bsrc[last];
-    const uint32_t ns = s1 - s0 + 1;
-    // at most EMIT_SPAN + 1 sources: each thread stages up to EMIT_SRC of
-    // them, issuing every gather before using any
+    // at most EMIT_SPAN + 1 sources (each has at least one slot); the clamp
+    // only guards the LDS arrays against inconsistent rectangles
+    const uint32_t ns = min(s1 - s0 + 1, (uint32_t)EMIT_SPAN + 1);
+    // every source's index, offset and rectangle are read in depth order
+    // (consecutive), all loads of a thread issued before any is used
     constexpr int EMIT_SRC = (EMIT_SPAN + 1 + EMIT_THREADS - 1) / EMIT_THREADS;
     uint32_t pid[EMIT_SRC], off[EMIT_SRC];
-    float2 uv[EMIT_SRC];
-    int2 rr[EMIT_SRC];
+    int2 rc[EMIT_SRC];
 #pragma unroll
     for (int q = 0; q < EMIT_SRC; q++) {
         const uint32_t k = (uint32_t)(t + q * EMIT_THREADS);
         pid[q] = k < ns ? pids[s0 + k] : 0u;
         off[q] = k < ns ? offs[s0 + k] : 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < EMIT_SRC; q++) {
-        const uint32_t k = (uint32_t)(t + q * EMIT_THREADS);
-        uv[q] = k < ns ? *reinterpret_cast<const float2*>(splats + (size_t)pid[q] * GS_SPLAT_FLOATS)
-                       : make_float2(0.0f, 0.0f);
-        rr[q] = k < ns ? radii[pid[q]] : make_int2(0, 0);
+        rc[q] = k < ns ? srect[s0 + k] : make_int2(0, 0);
     }
 #pragma unroll
     for (int q = 0; q < EMIT_SRC; q++) {
@@ -472,13 +507,12 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
         if (k >= ns) continue;
         const uint32_t v = (uint32_t)(pid[q] / (unsigned long long)N);
         const uint32_t g = pid[q] - v * (uint32_t)N;
-        int x0, y0, x1, y1;
-        tile_rect(uv[q].x, uv[q].y, rr[q].x, rr[q].y, tile, vt.W[v], vt.H[v], x0, y0, x1, y1);
+        const int x0 = rc[q].x & 0xFFFF, y0 = (int)((uint32_t)rc[q].x >> 16), x1 = rc[q].y & 0xFFFF;
         const int TX = vt.tiles_x[v];
         s_off[k] = off[q];
         s_gid[k] = g;
         s_base[k] = (uint32_t)(vt.tile_off[v] + y0 * TX + x0);
-        s_wt[k] = (uint32_t)(x1 - x0);
+        s_wt[k] = (uint32_t)max(x1 - x0, 1);
         s_tx[k] = (uint32_t)TX;
     }
     __syncthreads();
@@ -544,8 +578,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 uint32_t bsrc_last(unsigned long long cap) { return (uint32_t)((cap + EMIT_SPAN - 1) / EMIT_SPAN); }
 
 struct BinWs {
-    uint32_t *dk0, *dv0, *dk1, *dv1, *offs, *tk, *tv, *hist, *dtot, *part, *cnt, *bsrc;
-    unsigned long long* part_ex;
+    uint32_t *dk0, *dv0, *dk1, *dv1, *offs, *tk, *tv, *hist, *dtot, *cnt, *bsrc;
+    unsigned long long *part, *part_ex;
+    int2* srect;
     size_t bytes;
 };
 
@@ -567,7 +602,8 @@ BinWs bin_layout(char* base, unsigned long long vn, unsigned long long cap)
     w.tv = (uint32_t*)take(4 * cap);
     w.hist = (uint32_t*)take(4ull * 256 * RS_MAX_BLOCKS);
     w.dtot = (uint32_t*)take(4 * 256);
-    w.part = (uint32_t*)take(4 * RS_MAX_BLOCKS);
+    w.part = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
+    w.srect = (int2*)take(8 * vn);
     w.part_ex = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
     w.cnt = (uint32_t*)take(4 * 16);
     w.bsrc = (uint32_t*)take(4 * ((size_t)bsrc_last(cap) + 1));
@@ -589,8 +625,7 @@ size_t bin_sort_workspace_size(unsigned long long vn, unsigned long long cap)
     return bin_layout(nullptr, vn, cap).bytes;
 }
 
-hipError_t launch_bin_sort(const float* splats, const float* depths, const int2* radii,
-                           const int* tiles, long long N, const ViewTable& vt, int tile,
+hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, const ViewTable& vt,
                            unsigned long long cap, void* workspace, uint32_t* isect_tile,
                            uint32_t* isect_gid, int2* ranges, int* info, hipStream_t st)
 {
@@ -601,7 +636,7 @@ hipError_t launch_bin_sort(const float* splats, const float* depths, const int2*
     const int nb_d = sort_blocks(vn);
     SortIO io{};
     io.depths = depths;
-    io.tiles = tiles;
+    io.rects = rects;
     io.keys_out = w.dk0;
     io.vals_out = w.dv0;
     io.n_const = (uint32_t)vn;
@@ -619,11 +654,12 @@ hipError_t launch_bin_sort(const float* splats, const float* depths, const int2*
     const uint32_t* pids = vi;   // visible pairs in (depth, view, Gaussian) order
 
     // 2. scan of tiles_touched in that order
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb_d), dim3(SC_THREADS), 0, st, pids, tiles, w.cnt + 0, w.part);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb_d), dim3(SC_THREADS), 0, st, pids, rects, w.cnt + 0, w.srect,
+                       w.part);
     hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, st, w.part, nb_d, w.part_ex, (uint32_t)cap,
                        w.cnt, info);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb_d), dim3(SC_THREADS), 0, st, pids, tiles, w.cnt + 0,
-                       w.part_ex, (uint32_t)cap, w.cnt + 1, w.offs, w.bsrc, bsrc_last(cap));
+    hipLaunchKernelGGL(k_scan_down, dim3(nb_d), dim3(SC_THREADS), 0, st, w.srect, w.cnt + 0, w.part_ex,
+                       (uint32_t)cap, w.cnt + 1, w.offs, w.bsrc, bsrc_last(cap));
 
     // 3. emission; 4. tile passes (the last one lands in the caller's arrays)
     const int tbits = bits_for((unsigned long long)vt.total_tiles);
@@ -632,7 +668,7 @@ hipError_t launch_bin_sort(const float* splats, const float* depths, const int2*
     uint32_t *ev = (tpasses % 2 == 0) ? isect_gid : w.tv;
     const unsigned emit_blocks = (unsigned)((cap + EMIT_SPAN - 1) / EMIT_SPAN);
     hipLaunchKernelGGL(k_emit, dim3(emit_blocks), dim3(EMIT_THREADS), 0, st, pids, w.offs, w.bsrc,
-                       bsrc_last(cap), w.cnt, splats, radii, N, vt, tile, ek, ev);
+                       bsrc_last(cap), w.cnt, w.srect, N, vt, ek, ev);
     const int nb_t = sort_blocks(cap);
     uint32_t *tki = ek, *tvi = ev;
     uint32_t *tko = (ek == isect_tile) ? w.tk : isect_tile, *tvo = (ev == isect_gid) ? w.tv : isect_gid;

@@ -9,7 +9,7 @@ hipError_t launch_project(int deg, const float* means, const float* log_scales, 
                           const float* opac, const float* sh, long long N, const float* viewmats,
                           const float* intr, const ViewTable& vt, float near_plane, float far_plane,
                           float eps2d, int tile, int radius_mode, float* splats, float* depths, int2* radii,
-                          int* tiles, uint8_t* flags, hipStream_t stream);
+                          int* tiles, int2* rects, uint8_t* flags, hipStream_t stream);
 hipError_t launch_densify_stats(const float* grad2d, const uint8_t* flags, const int2* radii, long long N,
                                 const ViewTable& vt, float* grad_accum, int* count, int* max_radius,
                                 hipStream_t st);
@@ -20,8 +20,7 @@ hipError_t launch_project_bwd(int deg, const float* means, const float* log_scal
                               float* d_means, float* d_log_scales, float* d_quats, float* d_opac,
                               float* d_sh, hipStream_t stream);
 size_t bin_sort_workspace_size(unsigned long long vn, unsigned long long cap);
-hipError_t launch_bin_sort(const float* splats, const float* depths, const int2* radii,
-                           const int* tiles, long long N, const ViewTable& vt, int tile,
+hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, const ViewTable& vt,
                            unsigned long long cap, void* workspace, uint32_t* isect_tile,
                            uint32_t* isect_gid, int2* ranges, int* info, hipStream_t st);
 size_t tile_schedule_size(long long total_tiles);
@@ -113,7 +112,8 @@ int gs_project(const float* means, const float* log_scales, const float* quats,
                const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
                const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
                float near_plane, float far_plane, float eps2d, int tile, int radius_mode, float* splats,
-               float* depths, int32_t* radii, int32_t* tiles_touched, uint8_t* flags, void* stream)
+               float* depths, int32_t* radii, int32_t* tiles_touched, int32_t* tile_rects, uint8_t* flags,
+               void* stream)
 {
     ViewTable vt;
     if (n < 0 || n > 0x7FFFFFFFll || sh_degree < 0 || sh_degree > 3 || !tile_ok(tile) ||
@@ -125,13 +125,12 @@ int gs_project(const float* means, const float* log_scales, const float* quats,
     if (!(eps2d >= 0.0f) || !(near_plane > 0.0f) || !(far_plane > near_plane)) return GS_ERR_ARG;
     if (n == 0) return GS_OK;
     if (!means || !log_scales || !quats || !opacity_logits || !sh || !viewmats || !intrinsics ||
-        !splats || !depths || !radii || !tiles_touched || !flags || !aligned16(splats))
+        !splats || !depths || !radii || !tiles_touched || !tile_rects || !flags || !aligned16(splats))
         return GS_ERR_ARG;
     return status(gs::launch_project(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
                                      intrinsics, vt, near_plane, far_plane, eps2d, tile, radius_mode, splats,
-                                     depths,
-                                     reinterpret_cast<int2*>(radii), tiles_touched, flags,
-                                     as_stream(stream)));
+                                     depths, reinterpret_cast<int2*>(radii), tiles_touched,
+                                     reinterpret_cast<int2*>(tile_rects), flags, as_stream(stream)));
 }
 
 size_t gs_bin_sort_workspace_size(int64_t n, int n_views, int64_t capacity, int64_t total_tiles)
@@ -142,9 +141,8 @@ size_t gs_bin_sort_workspace_size(int64_t n, int n_views, int64_t capacity, int6
                                        (unsigned long long)capacity);
 }
 
-int gs_bin_sort(const float* splats, const float* depths, const int32_t* radii,
-                const int32_t* tiles_touched, int64_t n, int n_views, const int32_t* sizes, int tile,
-                int64_t capacity, void* workspace, size_t workspace_bytes, int32_t* isect_tile,
+int gs_bin_sort(const int32_t* tile_rects, const float* depths, int64_t n, int n_views, const int32_t* sizes,
+                int tile, int64_t capacity, void* workspace, size_t workspace_bytes, int32_t* isect_tile,
                 int32_t* isect_gid, int32_t* tile_ranges, int32_t* info, void* stream)
 {
     ViewTable vt;
@@ -153,12 +151,12 @@ int gs_bin_sort(const float* splats, const float* depths, const int32_t* radii,
     if ((unsigned long long)n * (unsigned long long)n_views > 0xFFFFFFFFull) return GS_ERR_ARG;
     if (capacity < 1 || capacity > 0x7FFFFFFFll) return GS_ERR_ARG;
     if (!isect_tile || !isect_gid || !tile_ranges || !info || !workspace) return GS_ERR_ARG;
-    if (n > 0 && (!splats || !depths || !radii || !tiles_touched)) return GS_ERR_ARG;
+    if (n > 0 && (!tile_rects || !depths)) return GS_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return GS_ERR_ARG;
     if (workspace_bytes < gs_bin_sort_workspace_size(n, n_views, capacity, vt.total_tiles))
         return GS_ERR_WORKSPACE;
-    return status(gs::launch_bin_sort(splats, depths, reinterpret_cast<const int2*>(radii), tiles_touched, n,
-                                      vt, tile, (unsigned long long)capacity, workspace,
+    return status(gs::launch_bin_sort(reinterpret_cast<const int2*>(tile_rects), depths, n, vt,
+                                      (unsigned long long)capacity, workspace,
                                       reinterpret_cast<uint32_t*>(isect_tile),
                                       reinterpret_cast<uint32_t*>(isect_gid),
                                       reinterpret_cast<int2*>(tile_ranges), info, as_stream(stream)));

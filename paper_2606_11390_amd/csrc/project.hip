@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void k_project(
     long long N, const float* __restrict__ viewmats, const float* __restrict__ intr, ViewTable vt,
     float near_plane, float far_plane, float eps2d, int tile, int radius_mode, float* __restrict__ splats,
     float* __restrict__ depths, int2* __restrict__ radii, int* __restrict__ tiles,
-    uint8_t* __restrict__ flags)
+    int2* __restrict__ rects, uint8_t* __restrict__ flags)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,6 +246,7 @@ __global__ __launch_bounds__(256) void k_project(
         bool vis = finite && ge.pz > near_plane && ge.pz < far_plane && sigma >= kAlphaMin &&
                    ge.D > 0.0f;
         int rx = 0, ry = 0, tt = 0;
+        int2 rc = make_int2(0, 0);
         float u = 0.0f, vv = 0.0f;
         if (vis) {
             u = cam.fx * ge.px / ge.pz + cam.cx;
@@ -268,6 +269,7 @@ __global__ __launch_bounds__(256) void k_project(
             tile_rect(u, vv, rx, ry, tile, cam.W, cam.H, x0, y0, x1, y1);
             tt = (x1 - x0) * (y1 - y0);
             vis = tt > 0;
+            rc = make_int2(x0 | (y0 << 16), x1 | (y1 << 16));
         }
         uint8_t fl = 0;
         if (vis) {
@@ -313,6 +315,7 @@ __global__ __launch_bounds__(256) void k_project(
         depths[o_vg] = ge.pz;
         radii[o_vg] = vis ? make_int2(rx, ry) : make_int2(0, 0);
         tiles[o_vg] = vis ? tt : 0;
+        rects[o_vg] = vis ? rc : make_int2(0, 0);
         flags[o_vg] = fl;
     }
 }
@@ -475,13 +478,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(
 #define GS_PROJ_LAUNCH(DEG)                                                                          \
     hipLaunchKernelGGL(k_project<DEG>, dim3(blocks), dim3(256), 0, stream, means, log_scales, quats, \
                        opac, sh, N, viewmats, intr, vt, near_plane, far_plane, eps2d, tile,          \
-                       radius_mode, splats, depths, radii, tiles, flags)
+                       radius_mode, splats, depths, radii, tiles, rects, flags)
 
 hipError_t launch_project(int deg, const float* means, const float* log_scales, const float* quats,
                           const float* opac, const float* sh, long long N, const float* viewmats,
                           const float* intr, const ViewTable& vt, float near_plane, float far_plane,
                           float eps2d, int tile, int radius_mode, float* splats, float* depths, int2* radii,
-                          int* tiles, uint8_t* flags, hipStream_t stream)
+                          int* tiles, int2* rects, uint8_t* flags, hipStream_t stream)
 {
     if (N == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((N + 255) / 256);

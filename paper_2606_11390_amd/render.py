@@ -67,6 +67,7 @@ class Renderer:
         self.depths = e(V * N)
         self.radii = e(V * N * 2, dt=torch.int32)
         self.tiles_touched = e(V * N, dt=torch.int32)
+        self.tile_rects = e(V * N * 2, dt=torch.int32)
         self.flags = e(V * N, dt=torch.uint8)
         self.ranges = e(self.total_tiles * 2, dt=torch.int32)
         self.info = torch.zeros(4, dtype=torch.int32, device=dev)
@@ -104,12 +105,12 @@ class Renderer:
     def project(self, P, cams):
         B.project(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
                   cams["viewmats"], cams["intrinsics"], self.sizes, self.near, self.far, self.eps2d,
-                  self.tile, self.splats, self.depths, self.radii, self.tiles_touched, self.flags,
-                  self.radius_mode)
+                  self.tile, self.splats, self.depths, self.radii, self.tiles_touched, self.tile_rects,
+                  self.flags, self.radius_mode)
 
     def bin_sort(self):
-        B.bin_sort(self.splats, self.depths, self.radii, self.tiles_touched, self.n, self.sizes, self.tile,
-                   self.capacity, self.workspace, self.isect_tile, self.isect_gid, self.ranges, self.info)
+        B.bin_sort(self.tile_rects, self.depths, self.n, self.sizes, self.tile, self.capacity, self.workspace,
+                   self.isect_tile, self.isect_gid, self.ranges, self.info)
         if "heavy" in (self.order, self.order_bwd) or "queue" in (self.order, self.order_bwd):
             B.tile_schedule(self.ranges, self.total_tiles, self.schedule)
 

@@ -42,6 +42,7 @@ def oracle_views(scene, tile, near=0.01, far=1e10, eps2d=0.3, P=None, radius_mod
     depth = np.zeros((V, N), F32)
     radii = np.zeros((V, N, 2), np.int32)
     tiles = np.zeros((V, N), np.int32)
+    rects = np.zeros((V, N, 2), np.int32)
     flags = np.zeros((V, N), np.uint8)
     for v in range(V):
         W, H = (int(x) for x in scene.sizes[v])
@@ -51,8 +52,15 @@ def oracle_views(scene, tile, near=0.01, far=1e10, eps2d=0.3, P=None, radius_mod
         depth[v] = pr["depth"].astype(F32)
         radii[v] = pr["radii"].T
         tiles[v] = pr["tiles"]
+        rects[v] = pack_rects(oracle.tile_rects(rec[v, :, 0], rec[v, :, 1], pr["radii"], tile, W, H))
         flags[v] = pr["visible"] | (pr["clamp"] << 1)
-    return P, projs, dict(splats=rec, depths=depth, radii=radii, tiles=tiles, flags=flags)
+    return P, projs, dict(splats=rec, depths=depth, radii=radii, tiles=tiles, rects=rects, flags=flags)
+
+
+def pack_rects(r):
+    """(x0, y0, x1, y1) rows -> the ABI's packed pair x0 | y0 << 16, x1 | y1 << 16."""
+    r = np.asarray(r, np.int64)
+    return np.stack([r[:, 0] | (r[:, 1] << 16), r[:, 2] | (r[:, 3] << 16)], axis=1).astype(np.int32)
 
 
 def oracle_binning(arrs, sizes, tile):
@@ -67,15 +75,16 @@ def gpu_project(scene, tile, near=0.01, far=1e10, eps2d=0.3, radius_mode=0):
     out = dict(splats=torch.zeros(V * N * 12, device="cuda"), depths=torch.zeros(V * N, device="cuda"),
                radii=torch.zeros(V * N * 2, dtype=torch.int32, device="cuda"),
                tiles=torch.zeros(V * N, dtype=torch.int32, device="cuda"),
+               rects=torch.zeros(V * N * 2, dtype=torch.int32, device="cuda"),
                flags=torch.zeros(V * N, dtype=torch.uint8, device="cuda"))
     B.project(dev(scene.means), dev(scene.log_scales), dev(scene.quats), dev(scene.opacity_logits),
               dev(scene.sh), scene.sh_degree, dev(scene.viewmats), dev(scene.intrinsics), scene.sizes, near,
-              far, eps2d, tile, out["splats"], out["depths"], out["radii"], out["tiles"], out["flags"],
-              radius_mode)
+              far, eps2d, tile, out["splats"], out["depths"], out["radii"], out["tiles"], out["rects"],
+              out["flags"], radius_mode)
     h = {k: host(v) for k, v in out.items()}
     return dict(splats=h["splats"].reshape(V, N, 12), depths=h["depths"].reshape(V, N),
                 radii=h["radii"].reshape(V, N, 2), tiles=h["tiles"].reshape(V, N),
-                flags=h["flags"].reshape(V, N))
+                rects=h["rects"].reshape(V, N, 2), flags=h["flags"].reshape(V, N))
 
 
 def gpu_bin_sort(arrs, sizes, tile, capacity):
@@ -87,9 +96,8 @@ def gpu_bin_sort(arrs, sizes, tile, capacity):
     ig = torch.full((capacity,), -7, dtype=torch.int32, device="cuda")
     rg = torch.full((2 * T,), -7, dtype=torch.int32, device="cuda")
     info = torch.full((4,), -7, dtype=torch.int32, device="cuda")
-    B.bin_sort(dev(arrs["splats"].reshape(-1)), dev(arrs["depths"].reshape(-1)),
-               dev(arrs["radii"].reshape(-1)), dev(arrs["tiles"].reshape(-1)), N, sizes, tile, capacity, ws,
-               it, ig, rg, info)
+    B.bin_sort(dev(arrs["rects"].reshape(-1)), dev(arrs["depths"].reshape(-1)), N, sizes, tile, capacity, ws, it,
+               ig, rg, info)
     return host(it), host(ig), host(rg).reshape(T, 2), host(info)
 
 

@@ -47,7 +47,7 @@ def test_host_side_argument_checks():
     # gs_project: negative N, bad degree, bad tile, bad view size, bad near/far
     args = lambda **kw: [kw.get("means", p), p, p, p, p, kw.get("n", 10), kw.get("deg", 0), p, p,
                          kw.get("sizes", szp), kw.get("V", 1), kw.get("near", 0.01), kw.get("far", 1e10),
-                         0.3, kw.get("tile", 16), kw.get("mode", 0), p, p, p, p, p, None]
+                         0.3, kw.get("tile", 16), kw.get("mode", 0), p, p, p, p, p, p, None]
     assert L.gs_project(*args(n=-1)) == -1
     assert L.gs_project(*args(deg=4)) == -1
     assert L.gs_project(*args(tile=12)) == -1
@@ -63,9 +63,9 @@ def test_host_side_argument_checks():
     ws = B.bin_sort_workspace_size(10, 1, 100, 12)
     assert ws > 0
     aligned = ctypes.c_void_p(256)
-    assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 100, aligned, ws - 1, p, p, p, p, None) == -4
-    assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 0, aligned, ws, p, p, p, p, None) == -1
-    assert L.gs_bin_sort(p, p, p, p, 10, 1, szp, 16, 100, ctypes.c_void_p(260), ws, p, p, p, p, None) == -1
+    assert L.gs_bin_sort(p, p, 10, 1, szp, 16, 100, aligned, ws - 1, p, p, p, p, None) == -4
+    assert L.gs_bin_sort(p, p, 10, 1, szp, 16, 0, aligned, ws, p, p, p, p, None) == -1
+    assert L.gs_bin_sort(p, p, 10, 1, szp, 16, 100, ctypes.c_void_p(260), ws, p, p, p, p, None) == -1
     # rasterisers: bad tile, missing outputs, a queue without a schedule
     bg = (ctypes.c_float * 3)(0, 0, 0)
     assert L.gs_rasterize_fwd(p, p, p, 10, 1, szp, 24, 0, 0, bg, None, None, p, p, p, None) == -1

@@ -85,6 +85,7 @@ def test_project_parity(name, tile):
         np.testing.assert_array_equal(gvis[ok], vis[ok])
         np.testing.assert_array_equal(g["radii"][v][ok], pr["radii"].T[ok])
         np.testing.assert_array_equal(g["tiles"][v][ok], pr["tiles"][ok])
+        np.testing.assert_array_equal(g["rects"][v][ok], arrs["rects"][v][ok])
         m = ok & vis
         np.testing.assert_array_equal(g["flags"][v][m] >> 1, pr["clamp"][m])
         rec = g["splats"][v][m].astype(np.float64)
