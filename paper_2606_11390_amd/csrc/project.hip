@@ -203,7 +203,10 @@ __device__ __forceinline__ void geometry(const Camera& cam, const float* mu, con
     g.D = (x0 * x0 + x1 * x1 + x2 * x2) + eps2d * (aa + cc) + eps2d * eps2d;
 }
 
-template <int DEG>
+// SV (one view): the SH coefficients are read where the colour sum uses
+// them instead of being kept for later views, which frees ~100 VGPRs at
+// degree 3 (occupancy 2 -> 6 waves per SIMD for this HBM-bound kernel).
+template <int DEG, bool SV>
 __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
@@ -236,9 +239,9 @@ __global__ __launch_bounds__(256) void k_project(
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
 
-    float coef[3 * K];
+    float coef[SV ? 1 : 3 * K];
     bool have_sh = false;
-    for (int v = 0; v < vt.n_views; v++) {
+    for (int v = 0; v < (SV ? 1 : vt.n_views); v++) {
         const Camera cam = load_camera(viewmats, intr, vt, v);
         const long long o_vg = (long long)v * N + g;
         Geo ge;
@@ -289,15 +292,18 @@ __global__ __launch_bounds__(256) void k_project(
             d0 *= idn; d1 *= idn; d2 *= idn;
             float Y[K];
             sh_basis<DEG>(d0, d1, d2, Y);
-            if (!have_sh) {
-                for (int j = 0; j < K; j++)
-                    for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
-                have_sh = true;
+            if constexpr (!SV) {
+                if (!have_sh) {
+                    for (int j = 0; j < K; j++)
+                        for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
+                    have_sh = true;
+                }
             }
             float col[3];
             for (int ch = 0; ch < 3; ch++) {
                 float acc = 0.0f;
-                for (int j = 0; j < K; j++) acc += coef[3 * j + ch] * Y[j];
+                for (int j = 0; j < K; j++)
+                    acc += (SV ? sh[((long long)j * 3 + ch) * N + g] : coef[SV ? 0 : 3 * j + ch]) * Y[j];
                 acc += 0.5f;
                 if (acc < 0.0f) fl |= (uint8_t)(GS_FLAG_CLAMP_R << ch);
                 col[ch] = fmaxf(acc, 0.0f);
@@ -320,7 +326,10 @@ __global__ __launch_bounds__(256) void k_project(
     }
 }
 
-template <int DEG>
+// SV (one view): SH gradients are written as soon as they are known and the
+// coefficients read where they are used, instead of accumulating and caching
+// 48 values each across views.
+template <int DEG, bool SV>
 __global__ __launch_bounds__(256) void k_project_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
@@ -336,8 +345,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     float gmu[3] = {0.0f, 0.0f, 0.0f};
     float gM[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     float gsig = 0.0f;
-    float gsh[3 * K];
-    for (int j = 0; j < 3 * K; j++) gsh[j] = 0.0f;
+    float gsh[SV ? 1 : 3 * K];
+    for (int j = 0; j < (SV ? 1 : 3 * K); j++) gsh[j] = 0.0f;
 
     bool any = false;
     for (int v = 0; v < vt.n_views; v++) any |= (flags[(long long)v * N + g] & GS_FLAG_VISIBLE) != 0;
@@ -360,13 +369,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
 
-    float coef[3 * K];
-    if (any) {
+    float coef[SV ? 1 : 3 * K];
+    if (!SV && any) {
         for (int j = 0; j < K; j++)
             for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
     }
+    // coefficient j, channel ch
+    auto cf = [&](int j, int ch) { return SV ? sh[((long long)j * 3 + ch) * N + g] : coef[SV ? 0 : 3 * j + ch]; };
 
-    for (int v = 0; any && v < vt.n_views; v++) {
+    for (int v = 0; any && v < (SV ? 1 : vt.n_views); v++) {
         const long long o_vg = (long long)v * N + g;
         const uint8_t fl = flags[o_vg];
         if (!(fl & GS_FLAG_VISIBLE)) continue;
@@ -432,10 +443,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(
         const float gc[3] = {(fl & GS_FLAG_CLAMP_R) ? 0.0f : gr[6], (fl & GS_FLAG_CLAMP_G) ? 0.0f : gr[7],
                              (fl & GS_FLAG_CLAMP_B) ? 0.0f : gr[8]};
         for (int j = 0; j < K; j++) {
-            sdot[j] = coef[3 * j] * gc[0] + coef[3 * j + 1] * gc[1] + coef[3 * j + 2] * gc[2];
-            gsh[3 * j] += Y[j] * gc[0];
-            gsh[3 * j + 1] += Y[j] * gc[1];
-            gsh[3 * j + 2] += Y[j] * gc[2];
+            sdot[j] = cf(j, 0) * gc[0] + cf(j, 1) * gc[1] + cf(j, 2) * gc[2];
+            if constexpr (SV) {
+                for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = Y[j] * gc[ch];
+            } else {
+                gsh[3 * j] += Y[j] * gc[0];
+                gsh[3 * j + 1] += Y[j] * gc[1];
+                gsh[3 * j + 2] += Y[j] * gc[2];
+            }
         }
         if (DEG > 0) {
             float gdx, gdy, gdz;
@@ -469,16 +484,23 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     for (int i = 0; i < 3; i++) d_log_scales[i * N + g] = any ? gl[i] : 0.0f;
     for (int k = 0; k < 4; k++) d_quats[k * N + g] = any ? (gq[k] - qh[k] * qd) * iq : 0.0f;
     d_opac[g] = any ? gsig * sigma * (1.0f - sigma) : 0.0f;
-    for (int j = 0; j < K; j++)
-        for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = gsh[3 * j + ch];
+    // (one view: a Gaussian that view sees had its SH gradients written above)
+    if (!SV || !any)
+        for (int j = 0; j < K; j++)
+            for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = SV ? 0.0f : gsh[3 * j + ch];
 }
 
 }  // namespace
 
-#define GS_PROJ_LAUNCH(DEG)                                                                          \
-    hipLaunchKernelGGL(k_project<DEG>, dim3(blocks), dim3(256), 0, stream, means, log_scales, quats, \
-                       opac, sh, N, viewmats, intr, vt, near_plane, far_plane, eps2d, tile,          \
-                       radius_mode, splats, depths, radii, tiles, rects, flags)
+#define GS_PROJ_LAUNCH(DEG)                                                                            \
+    if (vt.n_views == 1)                                                                               \
+        hipLaunchKernelGGL((k_project<DEG, true>), dim3(blocks), dim3(256), 0, stream, means, log_scales, \
+                           quats, opac, sh, N, viewmats, intr, vt, near_plane, far_plane, eps2d, tile,   \
+                           radius_mode, splats, depths, radii, tiles, rects, flags);                     \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_project<DEG, false>), dim3(blocks), dim3(256), 0, stream, means,            \
+                           log_scales, quats, opac, sh, N, viewmats, intr, vt, near_plane, far_plane,     \
+                           eps2d, tile, radius_mode, splats, depths, radii, tiles, rects, flags)
 
 hipError_t launch_project(int deg, const float* means, const float* log_scales, const float* quats,
                           const float* opac, const float* sh, long long N, const float* viewmats,
@@ -497,10 +519,15 @@ hipError_t launch_project(int deg, const float* means, const float* log_scales, 
     return hipGetLastError();
 }
 
-#define GS_PROJ_BWD_LAUNCH(DEG)                                                                    \
-    hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(blocks), dim3(256), 0, stream, means, log_scales,  \
-                       quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d, d_means,      \
-                       d_log_scales, d_quats, d_opac, d_sh)
+#define GS_PROJ_BWD_LAUNCH(DEG)                                                                        \
+    if (vt.n_views == 1)                                                                               \
+        hipLaunchKernelGGL((k_project_bwd<DEG, true>), dim3(blocks), dim3(256), 0, stream, means,         \
+                           log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,     \
+                           d_means, d_log_scales, d_quats, d_opac, d_sh);                                \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_project_bwd<DEG, false>), dim3(blocks), dim3(256), 0, stream, means,        \
+                           log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,     \
+                           d_means, d_log_scales, d_quats, d_opac, d_sh)
 
 hipError_t launch_project_bwd(int deg, const float* means, const float* log_scales,
                               const float* quats, const float* opac, const float* sh, long long N,
