@@ -167,7 +167,6 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
         int g_nxt = gids[min(r.x + GS_WAVE + lane, kl)];
         Rec cur = load_rec(base, gids[min(r.x + lane, kl)]);
         bool alive = true;
-        int nproc = 0;
         for (int kb = r.x; alive && kb < r.y; kb += GS_WAVE) {
             const Rec nxt = load_rec(base, g_nxt);
             const int g_nn = gids[min(kb + 2 * GS_WAVE + lane, kl)];
@@ -178,16 +177,12 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                              block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
             while (mask) {
-                // termination is tested every fourth composited entry: pixels
-                // that have stopped ignore the entries in between anyway
-                if ((nproc++ & 3) == 0) {
-                    bool all_done = true;
+                bool all_done = true;
 #pragma unroll
-                    for (int p = 0; p < P; p++) all_done = all_done && done[p];
-                    if (__ballot(!all_done) == 0ull) {
-                        alive = false;
-                        break;
-                    }
+                for (int p = 0; p < P; p++) all_done = all_done && done[p];
+                if (__ballot(!all_done) == 0ull) {
+                    alive = false;
+                    break;
                 }
                 const int j = __builtin_ctzll(mask);
                 mask &= mask - 1;
@@ -196,11 +191,21 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                 const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
                 const float dy = sv - fy;
                 const int k1 = kb + j - r.x + 1;
+                // alpha first: an entry no pixel of the wave takes costs no more
+                float alp[P];
+                bool okp[P], any = false;
+#pragma unroll
+                for (int p = 0; p < P; p++) {
+                    alp[p] = fminf(falloff(su - fx[p], dy, m00, m10, m11, ls).araw, kAlphaMax);
+                    okp[p] = !done[p] && alp[p] >= kAlphaMin;
+                    any = any || okp[p];
+                }
+                if (__ballot(any) == 0ull) continue;
                 const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
 #pragma unroll
                 for (int p = 0; p < P; p++) {
-                    const float al = fminf(falloff(su - fx[p], dy, m00, m10, m11, ls).araw, kAlphaMax);
-                    bool ok = !done[p] && al >= kAlphaMin;
+                    const float al = alp[p];
+                    bool ok = okp[p];
                     const float Tn = __builtin_fmaf(-T[p], al, T[p]);
                     const bool stop = ok && Tn < kTMin;
                     if (COUNT) stopk[p] = stop ? k1 : stopk[p];
