@@ -60,6 +60,18 @@ def make_scene(cfg, n_override=None):
     raise SystemExit(f"unknown config {cfg}")
 
 
+def per_step_ms(fn, steps, torch):
+    """Duration of each of `steps` calls (events between consecutive calls)."""
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
+    ev[-1].synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+
+
 def timed(fn, steps, torch):
     """Run fn `steps` times between two events on the current stream; ms per call."""
     torch.cuda.synchronize()
@@ -243,6 +255,7 @@ def main():
                 step()
         torch.cuda.synchronize()
         ms = timed(step, args.steps, torch)
+        r.step_fn = step
         return r, m, ms
 
     def run_plain_per_view():
@@ -320,6 +333,10 @@ def main():
         del rg
         torch.cuda.empty_cache()
         r_main, m, ms_main = run_path(tuned, True)
+        # per-step spread of the same step (after the timed block)
+        per = per_step_ms(r_main.step_fn, args.steps, torch)
+        result["per_step"] = {"median_ms": float(np.median(per)), "min_ms": float(np.min(per)),
+                              "max_ms": float(np.max(per))}
         log(f"batched (tile {tuned['tile']}, orders {tuned['order']} / {tuned['order_bwd']}, blocks {tuned['block']} / "
             f"{tuned['block_bwd']}): {ms_main:.3f} ms/step, "
             f"{pixels / ms_main / 1e3:.1f} MP/s, M={m}")
@@ -386,6 +403,8 @@ def main():
         "gaussians_per_s": round(gauss / ms_main * 1e3, 1),
         "plain": {k: round(v, 4) for k, v in result.get("plain", {}).items()},
         "batched_same_tile": result.get("batched_same_tile"),
+        "ms_per_step_spread": ({k: round(v, 4) for k, v in result["per_step"].items()}
+                               if "per_step" in result else None),
         "batched_generator_order": ({k: round(v, 4) for k, v in result["batched_generator_order"].items()}
                                     if "batched_generator_order" in result else None),
         "batched_opacity_radius": ({k: round(v, 4) for k, v in result["batched_opacity_radius"].items()}
