@@ -23,7 +23,11 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
 # per-file additions: the rasterisers' work-queue atomics are issued by one
 # lane and their result is read a whole tile later; the atomic optimizer would
 # rewrite them into a wave-aggregated form that reads the result at once
-FILE_FLAGS = {"raster.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+# The projection is compiled without floating-point contraction: its one-view
+# and several-view kernels differ in code shape, and the renders of a view
+# must not depend on which of them produced its splats.
+FILE_FLAGS = {"raster.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+              "project.hip": ["-ffp-contract=off"]}
 
 
 def sources():
