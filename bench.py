@@ -255,8 +255,7 @@ def main():
                 step()
         torch.cuda.synchronize()
         ms = timed(step, args.steps, torch)
-        r.step_fn = step
-        return r, m, ms
+        return r, m, ms, step
 
     def run_plain_per_view():
         """V single-view steps launched one after another (every call of the
@@ -290,7 +289,7 @@ def main():
         if scene.n_views > 1:
             r_plain, m, ms_plain = run_plain_per_view()
         else:
-            r_plain, m, ms_plain = run_path(None, False)
+            r_plain, m, ms_plain, _ = run_path(None, False)
         result["plain"] = {"ms_per_step": ms_plain, "mp_per_s": pixels / ms_plain / 1e3}
         log(f"plain: {ms_plain:.3f} ms/step, {pixels / ms_plain / 1e3:.1f} MP/s, M={m}")
         if args.only == "plain":
@@ -310,14 +309,14 @@ def main():
         if str(args.tile) in per_tile and tuned["tile"] != args.tile:
             # like-for-like figure at the plain path's tile edge
             t16 = per_tile[str(args.tile)]
-            r16, _, ms16 = run_path(t16, True)
+            r16, _, ms16, _ = run_path(t16, True)
             result["batched_same_tile"] = dict(t16, ms_per_step=ms16, mp_per_s=pixels / ms16 / 1e3)
             result["batched_same_tile"].pop("step_ms", None)
             del r16
             torch.cuda.empty_cache()
         # the same step with the opacity-aware screen box: identical images and
         # gradients from fewer intersections (reported beside the headline)
-        ro, mo, mso = run_path(tuned, True, radius_mode=B.RADIUS_OPACITY)
+        ro, mo, mso, _ = run_path(tuned, True, radius_mode=B.RADIUS_OPACITY)
         result["batched_opacity_radius"] = {"ms_per_step": mso, "mp_per_s": pixels / mso / 1e3,
                                             "intersections": int(mo)}
         log(f"batched, opacity-aware radius: {mso:.3f} ms/step, {pixels / mso / 1e3:.1f} MP/s, M={mo}")
@@ -326,15 +325,15 @@ def main():
         # the same step on the generator's order of the Gaussians
         P_m = P
         P = P_gen
-        rg, mg, msg = run_path(tuned, True)
+        rg, mg, msg, _ = run_path(tuned, True)
         result["batched_generator_order"] = {"ms_per_step": msg, "mp_per_s": pixels / msg / 1e3}
         log(f"batched, generator order of the Gaussians: {msg:.3f} ms/step, {pixels / msg / 1e3:.1f} MP/s, M={mg}")
         P = P_m
         del rg
         torch.cuda.empty_cache()
-        r_main, m, ms_main = run_path(tuned, True)
+        r_main, m, ms_main, step_main = run_path(tuned, True)
         # per-step spread of the same step (after the timed block)
-        per = per_step_ms(r_main.step_fn, args.steps, torch)
+        per = per_step_ms(step_main, args.steps, torch)
         result["per_step"] = {"median_ms": float(np.median(per)), "min_ms": float(np.min(per)),
                               "max_ms": float(np.max(per))}
         log(f"batched (tile {tuned['tile']}, orders {tuned['order']} / {tuned['order_bwd']}, blocks {tuned['block']} / "

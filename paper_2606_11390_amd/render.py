@@ -22,6 +22,8 @@ overflow word of ``gs_bin_sort`` tells the caller to grow it
 """
 from __future__ import annotations
 
+import gc
+
 import numpy as np
 import torch
 
@@ -190,6 +192,9 @@ class Renderer:
             for _ in range(warmup):
                 self.step(P, cams, targets, grads)
         torch.cuda.current_stream().wait_stream(s)
+        # a graph held only by a reference cycle must not be destroyed by the
+        # collector while this stream is capturing (HIP refuses that)
+        gc.collect()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self.step(P, cams, targets, grads)
