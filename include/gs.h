@@ -207,9 +207,11 @@ int gs_bin_sort(const int32_t* tile_rects, const float* depths, int64_t n, int n
 size_t gs_tile_schedule_size(int64_t total_tiles);
 
 /*
- * gs_tile_schedule - order tiles by decreasing list length (ties by tile
- * id), so that long tiles start first.  Writes order[T_total] (int32 global
- * tile ids) at the start of `schedule` (256-byte aligned).
+ * gs_tile_schedule - order tiles so that long lists start first: by
+ * decreasing list length rounded down to four significant bits (lengths
+ * below 8 kept exactly, lengths above 65535 taken as 65535), ties by tile
+ * id.  Writes order[T_total] (int32 global tile ids) at the start of
+ * `schedule` (256-byte aligned).
  */
 int gs_tile_schedule(const int32_t* tile_ranges, int64_t total_tiles, void* schedule,
                      size_t schedule_bytes, void* stream);
@@ -237,8 +239,8 @@ int gs_tile_order_xcd(int64_t total_tiles, int n_xcd, void* schedule, size_t sch
  * block_w, px_per_lane: the pixel block one wavefront covers (block_w wide,
  *   64 * px_per_lane / block_w rows) and the adjacent pixels each lane owns;
  *   0, 0 selects the default (8, 1).  Valid pairs: tile 8: (8, 1); tile 16:
- *   (8, 1), (16, 1), (16, 4); tile 32: (8, 1), (16, 4), (32, 4).  The choice
- *   changes only speed, never a result bit.
+ *   (8, 1), (16, 1), (16, 2), (16, 4); tile 32: (8, 1), (16, 2), (16, 4),
+ *   (32, 4).  The choice changes only speed, never a result bit.
  * schedule, queue: how tiles are assigned to workgroups.
  *   schedule NULL: one workgroup per tile, in tile order (queue must be NULL).
  *   schedule set, queue NULL: one workgroup per tile, workgroup b renders

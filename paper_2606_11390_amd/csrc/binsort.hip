@@ -37,7 +37,7 @@ constexpr int RS_WAVES = RS_THREADS / GS_WAVE;
 constexpr int RS_ITEMS = 8;
 constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;     // keys per chunk
 constexpr int RS_WAVE_SPAN = GS_WAVE * RS_ITEMS;     // keys per wave per chunk
-constexpr int RS_MAX_BLOCKS = 1024;
+constexpr int RS_MAX_BLOCKS = 4096;
 
 enum Source { SRC_PAIRS = 0, SRC_PROJ = 1, SRC_TILE_LEN = 2, SRC_MORTON = 3 };
 
@@ -119,9 +119,17 @@ __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t e
         v = i;
         return true;
     } else {
+        // longest lists first: 255 minus the list length rounded down to four
+        // significant bits (a one-pass key; the order only decides which
+        // tiles start first)
         const int2 r = io.ranges[i];
-        const uint32_t len = (uint32_t)min(r.y - r.x, 0xFFFF);
-        k = 0xFFFFu - len;
+        const uint32_t len = (uint32_t)min(max(r.y - r.x, 0), 0xFFFF);
+        uint32_t code = len;
+        if (len >= 8u) {
+            const uint32_t e = 31u - (uint32_t)__clz(len);   // 3 .. 15
+            code = ((e - 2u) << 3) | ((len >> (e - 3u)) & 7u);
+        }
+        k = 0xFFu - code;
         v = i;
         return true;
     }
@@ -205,28 +213,35 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortIO io, int shift, in
     }
 }
 
-// one block per digit: exclusive scan of its counts across the nb blocks
+// one block per digit: exclusive scan of its counts across the nb blocks, in
+// segments of blockDim.x counts with a running carry
 __global__ __launch_bounds__(1024) void k_rs_spine(uint32_t* __restrict__ hist, int nb,
                                                    uint32_t* __restrict__ dtot)
 {
     __shared__ uint32_t s_w[16];
     const int d = blockIdx.x, t = threadIdx.x, lane = __lane_id(), w = t / GS_WAVE;
-    const int nw = (blockDim.x + GS_WAVE - 1) / GS_WAVE;
-    const uint32_t x = t < nb ? hist[(size_t)d * nb + t] : 0u;
-    uint32_t inc = x;
-    for (int o = 1; o < GS_WAVE; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o);
-        if (lane >= o) inc += y;
+    const int nw = blockDim.x / GS_WAVE;
+    uint32_t carry = 0;
+    for (int s0 = 0; s0 < nb; s0 += blockDim.x) {
+        const int i = s0 + t;
+        const uint32_t x = i < nb ? hist[(size_t)d * nb + i] : 0u;
+        uint32_t inc = x;
+        for (int o = 1; o < GS_WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == GS_WAVE - 1) s_w[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int k = 0; k < nw; k++) {
+            if (k < w) before += s_w[k];
+            total += s_w[k];
+        }
+        if (i < nb) hist[(size_t)d * nb + i] = carry + before + inc - x;
+        carry += total;
+        __syncthreads();
     }
-    if (lane == GS_WAVE - 1) s_w[w] = inc;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-    for (int i = 0; i < nw; i++) {
-        if (i < w) before += s_w[i];
-        total += s_w[i];
-    }
-    if (t < nb) hist[(size_t)d * nb + t] = before + inc - x;
-    if (t == 0) dtot[d] = total;
+    if (t == 0) dtot[d] = carry;
 }
 
 template <int SRC>
@@ -297,7 +312,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
             const uint32_t k = s_k[j];
             const uint32_t d = (k >> shift) & mask;
             const uint32_t dst = s_base[d] + j - s_cex[d];
-            io.keys_out[dst] = k;
+            if (io.keys_out) io.keys_out[dst] = k;
             io.vals_out[dst] = s_v[j];
         }
         __syncthreads();
@@ -386,26 +401,33 @@ __global__ __launch_bounds__(1024) void k_scan_spine(const unsigned long long* _
 {
     __shared__ unsigned long long s_w[16];
     const int t = threadIdx.x, lane = __lane_id(), w = t / GS_WAVE;
-    const unsigned long long x = t < nb ? part[t] : 0ull;
-    unsigned long long inc = x;
-    for (int o = 1; o < GS_WAVE; o <<= 1) {
-        const unsigned long long y = __shfl_up(inc, o);
-        if (lane >= o) inc += y;
+    const int nw = blockDim.x / GS_WAVE;
+    unsigned long long carry = 0;
+    for (int s0 = 0; s0 < nb; s0 += blockDim.x) {
+        const int i = s0 + t;
+        const unsigned long long x = i < nb ? part[i] : 0ull;
+        unsigned long long inc = x;
+        for (int o = 1; o < GS_WAVE; o <<= 1) {
+            const unsigned long long y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == GS_WAVE - 1) s_w[w] = inc;
+        __syncthreads();
+        unsigned long long before = 0, total = 0;
+        for (int k = 0; k < nw; k++) {
+            if (k < w) before += s_w[k];
+            total += s_w[k];
+        }
+        if (i < nb) part_ex[i] = carry + before + inc - x;
+        carry += total;
+        __syncthreads();
     }
-    if (lane == GS_WAVE - 1) s_w[w] = inc;
-    __syncthreads();
-    unsigned long long before = 0, total = 0;
-    for (int i = 0; i < (int)(blockDim.x / GS_WAVE); i++) {
-        if (i < w) before += s_w[i];
-        total += s_w[i];
-    }
-    if (t < nb) part_ex[t] = before + inc - x;
     if (t == 0) {
         const unsigned long long cap = capacity;
-        cnt[1] = (uint32_t)(total < cap ? total : cap);
+        cnt[1] = (uint32_t)(carry < cap ? carry : cap);
         info[GS_INFO_VISIBLE] = (int)cnt[0];
-        info[GS_INFO_ISECT] = (int)(total < 0x7FFFFFFFull ? total : 0x7FFFFFFFull);
-        info[GS_INFO_OVERFLOW] = total > cap ? 1 : 0;
+        info[GS_INFO_ISECT] = (int)(carry < 0x7FFFFFFFull ? carry : 0x7FFFFFFFull);
+        info[GS_INFO_OVERFLOW] = carry > cap ? 1 : 0;
     }
 }
 
@@ -564,7 +586,7 @@ hipError_t radix_pass(const SortIO& io, int nb, int shift, int bits, uint32_t* h
                       uint32_t* count_out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rs_hist<SRC>, dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
-    const int sp_threads = ((nb + GS_WAVE - 1) / GS_WAVE) * GS_WAVE;
+    const int sp_threads = min(1024, ((nb + GS_WAVE - 1) / GS_WAVE) * GS_WAVE);
     hipLaunchKernelGGL(k_rs_spine, dim3(256), dim3(sp_threads), 0, st, hist, nb, dtot);
     hipLaunchKernelGGL(k_rs_scatter<SRC>, dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
                        dtot, count_out);
@@ -644,7 +666,8 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
     uint32_t *ki = w.dk0, *vi = w.dv0, *ko = w.dk1, *vo = w.dv1;
     for (int pass = 1; pass < 4; pass++) {
         SortIO p{};
-        p.keys_in = ki; p.vals_in = vi; p.keys_out = ko; p.vals_out = vo;
+        p.keys_in = ki; p.vals_in = vi; p.vals_out = vo;
+        p.keys_out = pass < 3 ? ko : nullptr;   // only the order of the last pass is used
         p.n_dev = w.cnt + 0;
         if ((e = radix_pass<SRC_PAIRS>(p, nb_d, 8 * pass, 8, w.hist, w.dtot, nullptr, st)) != hipSuccess)
             return e;
@@ -694,7 +717,7 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
 size_t tile_schedule_size(long long total_tiles)
 {
     const size_t t = (size_t)total_tiles;
-    return align256(4 * t) + 3 * align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS) + align256(4 * 256);
+    return align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS) + align256(4 * 256);
 }
 
 hipError_t launch_tile_schedule(const int2* ranges, long long total_tiles, void* schedule, hipStream_t st)
@@ -702,23 +725,16 @@ hipError_t launch_tile_schedule(const int2* ranges, long long total_tiles, void*
     char* base = (char*)schedule;
     const size_t t = (size_t)total_tiles;
     uint32_t* order = (uint32_t*)base;
-    uint32_t* k0 = (uint32_t*)(base + align256(4 * t));
-    uint32_t* k1 = (uint32_t*)(base + 2 * align256(4 * t));
-    uint32_t* v1 = (uint32_t*)(base + 3 * align256(4 * t));
-    uint32_t* hist = (uint32_t*)(base + 4 * align256(4 * t));
-    uint32_t* dtot = (uint32_t*)(base + 4 * align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS));
+    uint32_t* hist = (uint32_t*)(base + align256(4 * t));
+    uint32_t* dtot = (uint32_t*)(base + align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS));
     const int nb = sort_blocks(t);
+    // one stable 8-bit pass; only the tile ids (the values) are kept
     SortIO a{};
     a.ranges = ranges;
-    a.keys_out = k0;
-    a.vals_out = v1;
+    a.keys_out = nullptr;
+    a.vals_out = order;
     a.n_const = (uint32_t)t;
-    hipError_t e;
-    if ((e = radix_pass<SRC_TILE_LEN>(a, nb, 0, 8, hist, dtot, nullptr, st)) != hipSuccess) return e;
-    SortIO b{};
-    b.keys_in = k0; b.vals_in = v1; b.keys_out = k1; b.vals_out = order;
-    b.n_const = (uint32_t)t;
-    return radix_pass<SRC_PAIRS>(b, nb, 8, 8, hist, dtot, nullptr, st);
+    return radix_pass<SRC_TILE_LEN>(a, nb, 0, 8, hist, dtot, nullptr, st);
 }
 
 // order[b] for workgroup b of a grid launch: workgroups are handed to the

@@ -326,9 +326,10 @@ __global__ __launch_bounds__(256) void k_project(
     }
 }
 
-// SV (one view): SH gradients are written as soon as they are known and the
-// coefficients read where they are used, instead of accumulating and caching
-// 48 values each across views.
+// SV (one view): the SH gradient is the basis times the colour gradient, so
+// only the 16 basis values and 3 colour gradients are kept (not 48 sums), and
+// the coefficients are read where they are used instead of being cached
+// across views.
 template <int DEG, bool SV>
 __global__ __launch_bounds__(256) void k_project_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
@@ -347,6 +348,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     float gsig = 0.0f;
     float gsh[SV ? 1 : 3 * K];
     for (int j = 0; j < (SV ? 1 : 3 * K); j++) gsh[j] = 0.0f;
+    // one view: the SH basis and colour gradient, kept for one store of the
+    // SH gradient by every lane after the view loop (zero where unseen)
+    float Ysv[SV ? K : 1], gcsv[3] = {0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < (SV ? K : 1); j++) Ysv[j] = 0.0f;
 
     bool any = false;
     for (int v = 0; v < vt.n_views; v++) any |= (flags[(long long)v * N + g] & GS_FLAG_VISIBLE) != 0;
@@ -445,13 +450,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(
         for (int j = 0; j < K; j++) {
             sdot[j] = cf(j, 0) * gc[0] + cf(j, 1) * gc[1] + cf(j, 2) * gc[2];
             if constexpr (SV) {
-                for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = Y[j] * gc[ch];
+                Ysv[j] = Y[j];
             } else {
                 gsh[3 * j] += Y[j] * gc[0];
                 gsh[3 * j + 1] += Y[j] * gc[1];
                 gsh[3 * j + 2] += Y[j] * gc[2];
             }
         }
+        if constexpr (SV)
+            for (int ch = 0; ch < 3; ch++) gcsv[ch] = gc[ch];
         if (DEG > 0) {
             float gdx, gdy, gdz;
             sh_grad_dot<DEG>(d0, d1, d2, sdot, gdx, gdy, gdz);
@@ -461,6 +468,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(
             gmu[2] += (gdz - d2 * dg) * idn;
         }
     }
+
+    // every lane of the wave stores each SH plane at once: whole lines, not
+    // two partial writes (seen and unseen lanes) that may each reach HBM
+    if constexpr (SV)
+        for (int j = 0; j < K; j++)
+            for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = Ysv[j] * gcsv[ch];
 
     // M = R diag(s), s = exp(l):  dl_j = s_j sum_i dM_ij R_ij;  dR_ij = dM_ij s_j
     float gR[9];
@@ -484,10 +497,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     for (int i = 0; i < 3; i++) d_log_scales[i * N + g] = any ? gl[i] : 0.0f;
     for (int k = 0; k < 4; k++) d_quats[k * N + g] = any ? (gq[k] - qh[k] * qd) * iq : 0.0f;
     d_opac[g] = any ? gsig * sigma * (1.0f - sigma) : 0.0f;
-    // (one view: a Gaussian that view sees had its SH gradients written above)
-    if (!SV || !any)
+    if constexpr (!SV)
         for (int j = 0; j < K; j++)
-            for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = SV ? 0.0f : gsh[3 * j + ch];
+            for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = gsh[3 * j + ch];
 }
 
 }  // namespace

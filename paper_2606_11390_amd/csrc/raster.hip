@@ -574,8 +574,8 @@ bool raster_cfg_ok(int tile, int bw, int ppl)
     if (bw == 0 && ppl == 0) return tile == 8 || tile == 16 || tile == 32;
     switch (tile) {
     case 8: return bw == 8 && ppl == 1;
-    case 16: return (bw == 8 && ppl == 1) || (bw == 16 && ppl == 1) || (bw == 16 && ppl == 4);
-    case 32: return (bw == 8 && ppl == 1) || (bw == 16 && ppl == 4) || (bw == 32 && ppl == 4);
+    case 16: return (bw == 8 && ppl == 1) || (bw == 16 && (ppl == 1 || ppl == 2 || ppl == 4));
+    case 32: return (bw == 8 && ppl == 1) || (bw == 16 && (ppl == 2 || ppl == 4)) || (bw == 32 && ppl == 4);
     default: return false;
     }
 }
@@ -594,10 +594,12 @@ hipError_t launch_raster_fwd(int tile, int bw, int ppl, const ViewTable& vt, con
     case 8: GS_FWD(8, 8, 1);
     case 16:
         if (bw == 16 && ppl == 4) GS_FWD(16, 16, 4);
+        if (bw == 16 && ppl == 2) GS_FWD(16, 16, 2);
         if (bw == 16) GS_FWD(16, 16, 1);
         GS_FWD(16, 8, 1);
     default:
         if (bw == 32) GS_FWD(32, 32, 4);
+        if (bw == 16 && ppl == 2) GS_FWD(32, 16, 2);
         if (bw == 16) GS_FWD(32, 16, 4);
         GS_FWD(32, 8, 1);
     }
@@ -618,10 +620,12 @@ hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, con
     case 8: GS_BWD(8, 8, 1);
     case 16:
         if (bw == 16 && ppl == 4) GS_BWD(16, 16, 4);
+        if (bw == 16 && ppl == 2) GS_BWD(16, 16, 2);
         if (bw == 16) GS_BWD(16, 16, 1);
         GS_BWD(16, 8, 1);
     default:
         if (bw == 32) GS_BWD(32, 32, 4);
+        if (bw == 16 && ppl == 2) GS_BWD(32, 16, 2);
         if (bw == 16) GS_BWD(32, 16, 4);
         GS_BWD(32, 8, 1);
     }

@@ -354,7 +354,7 @@ def test_ssim_l1_parity(lam):
     assert G.rel_max(G.host(d), dref) <= 1e-4
 
 
-BLOCKS = {8: [(8, 1)], 16: [(8, 1), (16, 1), (16, 4)], 32: [(8, 1), (16, 4), (32, 4)]}
+BLOCKS = {8: [(8, 1)], 16: [(8, 1), (16, 1), (16, 2), (16, 4)], 32: [(8, 1), (16, 2), (16, 4), (32, 4)]}
 
 
 @pytest.mark.parametrize("name,tile", [("ragged", 16), ("multi", 16), ("ragged", 32), ("multi", 32)])
@@ -457,3 +457,34 @@ def test_morton_order_bit_exact_and_gather(n):
     out = torch.empty_like(sh)
     B.gather_columns(sh, order, out)
     np.testing.assert_array_equal(G.host(out), s.sh[:, :, :n][:, :, G.host(order)])
+
+
+def _schedule_ref(lens):
+    """Tile order of the schedule as documented: decreasing length rounded
+    down to four significant bits (exact below 8, capped at 65535), ties by
+    tile id."""
+    n = np.clip(np.asarray(lens, np.int64), 0, 65535)
+    code = n.copy()
+    big = n >= 8
+    e = np.floor(np.log2(np.maximum(n, 1))).astype(np.int64)
+    code[big] = ((e[big] - 2) << 3) | ((n[big] >> (e[big] - 3)) & 7)
+    return np.argsort(255 - code, kind="stable").astype(np.int32)
+
+
+@pytest.mark.parametrize("T", [1, 333, 200_000, 5_000_000])
+def test_tile_schedule_order(T):
+    """Schedule = the documented stable order (several sort blocks, and more
+    than 1024 of them at 5M tiles)."""
+    import torch
+    from paper_2606_11390_amd import binding as B
+    rng = np.random.default_rng(T)
+    lens = np.minimum(rng.pareto(1.2, T) * 20, 1e6).astype(np.int64)
+    lens[: min(T, 12)] = [0, 7, 8, 15, 16, 17, 31, 32, 65535, 65536, 999999, 3][: min(T, 12)]
+    start = np.concatenate([[0], np.cumsum(lens)[:-1]]) % (1 << 30)
+    ranges = np.stack([start, start + lens], axis=1).astype(np.int64)
+    ranges = np.clip(ranges, 0, 0x7FFFFFFF).astype(np.int32)
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    sched = torch.empty(B.tile_schedule_size(T), dtype=torch.uint8, device="cuda")
+    B.tile_schedule(G.dev(ranges.reshape(-1)), T, sched)
+    got = G.host(sched[: 4 * T].view(torch.int32))
+    np.testing.assert_array_equal(got, _schedule_ref(lens))
