@@ -145,7 +145,10 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
     const float fy = (float)U.py + 0.5f;
     float fx[P], T[P], C0[P], C1[P], C2[P];
     int last[P], stopk[P];
-    bool done[P];
+    // live[p]: wave-uniform mask of the lanes whose pixel p is still
+    // compositing.  Kept as a scalar bit mask (not a per-lane flag) so that
+    // every vote below is one compare and scalar mask arithmetic.
+    uint64_t live[P];
 #pragma unroll
     for (int p = 0; p < P; p++) {
         fx[p] = (float)(U.px0 + p) + 0.5f;
@@ -153,7 +156,7 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
         C0[p] = C1[p] = C2[p] = 0.0f;
         last[p] = 0;
         stopk[p] = -1;
-        done[p] = !(U.px0 + p < W && U.py < H);
+        live[p] = __ballot(U.px0 + p < W && U.py < H);
     }
     const int2 r = ranges[gt];
     const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
@@ -177,10 +180,10 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                              block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
             while (mask) {
-                bool all_done = true;
+                uint64_t any_live = 0;
 #pragma unroll
-                for (int p = 0; p < P; p++) all_done = all_done && done[p];
-                if (__ballot(!all_done) == 0ull) {
+                for (int p = 0; p < P; p++) any_live |= live[p];
+                if (any_live == 0ull) {
                     alive = false;
                     break;
                 }
@@ -191,26 +194,26 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                 const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
                 const float dy = sv - fy;
                 const int k1 = kb + j - r.x + 1;
-                // alpha first: an entry no pixel of the wave takes costs no more
+                // alpha first: an entry no live pixel of the wave takes costs no more
                 float alp[P];
-                bool okp[P], any = false;
+                uint64_t take[P], any_take = 0;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
                     alp[p] = fminf(falloff(su - fx[p], dy, m00, m10, m11, ls).araw, kAlphaMax);
-                    okp[p] = !done[p] && alp[p] >= kAlphaMin;
-                    any = any || okp[p];
+                    take[p] = __ballot(alp[p] >= kAlphaMin) & live[p];
+                    any_take |= take[p];
                 }
-                if (__ballot(any) == 0ull) continue;
+                if (any_take == 0ull) continue;
                 const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
 #pragma unroll
                 for (int p = 0; p < P; p++) {
                     const float al = alp[p];
-                    bool ok = okp[p];
                     const float Tn = __builtin_fmaf(-T[p], al, T[p]);
-                    const bool stop = ok && Tn < kTMin;
-                    if (COUNT) stopk[p] = stop ? k1 : stopk[p];
-                    done[p] = done[p] || stop;
-                    ok = ok && !stop;
+                    // a pixel stops before the entry that would take T below 1e-4
+                    const uint64_t stop = __ballot(Tn < kTMin) & take[p];
+                    live[p] &= ~stop;
+                    if (COUNT) stopk[p] = __builtin_amdgcn_inverse_ballot_w64(stop) ? k1 : stopk[p];
+                    const bool ok = __builtin_amdgcn_inverse_ballot_w64(take[p] & ~stop);
                     const float wgt = ok ? al * T[p] : 0.0f;
                     C0[p] = __builtin_fmaf(wgt, cr, C0[p]);
                     C1[p] = __builtin_fmaf(wgt, cg, C1[p]);
