@@ -498,11 +498,13 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     __shared__ uint32_t s_base[EMIT_SPAN + 1];
     __shared__ uint32_t s_wt[EMIT_SPAN + 1];
     __shared__ uint32_t s_tx[EMIT_SPAN + 1];
+    __shared__ __align__(16) uint32_t s_src[EMIT_SPAN];   // source of each slot
+    __shared__ uint32_t s_wmax[EMIT_THREADS / GS_WAVE];
     const uint32_t m = cnt[1];
     const uint32_t start = blockIdx.x * (uint32_t)EMIT_SPAN;
     if (start >= m) return;
     const uint32_t end = min(m, start + (uint32_t)EMIT_SPAN);
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = __lane_id(), w = t / GS_WAVE;
     // sources of this workgroup's slots: from the one holding its first slot
     // to the one holding the next workgroup's first slot (which may start
     // exactly there; its slots then lie outside and are never selected)
@@ -523,6 +525,12 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
         off[q] = k < ns ? offs[s0 + k] : 0u;
         rc[q] = k < ns ? srect[s0 + k] : make_int2(0, 0);
     }
+    for (int i = t; i < EMIT_SPAN; i += EMIT_THREADS) s_src[i] = 0u;
+    __syncthreads();
+    // each source marks the slot where it starts (the first source, which
+    // starts at or before this workgroup's first slot, marks slot 0); slots
+    // of one source are consecutive and every source has one, so the source
+    // of a slot is the last mark at or before it: a prefix maximum
 #pragma unroll
     for (int q = 0; q < EMIT_SRC; q++) {
         const uint32_t k = (uint32_t)(t + q * EMIT_THREADS);
@@ -536,14 +544,32 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
         s_base[k] = (uint32_t)(vt.tile_off[v] + y0 * TX + x0);
         s_wt[k] = (uint32_t)max(x1 - x0, 1);
         s_tx[k] = (uint32_t)TX;
+        if (off[q] < end) s_src[off[q] > start ? off[q] - start : 0u] = k;
     }
     __syncthreads();
+    // inclusive max-scan over the EMIT_SPAN marks, thread t owning 8 in a row
+    static_assert(EMIT_SPAN == 8 * EMIT_THREADS, "8 slots per thread");
+    uint4 a = *reinterpret_cast<const uint4*>(&s_src[8 * t]);
+    uint4 b = *reinterpret_cast<const uint4*>(&s_src[8 * t + 4]);
+    a.y = max(a.y, a.x); a.z = max(a.z, a.y); a.w = max(a.w, a.z);
+    b.x = max(b.x, a.w); b.y = max(b.y, b.x); b.z = max(b.z, b.y); b.w = max(b.w, b.z);
+    uint32_t inc = b.w;
+    for (int o = 1; o < GS_WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc = max(inc, y);
+    }
+    if (lane == GS_WAVE - 1) s_wmax[w] = inc;
+    uint32_t ex = __shfl_up(inc, 1);
+    if (lane == 0) ex = 0u;
+    __syncthreads();
+    for (int i = 0; i < w; i++) ex = max(ex, s_wmax[i]);
+    a.x = max(a.x, ex); a.y = max(a.y, ex); a.z = max(a.z, ex); a.w = max(a.w, ex);
+    b.x = max(b.x, ex); b.y = max(b.y, ex); b.z = max(b.z, ex); b.w = max(b.w, ex);
+    *reinterpret_cast<uint4*>(&s_src[8 * t]) = a;
+    *reinterpret_cast<uint4*>(&s_src[8 * t + 4]) = b;
+    __syncthreads();
     for (uint32_t i = start + t; i < end; i += EMIT_THREADS) {
-        uint32_t lo = 0, hi = ns - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
-        }
+        const uint32_t lo = s_src[i - start];
         const uint32_t j = i - s_off[lo];
         const uint32_t wdt = s_wt[lo];
         const uint32_t row = j / wdt, col = j - row * wdt;
@@ -561,16 +587,32 @@ __global__ void k_fill_i32(int* __restrict__ p, int value, long long n)
     if (i < n) p[i] = value;
 }
 
+// thread t looks at keys 4t .. 4t + 3 (one 16-byte load) and their outer
+// neighbours; a run boundary between two keys sets the end of one tile's
+// range and the start of the next
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ cnt,
                          uint32_t total_tiles, int2* __restrict__ ranges)
 {
     const uint32_t m = cnt[1];
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const uint32_t k = keys[i];
-    if (k >= total_tiles) return;   // cannot happen for consistent inputs; never write out of range
-    if (i == 0 || keys[i - 1] != k) ranges[k].x = (int)i;
-    if (i == m - 1 || keys[i + 1] != k) ranges[k].y = (int)(i + 1);
+    const uint32_t i0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 >= m) return;
+    uint32_t k[6];   // keys i0 - 1 .. i0 + 4; 0xFFFFFFFF outside [0, m)
+    k[0] = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+    if (i0 + 4 <= m) {
+        const uint4 q = *reinterpret_cast<const uint4*>(keys + i0);
+        k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+    } else {
+        for (int r = 0; r < 4; r++) k[1 + r] = i0 + r < m ? keys[i0 + r] : 0xFFFFFFFFu;
+    }
+    k[5] = i0 + 4 < m ? keys[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const uint32_t i = i0 + r, c = k[1 + r];
+        // keys >= total_tiles cannot occur for consistent inputs; never write out of range
+        if (i >= m || c >= total_tiles) continue;
+        if (k[r] != c) ranges[c].x = (int)i;
+        if (k[r + 2] != c) ranges[c].y = (int)(i + 1);
+    }
 }
 
 int sort_blocks(unsigned long long n_max)
@@ -709,7 +751,7 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
     // 5. ranges
     const long long nr = 2ll * vt.total_tiles;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, (int*)ranges, 0, nr);
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, isect_tile, w.cnt,
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 1023) / 1024)), dim3(256), 0, st, isect_tile, w.cnt,
                        (uint32_t)vt.total_tiles, ranges);
     return hipGetLastError();
 }
