@@ -203,10 +203,9 @@ __device__ __forceinline__ void geometry(const Camera& cam, const float* mu, con
     g.D = (x0 * x0 + x1 * x1 + x2 * x2) + eps2d * (aa + cc) + eps2d * eps2d;
 }
 
-// The SH coefficients are read where the colour sum uses them, once per view
-// that sees the Gaussian (later views hit in L2), instead of being kept in
-// registers across views: 48 fewer live values at degree 3, occupancy 2 -> 8
-// waves per SIMD for this HBM-bound kernel.  SV: compiled for one view.
+// SV (one view): the SH coefficients are read where the colour sum uses
+// them instead of being kept for later views, which frees ~100 VGPRs at
+// degree 3 (occupancy 2 -> 6 waves per SIMD for this HBM-bound kernel).
 template <int DEG, bool SV>
 __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ means, const float* __restrict__ log_scales,
@@ -240,6 +239,8 @@ __global__ __launch_bounds__(256) void k_project(
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
 
+    float coef[SV ? 1 : 3 * K];
+    bool have_sh = false;
     for (int v = 0; v < (SV ? 1 : vt.n_views); v++) {
         const Camera cam = load_camera(viewmats, intr, vt, v);
         const long long o_vg = (long long)v * N + g;
@@ -291,10 +292,18 @@ __global__ __launch_bounds__(256) void k_project(
             d0 *= idn; d1 *= idn; d2 *= idn;
             float Y[K];
             sh_basis<DEG>(d0, d1, d2, Y);
+            if constexpr (!SV) {
+                if (!have_sh) {
+                    for (int j = 0; j < K; j++)
+                        for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
+                    have_sh = true;
+                }
+            }
             float col[3];
             for (int ch = 0; ch < 3; ch++) {
                 float acc = 0.0f;
-                for (int j = 0; j < K; j++) acc += sh[((long long)j * 3 + ch) * N + g] * Y[j];
+                for (int j = 0; j < K; j++)
+                    acc += (SV ? sh[((long long)j * 3 + ch) * N + g] : coef[SV ? 0 : 3 * j + ch]) * Y[j];
                 acc += 0.5f;
                 if (acc < 0.0f) fl |= (uint8_t)(GS_FLAG_CLAMP_R << ch);
                 col[ch] = fmaxf(acc, 0.0f);
@@ -318,7 +327,7 @@ __global__ __launch_bounds__(256) void k_project(
 }
 
 // SV (one view): the SH gradient is the basis times the colour gradient, so
-// only the 16 basis values and 3 colour gradients are kept.  In both forms
+// only the 16 basis values and 3 colour gradients are kept (not 48 sums), and
 // the coefficients are read where they are used instead of being cached
 // across views.
 template <int DEG, bool SV>
@@ -337,15 +346,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     float gmu[3] = {0.0f, 0.0f, 0.0f};
     float gM[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     float gsig = 0.0f;
+    float gsh[SV ? 1 : 3 * K];
+    for (int j = 0; j < (SV ? 1 : 3 * K); j++) gsh[j] = 0.0f;
     // one view: the SH basis and colour gradient, kept for one store of the
-    // SH gradient by every lane after the view loop (zero where unseen).
-    // Several views: the SH gradient is summed in place in d_sh (zeroed here
-    // by every lane, then one read-add-write per view that sees the
-    // Gaussian, in view order), which keeps 48 sums out of registers.
+    // SH gradient by every lane after the view loop (zero where unseen)
     float Ysv[SV ? K : 1], gcsv[3] = {0.0f, 0.0f, 0.0f};
     for (int j = 0; j < (SV ? K : 1); j++) Ysv[j] = 0.0f;
-    if constexpr (!SV)
-        for (int j = 0; j < 3 * K; j++) d_sh[(long long)j * N + g] = 0.0f;
 
     bool any = false;
     for (int v = 0; v < vt.n_views; v++) any |= (flags[(long long)v * N + g] & GS_FLAG_VISIBLE) != 0;
@@ -368,8 +374,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
 
-    // coefficient j, channel ch (read where used; a later view hits in L2)
-    auto cf = [&](int j, int ch) { return sh[((long long)j * 3 + ch) * N + g]; };
+    float coef[SV ? 1 : 3 * K];
+    if (!SV && any) {
+        for (int j = 0; j < K; j++)
+            for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
+    }
+    // coefficient j, channel ch
+    auto cf = [&](int j, int ch) { return SV ? sh[((long long)j * 3 + ch) * N + g] : coef[SV ? 0 : 3 * j + ch]; };
 
     for (int v = 0; any && v < (SV ? 1 : vt.n_views); v++) {
         const long long o_vg = (long long)v * N + g;
@@ -441,10 +452,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(
             if constexpr (SV) {
                 Ysv[j] = Y[j];
             } else {
-                for (int ch = 0; ch < 3; ch++) {
-                    float* d = d_sh + ((long long)j * 3 + ch) * N + g;
-                    *d = *d + Y[j] * gc[ch];
-                }
+                gsh[3 * j] += Y[j] * gc[0];
+                gsh[3 * j + 1] += Y[j] * gc[1];
+                gsh[3 * j + 2] += Y[j] * gc[2];
             }
         }
         if constexpr (SV)
@@ -487,6 +497,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     for (int i = 0; i < 3; i++) d_log_scales[i * N + g] = any ? gl[i] : 0.0f;
     for (int k = 0; k < 4; k++) d_quats[k * N + g] = any ? (gq[k] - qh[k] * qd) * iq : 0.0f;
     d_opac[g] = any ? gsig * sigma * (1.0f - sigma) : 0.0f;
+    if constexpr (!SV)
+        for (int j = 0; j < K; j++)
+            for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = gsh[3 * j + ch];
 }
 
 }  // namespace
