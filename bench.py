@@ -251,8 +251,10 @@ def main():
             step = r.replay
         else:
             step = lambda: r.step(P, cams, tg, grads)
-            for _ in range(args.warmup):
-                step()
+        # untimed warm-up of the step as it is timed (a graph's first replays
+        # include its upload)
+        for _ in range(max(1, args.warmup)):
+            step()
         torch.cuda.synchronize()
         ms = timed(step, args.steps, torch)
         return r, m, ms, step

@@ -108,26 +108,40 @@ __device__ __forceinline__ float bfly(float even, float odd, bool hi)
     return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xF, 0xF, false));
 }
 
+// bfly(x, 0, hi): the lane without `hi` gets the pair-sum of x, the other 0
+template <int CTRL>
+__device__ __forceinline__ float bfly0(float x, bool hi)
+{
+    const float s = x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    return hi ? 0.0f : s;
+}
+
 // Wave-wide sums of nine values, scattered: afterwards lane l (l < 16) holds
 // the total of value j(l) = b3 + 2 b2 + 4 b0 + 8 b1 (b_k = bit k of l), a
 // permutation of 0..15 in which 9..15 carry zeros.  The four in-row steps
 // pair lanes across bit 3 (row mirror), bit 2 (half-row mirror), bit 0 and
 // bit 1 (quad permutes); two shuffles then add the four rows.  About 40 VALU
 // operations instead of nine full reductions.
+// the value index j(l) whose total lane l holds after wave_sum9_scatter
+__device__ __forceinline__ int wave_sum9_slot(int l)
+{
+    return ((l & 8) ? 1 : 0) | ((l & 4) ? 2 : 0) | ((l & 1) ? 4 : 0) | ((l & 2) ? 8 : 0);
+}
+
 __device__ __forceinline__ float wave_sum9_scatter(const float* a, int& j)
 {
     const int l = __lane_id();
     const bool h1 = l & 8, h2 = l & 4, h3 = l & 1, h4 = l & 2;
     const float b0 = bfly<0x140>(a[0], a[1], h1), b1 = bfly<0x140>(a[2], a[3], h1);
     const float b2 = bfly<0x140>(a[4], a[5], h1), b3 = bfly<0x140>(a[6], a[7], h1);
-    const float b4 = bfly<0x140>(a[8], 0.0f, h1);
+    const float b4 = bfly0<0x140>(a[8], h1);
     const float c0 = bfly<0x141>(b0, b1, h2), c1 = bfly<0x141>(b2, b3, h2);
-    const float c2 = bfly<0x141>(b4, 0.0f, h2);
-    const float d0 = bfly<0xB1>(c0, c1, h3), d1 = bfly<0xB1>(c2, 0.0f, h3);
+    const float c2 = bfly0<0x141>(b4, h2);
+    const float d0 = bfly<0xB1>(c0, c1, h3), d1 = bfly0<0xB1>(c2, h3);
     float e = bfly<0x4E>(d0, d1, h4);
     e += __shfl_xor(e, 16);
     e += __shfl_xor(e, 32);
-    j = (h1 ? 1 : 0) | (h2 ? 2 : 0) | (h3 ? 4 : 0) | (h4 ? 8 : 0);
+    j = wave_sum9_slot(l);
     return e;
 }
 

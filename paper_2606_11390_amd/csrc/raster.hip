@@ -43,6 +43,14 @@ struct WaveStage {
     int gid[GS_WAVE];
 };
 
+// A wave's copy of its current batch's colours in LDS: the forward reads an
+// entry's colour with one broadcast LDS load instead of three readlanes (the
+// position and conic terms, needed for every entry, stay on readlanes so
+// that the LDS return path is not the limit).
+struct ColStage {
+    float4 col[GS_WAVE];
+};
+
 __device__ __forceinline__ Rec load_rec(const float* __restrict__ base, int gid)
 {
     const float4* p = reinterpret_cast<const float4*>(base + (size_t)gid * GS_SPLAT_FLOATS);
@@ -136,7 +144,7 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                                          const int2* __restrict__ ranges, long long N, float bg0,
                                          float bg1, float bg2, float* __restrict__ img,
                                          float* __restrict__ Tout, int* __restrict__ lastout,
-                                         int* __restrict__ visits)
+                                         int* __restrict__ visits, ColStage* __restrict__ cst)
 {
     using L = Layout<TS, BW, P>;
     const Unit U = unit_of<TS, BW, P>(vt, gt, wit);
@@ -179,6 +187,9 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                              !misses(__float_as_int(cur.c.w), U.by0, by1) &&
                              block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
+            // the previous batch's reads of the stage precede this write in
+            // the wave's program order, and LDS serves one wave in order
+            cst->col[lane] = make_float4(cur.b.z, cur.b.w, cur.c.x, 0.0f);
             while (mask) {
                 uint64_t any_live = 0;
 #pragma unroll
@@ -204,7 +215,8 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                     any_take |= take[p];
                 }
                 if (any_take == 0ull) continue;
-                const float cr = lane_f(cur.b.z, j), cg = lane_f(cur.b.w, j), cb = lane_f(cur.c.x, j);
+                const float4 cc = cst->col[j];
+                const float cr = cc.x, cg = cc.y, cb = cc.z;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
                     const float al = alp[p];
@@ -289,6 +301,9 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
     const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
     float* gbase = grad2d + (size_t)U.v * (size_t)N * GS_GRAD_FLOATS;
     const int lane = __lane_id();
+    // factor of the gradient value this lane's wave sum carries
+    const int jl = wave_sum9_slot(lane);
+    const float gscale = jl < 2 ? 2.0f : (jl == 3 ? 2.0f * kC0 : (jl == 2 || jl == 4 ? kC0 : 1.0f));
     // batches walk the list from its last contributing entry backwards: lane
     // l of the batch starting at kb holds entry kb - l.  As in the forward,
     // the next batch's records and the one after's indices are in flight
@@ -333,9 +348,9 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                 const float2 rc = *reinterpret_cast<const float2*>(&stage->rec[2][j]);
                 const float cr = rb.z, cg = rb.w, cb = rc.x;
                 const float inv_sig = __builtin_amdgcn_rcpf(rc.y);
+                // a0..a4 leave out constant factors (2, 2, c0, 2 c0, c0) that
+                // are applied once to the wave sums (gscale)
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
-                // per-entry constants of the conic terms (q' = c0 (A dx^2 + 2 B dx dy + C dy^2))
-                const float dyc = kC0 * dy, dyc2 = 2.0f * kC0 * dy;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
                     const float dx = su - fx[p];
@@ -359,24 +374,22 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                     a7 = __builtin_fmaf(wgt, g1[p], a7);
                     a8 = __builtin_fmaf(wgt, g2[p], a8);
                     a5 = __builtin_fmaf(f.araw * inv_sig, gu, a5);
-                    // q' = |M^T d|^2:  dq'/du = 2 (M w)_x, dq'/dv = 2 (M w)_y
+                    // q' = |M^T d|^2:  dq'/du = 2 (M w)_x, dq'/dv = 2 (M w)_y;
+                    // q' = c0 (A dx^2 + 2 B dx dy + C dy^2)
                     a0 = __builtin_fmaf(gq, m00 * f.w0, a0);
                     a1 = __builtin_fmaf(gq, __builtin_fmaf(m10, f.w0, m11 * f.w1), a1);
                     const float gqx = gq * dx;
-                    a2 = __builtin_fmaf(gqx * kC0, dx, a2);
-                    a3 = __builtin_fmaf(gqx, dyc2, a3);
-                    a4 = __builtin_fmaf(gq, dyc * dy, a4);
+                    a2 = __builtin_fmaf(gqx, dx, a2);
+                    a3 = __builtin_fmaf(gqx, dy, a3);
+                    a4 = __builtin_fmaf(gq * dy, dy, a4);
                     S0[p] = __builtin_fmaf(alo, d0, S0[p]);
                     S1[p] = __builtin_fmaf(alo, d1, S1[p]);
                     S2[p] = __builtin_fmaf(alo, d2, S2[p]);
                     T[p] = Tk;
                 }
-                // dq'/du, dq'/dv carry a factor 2
-                a0 *= 2.0f;
-                a1 *= 2.0f;
                 const float acc[GS_GRAD_FLOATS] = {a0, a1, a2, a3, a4, a5, a6, a7, a8};
                 int jj;
-                const float x = wave_sum9_scatter(acc, jj);
+                const float x = wave_sum9_scatter(acc, jj) * gscale;
                 if (lane < 16 && jj < GS_GRAD_FLOATS)
                     unsafeAtomicAdd(gbase + (size_t)gid * GS_GRAD_FLOATS + jj, x);
             }
@@ -427,10 +440,12 @@ __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_f
     const int* __restrict__ order, float* __restrict__ img, float* __restrict__ Tout,
     int* __restrict__ lastout, int* __restrict__ visits)
 {
+    __shared__ ColStage cst[Layout<TS, BW, P>::WPT];
     const int gt = tile_of_block(order, vt.total_tiles);
     if (gt < 0) return;
     const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
-    fwd_unit<TS, BW, P, COUNT>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout, lastout, visits);
+    fwd_unit<TS, BW, P, COUNT>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout, lastout, visits,
+                               &cst[wit]);
 }
 
 template <int TS, int BW, int P>
@@ -441,6 +456,7 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
     float* __restrict__ Tout, int* __restrict__ lastout)
 {
     using L = Layout<TS, BW, P>;
+    __shared__ ColStage cst;
     const int n_items = vt.total_tiles * L::WPT;
     const int n_chunks = (n_items + QCHUNK - 1) / QCHUNK;
     // the next chunk is claimed before the current one is processed, so the
@@ -452,7 +468,7 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
             const int gt = order[item / L::WPT];
             if ((unsigned)gt < (unsigned)vt.total_tiles)
                 fwd_unit<TS, BW, P, false>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, img,
-                                           Tout, lastout, nullptr);
+                                           Tout, lastout, nullptr, &cst);
         }
         c = ticket(next);
     }
