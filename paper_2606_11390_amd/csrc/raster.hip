@@ -43,11 +43,13 @@ struct WaveStage {
     int gid[GS_WAVE];
 };
 
-// A wave's copy of its current batch's colours in LDS: the forward reads an
-// entry's colour with one broadcast LDS load instead of three readlanes (the
-// position and conic terms, needed for every entry, stay on readlanes so
-// that the LDS return path is not the limit).
+// A wave's copy of part of its current batch in LDS: the forward reads an
+// entry's (u, v, m00, m10) and its colour with broadcast LDS loads instead
+// of seven readlanes, which take vector issue slots from the per-pixel work
+// that bounds it (m11 and log2 sigma stay on readlanes, so that the LDS
+// return path is not the limit).
 struct ColStage {
+    float4 a[GS_WAVE];
     float4 col[GS_WAVE];
 };
 
@@ -189,6 +191,7 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
             unsigned long long mask = __ballot(hit);
             // the previous batch's reads of the stage precede this write in
             // the wave's program order, and LDS serves one wave in order
+            cst->a[lane] = cur.a;
             cst->col[lane] = make_float4(cur.b.z, cur.b.w, cur.c.x, 0.0f);
             while (mask) {
                 uint64_t any_live = 0;
@@ -200,8 +203,8 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                 }
                 const int j = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                const float su = lane_f(cur.a.x, j), sv = lane_f(cur.a.y, j);
-                const float m00 = lane_f(cur.a.z, j), m10 = lane_f(cur.a.w, j);
+                const float4 ea = cst->a[j];
+                const float su = ea.x, sv = ea.y, m00 = ea.z, m10 = ea.w;
                 const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
                 const float dy = sv - fy;
                 const int k1 = kb + j - r.x + 1;
