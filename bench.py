@@ -35,6 +35,8 @@ import numpy as np  # noqa: E402
 # HBM / VALU peaks of one MI355X (published)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+# without packed FP32 instructions (the build disables them): 256 CU x 64 lanes x 2 x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # algorithmic FP32 operations per list entry a pixel examines (FMA = 2)
 FWD_FLOPS_PER_VISIT = 25
 BWD_FLOPS_PER_VISIT = 63
@@ -85,23 +87,87 @@ def timed(fn, steps, torch):
 
 
 def stage_times(r, P, cams, tg, grads, steps, torch):
-    """Average duration of each call of the step, each timed over `steps`
-    back-to-back launches with HIP events on the launch stream."""
-    r.forward(P, cams)
-    r.loss_l2(tg)
-    out = {}
-    out["project"] = timed(lambda: r.project(P, cams), steps, torch)
-    out["bin_sort"] = timed(r.bin_sort, steps, torch)
-    out["raster_fwd"] = timed(r.raster_fwd, steps, torch)
-    out["loss"] = timed(lambda: r.loss_l2(tg), steps, torch)
+    """Average duration of each call of the step inside whole steps: the calls
+    of `steps` steps launched one after another on the launch stream, in the
+    order of the captured step, with HIP events between them (the host stays
+    ahead of the GPU, so an interval is the call's own GPU time).  The
+    backward's 2-D gradient buffer is zeroed by a separate fill before the
+    rasteriser backward is called in accumulate mode: the same work as the
+    step's non-accumulating call, with the fill outside the timed kernel."""
     from paper_2606_11390_amd import binding as B
     s, q = r._sched(r.order_bwd)
-    out["raster_bwd"] = timed(lambda: B.rasterize_bwd(r.splats, r.isect_gid, r.ranges, r.n, r.sizes, r.tile,
-                                                      r.background, s, q, r.T_final, r.n_contrib, r.d_images,
-                                                      None, r.grad2d, accumulate=True, block=r.block_bwd),
-                                   steps, torch)
-    out["project_bwd"] = timed(lambda: r.project_bwd(P, cams, grads), steps, torch)
-    return out
+    fwd = ([("raster_fwd_l2", lambda: r.raster_fwd_l2(tg))] if r.fused_loss else
+           [("raster_fwd", r.raster_fwd), ("loss", lambda: r.loss_l2(tg))])
+    calls = [
+        ("project", lambda: r.project(P, cams)),
+        ("bin_sort", r.bin_sort),
+    ] + fwd + [
+        ("zero_grad2d", r.grad2d.zero_),
+        ("raster_bwd", lambda: B.rasterize_bwd(r.splats, r.isect_gid, r.ranges, r.n, r.sizes, r.tile,
+                                               r.background, s, q, r.T_final, r.n_contrib, r.d_images, None,
+                                               r.grad2d, accumulate=True, block=r.block_bwd)),
+        ("project_bwd", lambda: r.project_bwd(P, cams, grads)),
+    ]
+    for _ in range(2):
+        for _, fn in calls:
+            fn()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)] for _ in range(steps)]
+    for i in range(steps):
+        for k, (_, fn) in enumerate(calls):
+            ev[i][k].record()
+            fn()
+        ev[i][-1].record()
+    torch.cuda.synchronize()
+    return {name: sum(ev[i][k].elapsed_time(ev[i][k + 1]) for i in range(steps)) / steps
+            for k, (name, _) in enumerate(calls)}
+
+
+# source files whose kernels a counter summary covers, per step call
+KERNEL_SOURCES = {"raster_fwd": ["raster.hip", "gs_device.h"], "raster_fwd_l2": ["raster.hip", "gs_device.h"],
+                  "raster_bwd": ["raster.hip", "gs_device.h"],
+                  "project": ["project.hip", "gs_device.h"], "project_bwd": ["project.hip", "gs_device.h"]}
+
+
+def kernel_name(stage, r):
+    """Name of the kernel one step call launches (as rocprofv3 reports it)."""
+    if stage in ("raster_fwd", "raster_fwd_l2", "raster_bwd"):
+        fwd = stage != "raster_bwd"
+        blk = r.block if fwd else r.block_bwd
+        order = r.order if fwd else r.order_bwd
+        kind = "fwd" if fwd else "bwd"
+        suffix = "_persistent" if order == "queue" else ""
+        last = "" if (order == "queue" and kind == "fwd") else ", false"
+        return f"k_raster_{kind}{suffix}<{r.tile}, {blk[0]}, {blk[1]}{last}>"
+    return None
+
+
+def sources_sha1(stage):
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES.get(stage, []):
+        with open(os.path.join(ROOT, "paper_2606_11390_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(stage, r, workload):
+    """HBM bytes (read + written) per launch of the stage's kernel from the
+    committed FETCH_SIZE / WRITE_SIZE summary of this workload, or None when
+    there is none or it was taken on other kernel sources."""
+    name = kernel_name(stage, r)
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_counters.md")
+    if name is None or not os.path.exists(path):
+        return None
+    sha = sources_sha1(stage)
+    for line in open(path):
+        # traffic: kernel=<name> read_bytes=<int> write_bytes=<int> sources=<sha1 prefix>
+        if not line.startswith("traffic: "):
+            continue
+        f = dict(kv.split("=", 1) for kv in line[len("traffic: "):].strip().split(" | "))
+        if f.get("kernel") == name and f.get("sources") == sha:
+            return int(f["read_bytes"]) + int(f["write_bytes"])
+    return None
 
 
 def algorithmic_bytes(scene, visible, isect, total_tiles):
@@ -344,7 +410,7 @@ def main():
 
     # per-call durations on the main path, HIP events on the launch stream
     st = stage_times(r_main, P, cams, tg, grads, args.steps, torch)
-    log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
+    log("stage ms (inside whole steps): " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
     # algorithmic work of the compositing kernels
     vis = torch.empty(pixels, dtype=torch.int32, device="cuda")
     img2 = torch.empty(3 * pixels, device="cuda")
@@ -358,18 +424,22 @@ def main():
     info = r_main.info.cpu().numpy()
     work = algorithmic_bytes(scene, int(info[B.INFO_VISIBLE]), int(info[B.INFO_ISECT]), r_main.total_tiles)
     gbs = lambda k: work[k] / (st[k] * 1e-3) / 1e9
+    # with the fused loss the forward call also writes the loss gradient; its
+    # roofline counts the compositing FLOPs only (a lower bound of its work)
+    fkey = "raster_fwd_l2" if "raster_fwd_l2" in st else "raster_fwd"
     rooflines = {
-        "raster_fwd": ("alu", FWD_FLOPS_PER_VISIT * fwd_visits / (st["raster_fwd"] * 1e-3) / 1e12,
-                       PEAK_FP32_TFLOPS, "TFLOP/s"),
+        fkey: ("alu", FWD_FLOPS_PER_VISIT * fwd_visits / (st[fkey] * 1e-3) / 1e12,
+               PEAK_FP32_TFLOPS, "TFLOP/s"),
         "raster_bwd": ("alu", BWD_FLOPS_PER_VISIT * bwd_visits / (st["raster_bwd"] * 1e-3) / 1e12,
                        PEAK_FP32_TFLOPS, "TFLOP/s"),
     }
     for k in ("project", "bin_sort", "loss", "project_bwd"):
-        rooflines[k] = ("hbm", gbs(k), PEAK_HBM_GBS, "GB/s")
+        if k in st:
+            rooflines[k] = ("hbm", gbs(k), PEAK_HBM_GBS, "GB/s")
     dom = max((k for k in st if k in rooflines), key=lambda k: st[k])
     bound, ach, peak, unit = rooflines[dom]
     roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 4), "traffic": None}
+                "frac": round(ach / peak, 4), "traffic": counted_traffic(dom, r_main, scene.name)}
 
     cpu = None
     if not args.no_cpu_baseline and scene.n_views == 1:
@@ -414,7 +484,9 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in st.items()},
         "visits": {"forward": fwd_visits, "backward": bwd_visits},
         "roofline": roofline,
-        "roofline_all": {k: {"bound": b, "achieved": round(a, 3), "peak": p, "unit": u, "frac": round(a / p, 4)}
+        "roofline_all": {k: dict({"bound": b, "achieved": round(a, 3), "peak": p, "unit": u, "frac": round(a / p, 4)},
+                                 **({"frac_unpacked_fp32_peak": round(a / PEAK_FP32_UNPACKED_TFLOPS, 4)}
+                                    if b == "alu" else {}))
                          for k, (b, a, p, u) in rooflines.items()},
         "cpu_baseline": cpu,
     }

@@ -581,10 +581,25 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
 // ---------------------------------------------------------------------------
 // tile ranges
 // ---------------------------------------------------------------------------
-__global__ void k_fill_i32(int* __restrict__ p, int value, long long n)
+// 16-byte stores over the aligned body; the up to three elements before the
+// first 16-byte boundary and after the last one are written singly
+__global__ void k_fill_i32(int* __restrict__ p, int value, long long head, long long nv, long long n)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = value;
+    if (i < nv) reinterpret_cast<int4*>(p + head)[i] = make_int4(value, value, value, value);
+    if (i < head) p[i] = value;
+    const long long t0 = head + 4 * nv;
+    if (i < n - t0) p[t0 + i] = value;
+}
+
+hipError_t fill_i32(int* p, int value, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const long long head = min(n, (long long)(((16 - ((uintptr_t)p & 15)) & 15) / 4));
+    const long long nv = (n - head) / 4;
+    const long long threads = max(nv, 4ll);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, p, value, head, nv, n);
+    return hipGetLastError();
 }
 
 // thread t looks at keys 4t .. 4t + 3 (one 16-byte load) and their outer
@@ -750,7 +765,7 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
 
     // 5. ranges
     const long long nr = 2ll * vt.total_tiles;
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, (int*)ranges, 0, nr);
+    if ((e = fill_i32((int*)ranges, 0, nr, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 1023) / 1024)), dim3(256), 0, st, isect_tile, w.cnt,
                        (uint32_t)vt.total_tiles, ranges);
     return hipGetLastError();
@@ -800,9 +815,7 @@ hipError_t launch_tile_order_xcd(long long total_tiles, int n_xcd, void* schedul
 
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, value, n);
-    return hipGetLastError();
+    return fill_i32(p, value, n, st);
 }
 
 size_t morton_workspace_size(long long n)
