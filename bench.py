@@ -96,12 +96,11 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
     step's non-accumulating call, with the fill outside the timed kernel."""
     from paper_2606_11390_amd import binding as B
     s, q = r._sched(r.order_bwd)
-    fwd = ([("raster_fwd_l2", lambda: r.raster_fwd_l2(tg))] if r.fused_loss else
-           [("raster_fwd", r.raster_fwd), ("loss", lambda: r.loss_l2(tg))])
     calls = [
         ("project", lambda: r.project(P, cams)),
         ("bin_sort", r.bin_sort),
-    ] + fwd + [
+        ("raster_fwd", r.raster_fwd),
+        ("loss", lambda: r.loss_l2(tg)),
         ("zero_grad2d", r.grad2d.zero_),
         ("raster_bwd", lambda: B.rasterize_bwd(r.splats, r.isect_gid, r.ranges, r.n, r.sizes, r.tile,
                                                r.background, s, q, r.T_final, r.n_contrib, r.d_images, None,
@@ -124,15 +123,14 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
 
 
 # source files whose kernels a counter summary covers, per step call
-KERNEL_SOURCES = {"raster_fwd": ["raster.hip", "gs_device.h"], "raster_fwd_l2": ["raster.hip", "gs_device.h"],
-                  "raster_bwd": ["raster.hip", "gs_device.h"],
+KERNEL_SOURCES = {"raster_fwd": ["raster.hip", "gs_device.h"], "raster_bwd": ["raster.hip", "gs_device.h"],
                   "project": ["project.hip", "gs_device.h"], "project_bwd": ["project.hip", "gs_device.h"]}
 
 
 def kernel_name(stage, r):
     """Name of the kernel one step call launches (as rocprofv3 reports it)."""
-    if stage in ("raster_fwd", "raster_fwd_l2", "raster_bwd"):
-        fwd = stage != "raster_bwd"
+    if stage in ("raster_fwd", "raster_bwd"):
+        fwd = stage == "raster_fwd"
         blk = r.block if fwd else r.block_bwd
         order = r.order if fwd else r.order_bwd
         kind = "fwd" if fwd else "bwd"
@@ -424,18 +422,14 @@ def main():
     info = r_main.info.cpu().numpy()
     work = algorithmic_bytes(scene, int(info[B.INFO_VISIBLE]), int(info[B.INFO_ISECT]), r_main.total_tiles)
     gbs = lambda k: work[k] / (st[k] * 1e-3) / 1e9
-    # with the fused loss the forward call also writes the loss gradient; its
-    # roofline counts the compositing FLOPs only (a lower bound of its work)
-    fkey = "raster_fwd_l2" if "raster_fwd_l2" in st else "raster_fwd"
     rooflines = {
-        fkey: ("alu", FWD_FLOPS_PER_VISIT * fwd_visits / (st[fkey] * 1e-3) / 1e12,
-               PEAK_FP32_TFLOPS, "TFLOP/s"),
+        "raster_fwd": ("alu", FWD_FLOPS_PER_VISIT * fwd_visits / (st["raster_fwd"] * 1e-3) / 1e12,
+                       PEAK_FP32_TFLOPS, "TFLOP/s"),
         "raster_bwd": ("alu", BWD_FLOPS_PER_VISIT * bwd_visits / (st["raster_bwd"] * 1e-3) / 1e12,
                        PEAK_FP32_TFLOPS, "TFLOP/s"),
     }
     for k in ("project", "bin_sort", "loss", "project_bwd"):
-        if k in st:
-            rooflines[k] = ("hbm", gbs(k), PEAK_HBM_GBS, "GB/s")
+        rooflines[k] = ("hbm", gbs(k), PEAK_HBM_GBS, "GB/s")
     dom = max((k for k in st if k in rooflines), key=lambda k: st[k])
     bound, ach, peak, unit = rooflines[dom]
     roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,

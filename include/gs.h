@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 4
+#define GS_ABI_VERSION 3
 #define GS_MAX_VIEWS 64
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD_FLOATS 9
@@ -259,34 +259,6 @@ int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_
                      int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
                      const float* background, const void* schedule, int32_t* queue, float* images,
                      float* T_final, int32_t* n_contrib, void* stream);
-
-/*
- * gs_rasterize_fwd_l2_workspace_size - bytes of device workspace
- * gs_rasterize_fwd_l2 needs for these views and tile edge (one double per
- * wavefront work unit); 0 for invalid arguments.
- */
-size_t gs_rasterize_fwd_l2_workspace_size(int n_views, const int32_t* sizes, int tile);
-
-/*
- * gs_rasterize_fwd_l2 - gs_rasterize_fwd followed by the L2 image loss of
- * gs_loss_l2 (paper Section 4: per-camera rasterisation, then the image-space
- * loss), fused: the wavefront that writes a pixel also writes
- * d_images = 2 (images - targets) / n_elems for it and adds its squared
- * differences to a per-wavefront partial sum in `workspace`; one small kernel
- * then sums the partials in a fixed order, loss = sum / n_elems with n_elems =
- * 3 x all pixels.  images, T_final, n_contrib and d_images are bit-identical
- * to gs_rasterize_fwd + gs_loss_l2; the loss differs from gs_loss_l2's only by
- * the order of the sum (both deterministic).  The image is never read back.
- * Arguments: those of gs_rasterize_fwd, plus targets (packed like images),
- * loss (device float[1], overwritten), d_images (packed like images,
- * overwritten) and a device workspace of at least
- * gs_rasterize_fwd_l2_workspace_size bytes (GS_ERR_WORKSPACE otherwise).
- */
-int gs_rasterize_fwd_l2(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
-                        int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
-                        const float* background, const void* schedule, int32_t* queue, float* images,
-                        float* T_final, int32_t* n_contrib, const float* targets, float* loss, float* d_images,
-                        void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * gs_rasterize_bwd - backward of gs_rasterize_fwd (paper Section 4: backward

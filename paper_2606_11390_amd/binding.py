@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
-GS_ABI_VERSION = 4
+GS_ABI_VERSION = 3
 GS_MAX_VIEWS = 64
 SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
@@ -46,9 +46,6 @@ _SIGS = {
     "gs_tile_schedule": (_int, [_p, _i64, _p, _sz, _p]),
     "gs_tile_order_xcd": (_int, [_i64, _int, _p, _sz, _p]),
     "gs_rasterize_fwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p]),
-    "gs_rasterize_fwd_l2_workspace_size": (_sz, [_int, _p, _int]),
-    "gs_rasterize_fwd_l2": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p,
-                                   _p, _p, _p, _p, _sz, _p]),
     "gs_rasterize_bwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p,
                                 _int, _p]),
     "gs_project_bwd": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
@@ -221,26 +218,6 @@ def project_bwd(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmat
                               _ptr(d_quats, F32, "d_quats"), _ptr(d_opacity_logits, F32, "d_opacity_logits"),
                               _ptr(d_sh, F32, "d_sh"), _stream())
     _check(rc, "gs_project_bwd")
-
-
-def rasterize_fwd_l2_workspace_size(sizes, tile):
-    sz, szp = _host_i32(np.asarray(sizes).reshape(-1, 2))
-    return int(lib().gs_rasterize_fwd_l2_workspace_size(sz.shape[0], szp, int(tile)))
-
-
-def rasterize_fwd_l2(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, queue, images,
-                     T_final, n_contrib, targets, loss, d_images, workspace, block=(0, 0)):
-    sz, szp = _host_i32(sizes)
-    bg, bgp = _host_f32(background)
-    rc = lib().gs_rasterize_fwd_l2(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
-                                   _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile),
-                                   int(block[0]), int(block[1]), bgp,
-                                   _ptr(schedule, U8, "schedule"), _ptr(queue, I32, "queue"),
-                                   _ptr(images, F32, "images"), _ptr(T_final, F32, "T_final"),
-                                   _ptr(n_contrib, I32, "n_contrib"), _ptr(targets, F32, "targets"),
-                                   _ptr(loss, F32, "loss"), _ptr(d_images, F32, "d_images"),
-                                   _ptr(workspace, U8, "workspace"), workspace.numel(), _stream())
-    _check(rc, "gs_rasterize_fwd_l2")
 
 
 def loss_workspace_size(n_elems):

@@ -30,10 +30,7 @@ bool raster_cfg_ok(int tile, int bw, int ppl);
 hipError_t launch_raster_fwd(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
                              const int* gids, const int2* ranges, long long N, const float* bg,
                              const int* order, int* queue, float* img, float* Tout, int* lastout, int* visits,
-                             hipStream_t st, const float* tgt = nullptr, float* dimg = nullptr,
-                             double* part = nullptr, float scale = 0.0f);
-int raster_units_per_tile(int tile, int bw, int ppl);
-hipError_t launch_l2_final(const double* part, long long nb, long long n, float* loss, hipStream_t st);
+                             hipStream_t st);
 hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
                              const int* gids, const int2* ranges, long long N, const float* bg,
                              const int* order, int* queue, const float* Tfin, const int* nlast,
@@ -207,44 +204,6 @@ int gs_rasterize_fwd(const float* splats, const int32_t* isect_gid, const int32_
                                         reinterpret_cast<const int2*>(tile_ranges), n, background,
                                         static_cast<const int*>(schedule), queue, images, T_final, n_contrib,
                                         nullptr, as_stream(stream)));
-}
-
-size_t gs_rasterize_fwd_l2_workspace_size(int n_views, const int32_t* sizes, int tile)
-{
-    ViewTable vt;
-    if (!tile_ok(tile) || !make_views(sizes, n_views, tile, vt)) return 0;
-    // the largest number of work units per tile of any configuration (one pixel per lane)
-    return sizeof(double) * (size_t)vt.total_tiles * (size_t)gs::raster_units_per_tile(tile, 0, 0);
-}
-
-int gs_rasterize_fwd_l2(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,
-                        int64_t n, int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
-                        const float* background, const void* schedule, int32_t* queue, float* images,
-                        float* T_final, int32_t* n_contrib, const float* targets, float* loss, float* d_images,
-                        void* workspace, size_t workspace_bytes, void* stream)
-{
-    ViewTable vt;
-    if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
-        return GS_ERR_ARG;
-    if (!gs::raster_cfg_ok(tile, block_w, px_per_lane)) return GS_ERR_ARG;
-    if (!tile_ranges || !images || !T_final || !n_contrib || !background) return GS_ERR_ARG;
-    if (!targets || !loss || !d_images || !workspace) return GS_ERR_ARG;
-    if (!isect_gid || (n > 0 && (!splats || !aligned16(splats)))) return GS_ERR_ARG;
-    if (queue && !schedule) return GS_ERR_ARG;
-    for (int c = 0; c < 3; c++)
-        if (!std::isfinite(background[c])) return GS_ERR_ARG;
-    if (workspace_bytes < gs_rasterize_fwd_l2_workspace_size(n_views, sizes, tile)) return GS_ERR_WORKSPACE;
-    const long long n_elems = 3ll * vt.pix_off[vt.n_views];
-    const long long units = (long long)vt.total_tiles * gs::raster_units_per_tile(tile, block_w, px_per_lane);
-    hipError_t e = gs::launch_raster_fwd(tile, block_w, px_per_lane, vt, splats, isect_gid,
-                                         reinterpret_cast<const int2*>(tile_ranges), n, background,
-                                         static_cast<const int*>(schedule), queue, images, T_final, n_contrib,
-                                         nullptr, as_stream(stream), targets, d_images,
-                                         static_cast<double*>(workspace),
-                                         n_elems > 0 ? (float)(2.0 / (double)n_elems) : 0.0f);
-    if (e != hipSuccess) return status(e);
-    return status(gs::launch_l2_final(static_cast<const double*>(workspace), units, n_elems, loss,
-                                      as_stream(stream)));
 }
 
 int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges,

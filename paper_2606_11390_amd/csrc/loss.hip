@@ -35,12 +35,12 @@ __global__ __launch_bounds__(L_THREADS) void k_l2_partial(const float* __restric
     }
 }
 
-__global__ __launch_bounds__(L_THREADS) void k_l2_final(const double* __restrict__ part, long long nb,
+__global__ __launch_bounds__(L_THREADS) void k_l2_final(const double* __restrict__ part, int nb,
                                                         double inv_n, float* __restrict__ loss)
 {
     __shared__ double s[L_THREADS];
     double acc = 0.0;
-    for (long long i = threadIdx.x; i < nb; i += L_THREADS) acc += part[i];
+    for (int i = threadIdx.x; i < nb; i += L_THREADS) acc += part[i];
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int o = L_THREADS / 2; o > 0; o >>= 1) {
@@ -68,16 +68,8 @@ hipError_t launch_loss_l2(const float* img, const float* tgt, long long n, float
     const int nb = loss_blocks(n);
     hipLaunchKernelGGL(k_l2_partial, dim3(nb), dim3(L_THREADS), 0, st, img, tgt, n,
                        n > 0 ? (float)(2.0 / (double)n) : 0.0f, dimg, (double*)ws);
-    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(L_THREADS), 0, st, (const double*)ws, (long long)nb,
+    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(L_THREADS), 0, st, (const double*)ws, nb,
                        n > 0 ? 1.0 / (double)n : 0.0, loss);
-    return hipGetLastError();
-}
-
-// loss = (sum of the nb partial sums, in a fixed order) / n
-hipError_t launch_l2_final(const double* part, long long nb, long long n, float* loss, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(L_THREADS), 0, st, part, nb, n > 0 ? 1.0 / (double)n : 0.0,
-                       loss);
     return hipGetLastError();
 }
 

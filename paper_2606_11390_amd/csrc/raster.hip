@@ -53,17 +53,6 @@ struct ColStage {
     float4 col[GS_WAVE];
 };
 
-// Optional L2 image loss fused into the forward's output stage: the lane that
-// writes a pixel also writes d_images = scale (image - target) and the wave
-// sums (image - target)^2 into its own partial slot (one per work unit, so
-// the final reduction is in a fixed order).  tgt == nullptr: no loss.
-struct L2Out {
-    const float* tgt;
-    float* dimg;
-    double* part;
-    float scale;
-};
-
 __device__ __forceinline__ Rec load_rec(const float* __restrict__ base, int gid)
 {
     const float4* p = reinterpret_cast<const float4*>(base + (size_t)gid * GS_SPLAT_FLOATS);
@@ -157,7 +146,7 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                                          const int2* __restrict__ ranges, long long N, float bg0,
                                          float bg1, float bg2, float* __restrict__ img,
                                          float* __restrict__ Tout, int* __restrict__ lastout,
-                                         int* __restrict__ visits, ColStage* __restrict__ cst, L2Out l2)
+                                         int* __restrict__ visits, ColStage* __restrict__ cst)
 {
     using L = Layout<TS, BW, P>;
     const Unit U = unit_of<TS, BW, P>(vt, gt, wit);
@@ -254,33 +243,18 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
     }
     const long long po = U.v < 0 ? 0 : vt.pix_off[U.v];
     const long long plane = (long long)W * H;
-    float lsum = 0.0f;
 #pragma unroll
     for (int p = 0; p < P; p++) {
         if (U.px0 + p < W && U.py < H) {
             const long long pix = (long long)U.py * W + U.px0 + p;
-            const float out[3] = {__builtin_fmaf(T[p], bg0, C0[p]), __builtin_fmaf(T[p], bg1, C1[p]),
-                                  __builtin_fmaf(T[p], bg2, C2[p])};
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) img[3 * po + ch * plane + pix] = out[ch];
+            img[3 * po + pix] = __builtin_fmaf(T[p], bg0, C0[p]);
+            img[3 * po + plane + pix] = __builtin_fmaf(T[p], bg1, C1[p]);
+            img[3 * po + 2 * plane + pix] = __builtin_fmaf(T[p], bg2, C2[p]);
             Tout[po + pix] = T[p];
             lastout[po + pix] = last[p];
             // list entries this pixel examined: up to its stop, else the whole list
             if (COUNT) visits[po + pix] = stopk[p] >= 0 ? stopk[p] : r.y - r.x;
-            if (l2.tgt) {
-#pragma unroll
-                for (int ch = 0; ch < 3; ch++) {
-                    const long long e = 3 * po + ch * plane + pix;
-                    const float d = out[ch] - l2.tgt[e];
-                    l2.dimg[e] = l2.scale * d;
-                    lsum = __builtin_fmaf(d, d, lsum);
-                }
-            }
         }
-    }
-    if (l2.tgt) {
-        const float ws = wave_sum(lsum);
-        if (lane == 0) l2.part[(long long)gt * L::WPT + wit] = (double)ws;
     }
 }
 
@@ -467,14 +441,14 @@ __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_f
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
     const int* __restrict__ order, float* __restrict__ img, float* __restrict__ Tout,
-    int* __restrict__ lastout, int* __restrict__ visits, L2Out l2)
+    int* __restrict__ lastout, int* __restrict__ visits)
 {
     __shared__ ColStage cst[Layout<TS, BW, P>::WPT];
     const int gt = tile_of_block(order, vt.total_tiles);
     if (gt < 0) return;
     const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
     fwd_unit<TS, BW, P, COUNT>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout, lastout, visits,
-                               &cst[wit], l2);
+                               &cst[wit]);
 }
 
 template <int TS, int BW, int P>
@@ -482,7 +456,7 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
     const int* __restrict__ order, int* __restrict__ queue, float* __restrict__ img,
-    float* __restrict__ Tout, int* __restrict__ lastout, L2Out l2)
+    float* __restrict__ Tout, int* __restrict__ lastout)
 {
     using L = Layout<TS, BW, P>;
     __shared__ ColStage cst;
@@ -497,7 +471,7 @@ __global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_persistent(
             const int gt = order[item / L::WPT];
             if ((unsigned)gt < (unsigned)vt.total_tiles)
                 fwd_unit<TS, BW, P, false>(vt, gt, item % L::WPT, splats, gids, ranges, N, bg0, bg1, bg2, img,
-                                           Tout, lastout, nullptr, &cst, l2);
+                                           Tout, lastout, nullptr, &cst);
         }
         c = ticket(next);
     }
@@ -562,22 +536,21 @@ int persistent_blocks()
 template <int TS, int BW, int P>
 hipError_t fwd_cfg(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges, long long N,
                    const float* bg, const int* order, int* queue, float* img, float* Tout, int* lastout,
-                   int* visits, const L2Out& l2, hipStream_t st)
+                   int* visits, hipStream_t st)
 {
     using L = Layout<TS, BW, P>;
     if (visits) {
         hipLaunchKernelGGL((k_raster_fwd<TS, BW, P, true>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st,
-                           vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], nullptr, img, Tout, lastout, visits,
-                           L2Out{nullptr, nullptr, nullptr, 0.0f});
+                           vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], nullptr, img, Tout, lastout, visits);
     } else if (order && queue) {
         hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, queue);
         hipLaunchKernelGGL((k_raster_fwd_persistent<TS, BW, P>), dim3(persistent_blocks()), dim3(GS_WAVE), 0,
                            st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, queue, img, Tout,
-                           lastout, l2);
+                           lastout);
     } else {
         hipLaunchKernelGGL((k_raster_fwd<TS, BW, P, false>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0,
                            st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, img, Tout, lastout,
-                           nullptr, l2);
+                           nullptr);
     }
     return hipGetLastError();
 }
@@ -630,22 +603,13 @@ bool raster_cfg_ok(int tile, int bw, int ppl)
 }
 
 #define GS_FWD(TS, BW, P) \
-    return fwd_cfg<TS, BW, P>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, l2, st)
-
-// work units (waves) per tile of a configuration: the size of the fused
-// loss's partial array is total_tiles times this
-int raster_units_per_tile(int tile, int bw, int ppl)
-{
-    if (bw == 0) { bw = 8; ppl = 1; }
-    return tile * tile / (GS_WAVE * ppl);
-}
+    return fwd_cfg<TS, BW, P>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st)
 
 hipError_t launch_raster_fwd(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
                              const int* gids, const int2* ranges, long long N, const float* bg,
                              const int* order, int* queue, float* img, float* Tout, int* lastout, int* visits,
-                             hipStream_t st, const float* tgt, float* dimg, double* part, float scale)
+                             hipStream_t st)
 {
-    const L2Out l2{tgt, dimg, part, scale};
     if (vt.total_tiles == 0) return hipSuccess;
     if (bw == 0) { bw = 8; ppl = 1; }
     switch (tile) {

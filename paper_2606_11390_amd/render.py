@@ -38,12 +38,9 @@ N_XCD = 8
 class Renderer:
     def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
                  background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda",
-                 radius_mode=0, order=None, order_bwd=None, fused_loss=True):
+                 radius_mode=0, order=None, order_bwd=None):
         # screen box rule of the projection (GS_RADIUS_*)
         self.radius_mode = int(radius_mode)
-        # step(): L2 loss fused into the rasteriser forward (gs_rasterize_fwd_l2)
-        # or a separate gs_loss_l2 call
-        self.fused_loss = bool(fused_loss)
         # wave pixel blocks (width, pixels per lane) of the forward and backward rasterisers
         self.block = tuple(int(x) for x in block)
         self.block_bwd = self.block if block_bwd is None else tuple(int(x) for x in block_bwd)
@@ -83,7 +80,6 @@ class Renderer:
         self.d_images = e(3 * self.pixels)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.loss_ws = e(max(1, B.loss_workspace_size(3 * self.pixels)), dt=torch.uint8)
-        self.fwd_l2_ws = e(max(1, B.rasterize_fwd_l2_workspace_size(self.sizes, self.tile)), dt=torch.uint8)
         self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
         self.schedule = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
         self.schedule_xcd = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
@@ -154,12 +150,6 @@ class Renderer:
     def loss_l2(self, targets):
         B.loss_l2(self.images, targets, self.loss, self.d_images, self.loss_ws)
 
-    def raster_fwd_l2(self, targets):
-        s, q = self._sched()
-        B.rasterize_fwd_l2(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
-                           self.background, s, q, self.images, self.T_final, self.n_contrib, targets, self.loss,
-                           self.d_images, self.fwd_l2_ws, block=self.block)
-
     def forward(self, P, cams):
         self.project(P, cams)
         self.bin_sort()
@@ -175,13 +165,8 @@ class Renderer:
     def step(self, P, cams, targets, grads):
         """Forward, L2 loss against packed ``targets`` and backward into
         ``grads`` (dict of tensors shaped like the parameters)."""
-        if self.fused_loss:
-            self.project(P, cams)
-            self.bin_sort()
-            self.raster_fwd_l2(targets)
-        else:
-            self.forward(P, cams)
-            self.loss_l2(targets)
+        self.forward(P, cams)
+        self.loss_l2(targets)
         return self.backward(P, cams, self.d_images, grads)
 
     def fit_capacity(self, P, cams, headroom=1.25):

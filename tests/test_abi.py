@@ -79,14 +79,6 @@ def test_host_side_argument_checks():
     assert L.gs_rasterize_bwd(p, p, p, 10, 1, szp, 16, 8, 4, bg, None, None, p, p, p, None, p, 0, None) == -1
     assert L.gs_project_bwd(p, p, p, p, p, 10, 5, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, None) == -1
     assert L.gs_loss_l2(p, p, 10, p, p, p, 0, None) == -4
-    # fused forward + loss: missing loss outputs, workspace too small
-    fws = L.gs_rasterize_fwd_l2_workspace_size(1, szp, 16)
-    assert fws > 0
-    assert L.gs_rasterize_fwd_l2(p, p, p, 10, 1, szp, 16, 0, 0, bg, None, None, p, p, p, p, None, p, p, fws,
-                                 None) == -1
-    assert L.gs_rasterize_fwd_l2(p, p, p, 10, 1, szp, 16, 0, 0, bg, None, None, p, p, p, p, p, p, p, fws - 1,
-                                 None) == -4
-    assert L.gs_rasterize_fwd_l2_workspace_size(1, szp, 24) == 0
     assert L.gs_tile_schedule(p, 0, p, 0, None) == -1
     assert L.gs_tile_order_xcd(100, 0, aligned, 4096, None) == -1
     assert L.gs_tile_order_xcd(100, 8, aligned, 8, None) == -4
@@ -99,8 +91,4 @@ def test_workspace_sizes_grow_with_problem():
     c = B.bin_sort_workspace_size(1000, 1, 50000, 64)
     assert 0 < a < b and a < c
     assert B.loss_workspace_size(10) >= 8
-    # one double per wavefront unit: 64 pixels per unit at every tile edge
-    for t in (8, 16, 32):
-        assert B.rasterize_fwd_l2_workspace_size([[100, 75], [33, 17]], t) == \
-            8 * int(B.tile_grid([[100, 75], [33, 17]], t)[1][-1]) * t * t // 64
     assert B.tile_schedule_size(100) >= 400

@@ -220,34 +220,3 @@ def test_renderer_reports_overflow():
     m = r.fit_capacity(P, cams)
     assert r.capacity >= m
     R.render(r, P, cams)
-
-
-@pytest.mark.parametrize("order", ["tile", "heavy", "queue"])
-@pytest.mark.parametrize("name,tile", [("ragged", 16), ("multi", 8), ("multi", 32)])
-def test_fused_forward_loss_equals_separate_calls(name, tile, order):
-    """gs_rasterize_fwd_l2 = gs_rasterize_fwd + gs_loss_l2: images, T, last
-    and d_images bit for bit; the loss up to the order of its sum."""
-    s = (scenes.tiny(seed=21, n_gaussians=1500, width=100, height=75, focal=90.0) if name == "ragged" else
-         scenes.blobs(5, 30_000, 64, 20.0, [(320, 240, 250.0), (200, 150, 156.0), (128, 96, 100.0),
-                                            (257, 131, 200.0)], name="multi"))
-    G.say(f"[fused loss] {name} tile={tile} order={order}")
-    out = []
-    for fused in (False, True):
-        r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=tile, capacity=1 << 18, order=order, fused_loss=fused)
-        P, cams = R.params_to_device(s)
-        r.fit_capacity(P, cams)
-        tg = R.packed_targets(s)
-        r.d_images.fill_(float("nan"))
-        r.loss.fill_(float("nan"))
-        if fused:
-            r.raster_fwd_l2(tg)
-        else:
-            r.raster_fwd()
-            r.loss_l2(tg)
-        torch.cuda.synchronize()
-        out.append({k: G.host(getattr(r, k)) for k in ("images", "T_final", "n_contrib", "d_images", "loss")})
-    a, b = out
-    for k in ("images", "T_final", "n_contrib", "d_images"):
-        np.testing.assert_array_equal(b[k], a[k], err_msg=k)
-    assert np.isfinite(b["loss"][0])
-    assert b["loss"][0] == pytest.approx(a["loss"][0], rel=1e-6)
