@@ -38,6 +38,7 @@ constexpr int RS_ITEMS = 8;
 constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;     // keys per chunk
 constexpr int RS_WAVE_SPAN = GS_WAVE * RS_ITEMS;     // keys per wave per chunk
 constexpr int RS_MAX_BLOCKS = 4096;
+constexpr int RS_MAX_BITS = 9;    // widest digit: 512 counters per wave
 
 enum Source { SRC_PAIRS = 0, SRC_PROJ = 1, SRC_TILE_LEN = 2, SRC_MORTON = 3 };
 
@@ -175,13 +176,16 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t* s_
     return before + inc - x;
 }
 
-template <int SRC>
+// DBITS: the largest digit width a kernel instance handles (8 or 11 bits:
+// 256 or 2048 counters per wave in LDS); `bits` <= DBITS is the pass's width
+template <int SRC, int DBITS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortIO io, int shift, int bits,
                                                         uint32_t* __restrict__ hist)
 {
-    __shared__ uint32_t s_cnt[RS_WAVES][256];
+    constexpr int ND = 1 << DBITS;
+    __shared__ uint32_t s_cnt[RS_WAVES][ND];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x, w = t / GS_WAVE;
-    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&s_cnt[0][0])[i] = 0;
+    for (int i = t; i < RS_WAVES * ND; i += RS_THREADS) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = io_count(io);
     uint32_t beg, end;
@@ -206,10 +210,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortIO io, int shift, in
         }
     }
     __syncthreads();
-    if (t < 256) {
+    const int nd = 1 << bits;
+    for (int d = t; d < nd; d += RS_THREADS) {
         uint32_t s = 0;
-        for (int i = 0; i < RS_WAVES; i++) s += s_cnt[i][t];
-        hist[(size_t)t * nb + b] = s;
+        for (int i = 0; i < RS_WAVES; i++) s += s_cnt[i][d];
+        hist[(size_t)d * nb + b] = s;
     }
 }
 
@@ -244,26 +249,58 @@ __global__ __launch_bounds__(1024) void k_rs_spine(uint32_t* __restrict__ hist, 
     if (t == 0) dtot[d] = carry;
 }
 
-template <int SRC>
+// exclusive scan over the ND digits of a 256-thread block, thread t owning
+// digits t * DPT .. t * DPT + DPT - 1 (x: its DPT values, replaced by their
+// exclusive prefixes); returns the total
+template <int DPT>
+__device__ __forceinline__ uint32_t block_excl_scan_digits(uint32_t (&x)[DPT], uint32_t* s_tmp)
+{
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; i++) {
+        const uint32_t v = x[i];
+        x[i] = sum;
+        sum += v;
+    }
+    uint32_t total;
+    const uint32_t before = block_excl_scan_256(sum, s_tmp, total);
+#pragma unroll
+    for (int i = 0; i < DPT; i++) x[i] += before;
+    return total;
+}
+
+template <int SRC, int DBITS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift, int bits,
                                                            const uint32_t* __restrict__ excl,
                                                            const uint32_t* __restrict__ dtot,
                                                            uint32_t* __restrict__ count_out)
 {
-    __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_wcnt[RS_WAVES][256];
-    __shared__ uint32_t s_cex[256];
+    constexpr int ND = 1 << DBITS;
+    constexpr int DPT = ND / RS_THREADS;   // digits per thread in the digit scans
+    static_assert(DPT >= 1 && ND % RS_THREADS == 0, "digit count");
+    __shared__ uint32_t s_base[ND];
+    __shared__ uint32_t s_wcnt[RS_WAVES][ND];
+    __shared__ uint32_t s_cex[ND];
     __shared__ uint32_t s_tmp[RS_WAVES];
     __shared__ uint32_t s_k[RS_CHUNK];
     __shared__ uint32_t s_v[RS_CHUNK];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x, w = t / GS_WAVE, lane = __lane_id();
+    const int nd = 1 << bits;
     const uint32_t mask = (1u << bits) - 1u;
 
     // global start of each digit for this block
-    uint32_t all;
-    const uint32_t dbase = block_excl_scan_256(dtot[t], s_tmp, all);
-    s_base[t] = dbase + excl[(size_t)t * nb + b];
-    if (count_out && b == 0 && t == 0) *count_out = all;
+    {
+        uint32_t x[DPT];
+#pragma unroll
+        for (int i = 0; i < DPT; i++) x[i] = t * DPT + i < nd ? dtot[t * DPT + i] : 0u;
+        const uint32_t all = block_excl_scan_digits<DPT>(x, s_tmp);
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const int d = t * DPT + i;
+            s_base[d] = d < nd ? x[i] + excl[(size_t)d * nb + b] : 0u;
+        }
+        if (count_out && b == 0 && t == 0) *count_out = all;
+    }
 
     const uint32_t n = io_count(io);
     uint32_t beg, end;
@@ -271,7 +308,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
     const uint64_t lt = lanemask_lt();
 
     for (uint32_t cb = beg; cb < end; cb += RS_CHUNK) {
-        for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&s_wcnt[0][0])[i] = 0;
+        for (int i = t; i < RS_WAVES * nd; i += RS_THREADS) s_wcnt[i >> bits][i & (nd - 1)] = 0;
         __syncthreads();
         uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
         bool ok[RS_ITEMS];
@@ -289,15 +326,26 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
         }
         __syncthreads();
         // per digit: exclusive prefix across waves, chunk total, chunk digit start
-        uint32_t wp[RS_WAVES], tot = 0;
-        for (int i = 0; i < RS_WAVES; i++) {
-            wp[i] = tot;
-            tot += s_wcnt[i][t];
+        uint32_t tot[DPT];
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const int d = t * DPT + i;
+            uint32_t acc = 0;
+            if (d < nd) {
+                for (int k = 0; k < RS_WAVES; k++) {
+                    const uint32_t c = s_wcnt[k][d];
+                    s_wcnt[k][d] = acc;
+                    acc += c;
+                }
+            }
+            tot[i] = acc;
         }
-        uint32_t ctot;
-        const uint32_t cex = block_excl_scan_256(tot, s_tmp, ctot);
-        s_cex[t] = cex;
-        for (int i = 0; i < RS_WAVES; i++) s_wcnt[i][t] = wp[i];
+        uint32_t cex[DPT];
+#pragma unroll
+        for (int i = 0; i < DPT; i++) cex[i] = tot[i];
+        const uint32_t ctot = block_excl_scan_digits<DPT>(cex, s_tmp);
+#pragma unroll
+        for (int i = 0; i < DPT; i++) s_cex[t * DPT + i] = cex[i];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < RS_ITEMS; r++) {
@@ -316,7 +364,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
             io.vals_out[dst] = s_v[j];
         }
         __syncthreads();
-        s_base[t] += tot;
+#pragma unroll
+        for (int i = 0; i < DPT; i++) s_base[t * DPT + i] += tot[i];
     }
 }
 
@@ -642,12 +691,29 @@ template <int SRC>
 hipError_t radix_pass(const SortIO& io, int nb, int shift, int bits, uint32_t* hist, uint32_t* dtot,
                       uint32_t* count_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rs_hist<SRC>, dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
     const int sp_threads = min(1024, ((nb + GS_WAVE - 1) / GS_WAVE) * GS_WAVE);
-    hipLaunchKernelGGL(k_rs_spine, dim3(256), dim3(sp_threads), 0, st, hist, nb, dtot);
-    hipLaunchKernelGGL(k_rs_scatter<SRC>, dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
-                       dtot, count_out);
+    if (bits <= 8) {
+        hipLaunchKernelGGL((k_rs_hist<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
+        hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
+        hipLaunchKernelGGL((k_rs_scatter<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
+                           dtot, count_out);
+    } else {
+        hipLaunchKernelGGL((k_rs_hist<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
+                           hist);
+        hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
+        hipLaunchKernelGGL((k_rs_scatter<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
+                           hist, dtot, count_out);
+    }
     return hipGetLastError();
+}
+
+// widths of the fewest passes of at most RS_MAX_BITS bits covering `total`
+// bits, split as evenly as possible (e.g. 32 -> 8, 8, 8, 8; 17 -> 9, 8)
+int plan_passes(int total, int* widths)
+{
+    const int np = (total + RS_MAX_BITS - 1) / RS_MAX_BITS;
+    for (int p = 0; p < np; p++) widths[p] = total / np + (p < total % np ? 1 : 0);
+    return np;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -679,8 +745,8 @@ BinWs bin_layout(char* base, unsigned long long vn, unsigned long long cap)
     w.offs = (uint32_t*)take(4 * vn);
     w.tk = (uint32_t*)take(4 * cap);
     w.tv = (uint32_t*)take(4 * cap);
-    w.hist = (uint32_t*)take(4ull * 256 * RS_MAX_BLOCKS);
-    w.dtot = (uint32_t*)take(4 * 256);
+    w.hist = (uint32_t*)take(4ull * (1u << RS_MAX_BITS) * RS_MAX_BLOCKS);
+    w.dtot = (uint32_t*)take(4 * (1u << RS_MAX_BITS));
     w.part = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
     w.srect = (int2*)take(8 * vn);
     w.part_ex = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
@@ -719,14 +785,16 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
     io.keys_out = w.dk0;
     io.vals_out = w.dv0;
     io.n_const = (uint32_t)vn;
-    if ((e = radix_pass<SRC_PROJ>(io, nb_d, 0, 8, w.hist, w.dtot, w.cnt + 0, st)) != hipSuccess) return e;
+    int dw[4];
+    const int dpasses = plan_passes(32, dw);
+    if ((e = radix_pass<SRC_PROJ>(io, nb_d, 0, dw[0], w.hist, w.dtot, w.cnt + 0, st)) != hipSuccess) return e;
     uint32_t *ki = w.dk0, *vi = w.dv0, *ko = w.dk1, *vo = w.dv1;
-    for (int pass = 1; pass < 4; pass++) {
+    for (int pass = 1, shift = dw[0]; pass < dpasses; shift += dw[pass], pass++) {
         SortIO p{};
         p.keys_in = ki; p.vals_in = vi; p.vals_out = vo;
-        p.keys_out = pass < 3 ? ko : nullptr;   // only the order of the last pass is used
+        p.keys_out = pass + 1 < dpasses ? ko : nullptr;   // only the order of the last pass is used
         p.n_dev = w.cnt + 0;
-        if ((e = radix_pass<SRC_PAIRS>(p, nb_d, 8 * pass, 8, w.hist, w.dtot, nullptr, st)) != hipSuccess)
+        if ((e = radix_pass<SRC_PAIRS>(p, nb_d, shift, dw[pass], w.hist, w.dtot, nullptr, st)) != hipSuccess)
             return e;
         uint32_t* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
@@ -743,7 +811,8 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
 
     // 3. emission; 4. tile passes (the last one lands in the caller's arrays)
     const int tbits = bits_for((unsigned long long)vt.total_tiles);
-    const int tpasses = (tbits + 7) / 8;
+    int tw[4];
+    const int tpasses = plan_passes(tbits, tw);
     uint32_t *ek = (tpasses % 2 == 0) ? isect_tile : w.tk;
     uint32_t *ev = (tpasses % 2 == 0) ? isect_gid : w.tv;
     const unsigned emit_blocks = (unsigned)((cap + EMIT_SPAN - 1) / EMIT_SPAN);
@@ -752,12 +821,11 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
     const int nb_t = sort_blocks(cap);
     uint32_t *tki = ek, *tvi = ev;
     uint32_t *tko = (ek == isect_tile) ? w.tk : isect_tile, *tvo = (ev == isect_gid) ? w.tv : isect_gid;
-    for (int pass = 0; pass < tpasses; pass++) {
-        const int shift = 8 * pass, bits = min(8, tbits - shift);
+    for (int pass = 0, shift = 0; pass < tpasses; shift += tw[pass], pass++) {
         SortIO p{};
         p.keys_in = tki; p.vals_in = tvi; p.keys_out = tko; p.vals_out = tvo;
         p.n_dev = w.cnt + 1;
-        if ((e = radix_pass<SRC_PAIRS>(p, nb_t, shift, bits, w.hist, w.dtot, nullptr, st)) != hipSuccess)
+        if ((e = radix_pass<SRC_PAIRS>(p, nb_t, shift, tw[pass], w.hist, w.dtot, nullptr, st)) != hipSuccess)
             return e;
         uint32_t* tk = tki; tki = tko; tko = tk;
         uint32_t* tv = tvi; tvi = tvo; tvo = tv;
