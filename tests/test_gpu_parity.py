@@ -38,6 +38,8 @@ SCENES = {
     "ragged": lambda: scenes.tiny(seed=21, n_gaussians=1500, width=100, height=75, focal=90.0),
     "hd": lambda: scenes.hd(n_gaussians=200_000),
     "multi": _multi,
+    # 512 x 130 tiles of 8 px: 17-bit tile ids, sorted in a 9-bit and an 8-bit pass
+    "wide": lambda: scenes.tiny(seed=31, n_gaussians=3000, width=4096, height=1040, focal=1000.0),
 }
 
 
@@ -120,7 +122,7 @@ def test_project_parity(name, tile):
         assert (e_fac.max() if m.any() else 0) <= 1e-3
 
 
-@pytest.mark.parametrize("name,tile", CASES)
+@pytest.mark.parametrize("name,tile", CASES + [("wide", 8)])
 def test_bin_sort_bit_exact(name, tile):
     s = scene(name)
     _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
