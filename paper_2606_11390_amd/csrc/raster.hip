@@ -39,8 +39,7 @@ struct Rec {
 // back with three broadcast LDS loads instead of eleven readlanes, which
 // would take VALU issue slots from the per-pixel work that bounds it).
 struct WaveStage {
-    float4 rec[3][GS_WAVE];
-    int gid[GS_WAVE];
+    float4 rec[3][GS_WAVE];   // rec[2] holds (b, sigma, splat index, -): the box is only needed by the cull
 };
 
 // A wave's copy of part of its current batch in LDS: the forward reads an
@@ -304,9 +303,11 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
     const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
     float* gbase = grad2d + (size_t)U.v * (size_t)N * GS_GRAD_FLOATS;
     const int lane = __lane_id();
-    // factor of the gradient value this lane's wave sum carries
+    // factor of the gradient value this lane's wave sum carries: the q'
+    // derivatives (slots 0-4) leave out -ln 2 and, per slot, 2, 2, c0, 2 c0, c0
     const int jl = wave_sum9_slot(lane);
-    const float gscale = jl < 2 ? 2.0f : (jl == 3 ? 2.0f * kC0 : (jl == 2 || jl == 4 ? kC0 : 1.0f));
+    const float gscale =
+        jl < 2 ? -2.0f * kLn2 : (jl == 3 ? -2.0f * kC0 * kLn2 : (jl == 2 || jl == 4 ? -kC0 * kLn2 : 1.0f));
     // batches walk the list from its last contributing entry backwards: lane
     // l of the batch starting at kb holds entry kb - l.  As in the forward,
     // the next batch's records and the one after's indices are in flight
@@ -327,8 +328,7 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
             // the wave's program order, and LDS serves one wave in order
             stage->rec[0][lane] = cur.a;
             stage->rec[1][lane] = cur.b;
-            stage->rec[2][lane] = cur.c;
-            stage->gid[lane] = g_cur;
+            stage->rec[2][lane] = make_float4(cur.c.x, cur.c.y, __int_as_float(g_cur), 0.0f);
             while (mask) {
                 const int j = __builtin_ctzll(mask);
                 mask &= mask - 1;
@@ -347,12 +347,12 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                     any = any || okp[p];
                 }
                 if (__ballot(any) == 0ull) continue;
-                const int gid = __builtin_amdgcn_readfirstlane(stage->gid[j]);
-                const float2 rc = *reinterpret_cast<const float2*>(&stage->rec[2][j]);
+                const float4 rc = stage->rec[2][j];
+                const int gid = __builtin_amdgcn_readfirstlane(__float_as_int(rc.z));
                 const float cr = rb.z, cg = rb.w, cb = rc.x;
                 const float inv_sig = __builtin_amdgcn_rcpf(rc.y);
-                // a0..a4 leave out constant factors (2, 2, c0, 2 c0, c0) that
-                // are applied once to the wave sums (gscale)
+                // a0..a4 leave out constant factors (-ln 2 times 2, 2, c0,
+                // 2 c0, c0) that are applied once to the wave sums (gscale)
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
@@ -372,7 +372,8 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                     if (HAS_DA) ga = __builtin_fmaf(gA[p], rom, ga);
                     // d alpha / d(sigma, q') vanish where alpha is clamped at 0.99
                     const float gu = (ok && f.araw < kAlphaMax) ? ga : 0.0f;
-                    const float gq = -kLn2 * al * gu;
+                    // dL/dq' = -ln 2 al gu; the -ln 2 is one of the factors in gscale
+                    const float gq = al * gu;
                     a6 = __builtin_fmaf(wgt, g0[p], a6);
                     a7 = __builtin_fmaf(wgt, g1[p], a7);
                     a8 = __builtin_fmaf(wgt, g2[p], a8);
