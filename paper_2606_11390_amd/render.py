@@ -87,6 +87,8 @@ class Renderer:
         self.capacity = 0
         self.set_capacity(capacity)
         self.graph = None
+        # second stream of step() (default priority)
+        self._side = torch.cuda.Stream(device=self.device)
 
     # ---------------------------------------------------------------- buffers
     def set_capacity(self, capacity):
@@ -135,11 +137,11 @@ class Renderer:
         B.rasterize_fwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
                         self.background, s, q, self.images, self.T_final, self.n_contrib, block=self.block)
 
-    def raster_bwd(self, d_images, d_alpha=None):
+    def raster_bwd(self, d_images, d_alpha=None, accumulate=False):
         s, q = self._sched(self.order_bwd)
         B.rasterize_bwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
                         self.background, s, q, self.T_final, self.n_contrib, d_images, d_alpha, self.grad2d,
-                        block=self.block_bwd)
+                        accumulate=accumulate, block=self.block_bwd)
 
     def project_bwd(self, P, cams, grads):
         B.project_bwd(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
@@ -164,10 +166,23 @@ class Renderer:
     # ---------------------------------------------------------- whole step
     def step(self, P, cams, targets, grads):
         """Forward, L2 loss against packed ``targets`` and backward into
-        ``grads`` (dict of tensors shaped like the parameters)."""
+        ``grads`` (dict of tensors shaped like the parameters).
+
+        The 2-D gradient buffer is zeroed on a second stream while the
+        projection, binning, forward and loss run (a fill of V N 36 bytes that
+        would otherwise sit between the loss and the backward); the backward
+        then accumulates into it.  Both streams have the default priority, and
+        the fork and join are events, so the step stays capturable."""
+        cur = torch.cuda.current_stream()
+        self._side.wait_stream(cur)   # earlier readers of grad2d have finished
+        with torch.cuda.stream(self._side):
+            self.grad2d.zero_()
         self.forward(P, cams)
         self.loss_l2(targets)
-        return self.backward(P, cams, self.d_images, grads)
+        cur.wait_stream(self._side)
+        self.raster_bwd(self.d_images, accumulate=True)
+        self.project_bwd(P, cams, grads)
+        return grads
 
     def fit_capacity(self, P, cams, headroom=1.25):
         """Run projection + binning eagerly and grow the intersection capacity

@@ -186,6 +186,8 @@ def test_graph_replay_matches_eager(order):
         for v in grads.values():
             v.fill_(float("nan"))
         r.images.fill_(float("nan"))
+        # the step zeroes the 2-D gradients itself (on its second stream)
+        r.grad2d.fill_(float("nan"))
         torch.cuda.synchronize()
         r.replay()
         torch.cuda.synchronize()
