@@ -359,7 +359,11 @@ def autotune(P, cams, targets, sh_degree, sizes, tiles=(8, 16, 32), steps=5, cac
         r.order_bwd, r.block_bwd = min(bwd_ms, key=bwd_ms.get)
         r.raster_fwd()
         r.capture(P, cams, targets, grads, warmup=1)
-        ms = _time_ms(r.replay, steps)
+        # the first replays include the graph's upload; the step is then timed
+        # over at least 10 replays (tile edges a few percent apart decide here)
+        for _ in range(3):
+            r.replay()
+        ms = _time_ms(r.replay, max(10, 2 * steps))
         trials[f"tile{tile}"] = {"step_ms": ms,
                                  "fwd_ms": {f"{o}/{b[0]}x{b[1]}": v for (o, b), v in fwd_ms.items()},
                                  "bwd_ms": {f"{o}/{b[0]}x{b[1]}": v for (o, b), v in bwd_ms.items()}}
