@@ -87,8 +87,6 @@ class Renderer:
         self.capacity = 0
         self.set_capacity(capacity)
         self.graph = None
-        # second stream of step() (default priority)
-        self._side = torch.cuda.Stream(device=self.device)
 
     # ---------------------------------------------------------------- buffers
     def set_capacity(self, capacity):
@@ -166,23 +164,10 @@ class Renderer:
     # ---------------------------------------------------------- whole step
     def step(self, P, cams, targets, grads):
         """Forward, L2 loss against packed ``targets`` and backward into
-        ``grads`` (dict of tensors shaped like the parameters).
-
-        The 2-D gradient buffer is zeroed on a second stream while the
-        projection, binning, forward and loss run (a fill of V N 36 bytes that
-        would otherwise sit between the loss and the backward); the backward
-        then accumulates into it.  Both streams have the default priority, and
-        the fork and join are events, so the step stays capturable."""
-        cur = torch.cuda.current_stream()
-        self._side.wait_stream(cur)   # earlier readers of grad2d have finished
-        with torch.cuda.stream(self._side):
-            self.grad2d.zero_()
+        ``grads`` (dict of tensors shaped like the parameters)."""
         self.forward(P, cams)
         self.loss_l2(targets)
-        cur.wait_stream(self._side)
-        self.raster_bwd(self.d_images, accumulate=True)
-        self.project_bwd(P, cams, grads)
-        return grads
+        return self.backward(P, cams, self.d_images, grads)
 
     def fit_capacity(self, P, cams, headroom=1.25):
         """Run projection + binning eagerly and grow the intersection capacity
