@@ -448,14 +448,27 @@ __device__ __forceinline__ QUnit qunit_of(const ViewTable& vt, int gt, int wit)
 }
 
 // per-row entry masks of one batch: the 8x8 block's exact test, then the
-// alpha box against each quarter
+// entry's ellipse q' <= log2(255 sigma) + 0.02 (the region block_may_take
+// keeps) against each quarter through its bounding box.  With q' = w0^2 + w1^2,
+// w0 = m00 dx + m10 dy, w1 = m11 dy, the ellipse q' <= L spans
+// |dy| <= sqrt(L) / m11 and |dx| <= sqrt(L) sqrt(m10^2 + m11^2) / (m00 m11);
+// both are widened by 0.1 % and 0.01 px against float32 rounding.  (The
+// record's integer box, padded by a pixel, is too loose for 4x4 quarters.)
 __device__ __forceinline__ void quarter_masks(const Rec& e, bool in, int bx0, int by0, uint64_t (&m)[4])
 {
     const int bxp = __float_as_int(e.c.z), byp = __float_as_int(e.c.w);
     const bool blk = in && !misses(bxp, bx0, bx0 + 7) && !misses(byp, by0, by0 + 7) &&
                      block_may_take(e, bx0, bx0 + 7, by0, by0 + 7);
-    const bool xl = !misses(bxp, bx0, bx0 + 3), xr = !misses(bxp, bx0 + 4, bx0 + 7);
-    const bool yt = !misses(byp, by0, by0 + 3), yb = !misses(byp, by0 + 4, by0 + 7);
+    const float m00 = e.a.z, m10 = e.a.w, m11 = e.b.x;
+    const float sl = __builtin_sqrtf(fmaxf(e.b.y + (7.99435344f + 0.02f), 0.0f));
+    const float rm11 = __builtin_amdgcn_rcpf(m11);
+    const float hy = __builtin_fmaf(sl * rm11, 1.001f, 0.01f);
+    const float hx = __builtin_fmaf(sl * __builtin_sqrtf(m10 * m10 + m11 * m11) * rm11 * __builtin_amdgcn_rcpf(m00),
+                                    1.001f, 0.01f);
+    // pixel centres of the left / right quarter columns: bx0 + 0.5 .. bx0 + 3.5, bx0 + 4.5 .. bx0 + 7.5
+    const float u = e.a.x - (float)bx0, v = e.a.y - (float)by0;
+    const bool xl = u - hx <= 3.5f && u + hx >= 0.5f, xr = u - hx <= 7.5f && u + hx >= 4.5f;
+    const bool yt = v - hy <= 3.5f && v + hy >= 0.5f, yb = v - hy <= 7.5f && v + hy >= 4.5f;
     m[0] = __ballot(blk && xl && yt);
     m[1] = __ballot(blk && xr && yt);
     m[2] = __ballot(blk && xl && yb);
