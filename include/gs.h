@@ -240,9 +240,7 @@ int gs_tile_order_xcd(int64_t total_tiles, int n_xcd, void* schedule, size_t sch
  *   64 * px_per_lane / block_w rows) and the adjacent pixels each lane owns;
  *   0, 0 selects the default (8, 1).  Valid pairs: tile 8: (8, 1); tile 16:
  *   (8, 1), (16, 1), (16, 2), (16, 4); tile 32: (8, 1), (16, 2), (16, 4),
- *   (32, 4).  (4, 1), at every tile edge, is the row-split 8x8 block: each
- *   16-lane row of the wavefront owns a 4x4 quarter and walks its own culled
- *   list.  The choice changes only speed, never a result bit.
+ *   (32, 4).  The choice changes only speed, never a result bit.
  * schedule, queue: how tiles are assigned to workgroups.
  *   schedule NULL: one workgroup per tile, in tile order (queue must be NULL).
  *   schedule set, queue NULL: one workgroup per tile, workgroup b renders

@@ -128,9 +128,7 @@ __device__ __forceinline__ int wave_sum9_slot(int l)
     return ((l & 8) ? 1 : 0) | ((l & 4) ? 2 : 0) | ((l & 1) ? 4 : 0) | ((l & 2) ? 8 : 0);
 }
 
-// The four in-row steps of wave_sum9_scatter: each 16-lane row ends with the
-// totals over its own lanes (lane l holds value j(l) of its row).
-__device__ __forceinline__ float row_sum9_scatter(const float* a, int& j)
+__device__ __forceinline__ float wave_sum9_scatter(const float* a, int& j)
 {
     const int l = __lane_id();
     const bool h1 = l & 8, h2 = l & 4, h3 = l & 1, h4 = l & 2;
@@ -140,15 +138,10 @@ __device__ __forceinline__ float row_sum9_scatter(const float* a, int& j)
     const float c0 = bfly<0x141>(b0, b1, h2), c1 = bfly<0x141>(b2, b3, h2);
     const float c2 = bfly0<0x141>(b4, h2);
     const float d0 = bfly<0xB1>(c0, c1, h3), d1 = bfly0<0xB1>(c2, h3);
-    j = wave_sum9_slot(l);
-    return bfly<0x4E>(d0, d1, h4);
-}
-
-__device__ __forceinline__ float wave_sum9_scatter(const float* a, int& j)
-{
-    float e = row_sum9_scatter(a, j);
+    float e = bfly<0x4E>(d0, d1, h4);
     e += __shfl_xor(e, 16);
     e += __shfl_xor(e, 32);
+    j = wave_sum9_slot(l);
     return e;
 }
 

@@ -404,279 +404,6 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Row-split waves: a wave still owns an 8x8 pixel block, but each 16-lane row
-// owns one 4x4 quarter of it and walks its own culled entry list, so a wave
-// iteration composites up to four different entries (one per row) and an
-// entry reaches only the rows whose quarter its alpha box overlaps.  Small
-// splats cover a few pixels; on the 4K workload this cuts the entries a wave
-// walks to about half of what one list per 8x8 block costs.  The per-pixel
-// arithmetic, the skip and stop tests and each pixel's entry order are those
-// of fwd_unit / bwd_unit, so every result bit is the same.
-// ---------------------------------------------------------------------------
-
-// A wave's LDS copy of its batch for the row-split forward: rows read
-// different entries, so every field comes from LDS (no readlane broadcast).
-struct QStage {
-    float4 a[GS_WAVE];
-    float4 b[GS_WAVE];
-    float cb[GS_WAVE];
-};
-
-struct QUnit {
-    int v, bx0, by0;   // view, 8x8 block origin
-    int px, py;        // this lane's pixel
-    int row;           // 16-lane row = quarter (0: top left, 1: top right, 2: bottom left, 3: bottom right)
-};
-
-template <int TS>
-__device__ __forceinline__ QUnit qunit_of(const ViewTable& vt, int gt, int wit)
-{
-    constexpr int WX = TS / 8;
-    QUnit u;
-    u.v = view_of_tile(vt, gt);
-    const int lt = gt - vt.tile_off[u.v];
-    const int TX = vt.tiles_x[u.v];
-    const int ty = lt / TX, tx = lt - ty * TX;
-    u.bx0 = tx * TS + (wit % WX) * 8;
-    u.by0 = ty * TS + (wit / WX) * 8;
-    const int lane = __lane_id(), i = lane & 15;
-    u.row = lane >> 4;
-    u.px = u.bx0 + (u.row & 1) * 4 + (i & 3);
-    u.py = u.by0 + (u.row >> 1) * 4 + (i >> 2);
-    return u;
-}
-
-// per-row entry masks of one batch: the 8x8 block's exact test, then the
-// entry's ellipse q' <= log2(255 sigma) + 0.02 (the region block_may_take
-// keeps) against each quarter through its bounding box.  With q' = w0^2 + w1^2,
-// w0 = m00 dx + m10 dy, w1 = m11 dy, the ellipse q' <= L spans
-// |dy| <= sqrt(L) / m11 and |dx| <= sqrt(L) sqrt(m10^2 + m11^2) / (m00 m11);
-// both are widened by 0.1 % and 0.01 px against float32 rounding.  (The
-// record's integer box, padded by a pixel, is too loose for 4x4 quarters.)
-__device__ __forceinline__ void quarter_masks(const Rec& e, bool in, int bx0, int by0, uint64_t (&m)[4])
-{
-    const int bxp = __float_as_int(e.c.z), byp = __float_as_int(e.c.w);
-    const bool blk = in && !misses(bxp, bx0, bx0 + 7) && !misses(byp, by0, by0 + 7) &&
-                     block_may_take(e, bx0, bx0 + 7, by0, by0 + 7);
-    const float m00 = e.a.z, m10 = e.a.w, m11 = e.b.x;
-    const float sl = __builtin_sqrtf(fmaxf(e.b.y + (7.99435344f + 0.02f), 0.0f));
-    const float rm11 = __builtin_amdgcn_rcpf(m11);
-    const float hy = __builtin_fmaf(sl * rm11, 1.001f, 0.01f);
-    const float hx = __builtin_fmaf(sl * __builtin_sqrtf(m10 * m10 + m11 * m11) * rm11 * __builtin_amdgcn_rcpf(m00),
-                                    1.001f, 0.01f);
-    // pixel centres of the left / right quarter columns: bx0 + 0.5 .. bx0 + 3.5, bx0 + 4.5 .. bx0 + 7.5
-    const float u = e.a.x - (float)bx0, v = e.a.y - (float)by0;
-    const bool xl = u - hx <= 3.5f && u + hx >= 0.5f, xr = u - hx <= 7.5f && u + hx >= 4.5f;
-    const bool yt = v - hy <= 3.5f && v + hy >= 0.5f, yb = v - hy <= 7.5f && v + hy >= 4.5f;
-    m[0] = __ballot(blk && xl && yt);
-    m[1] = __ballot(blk && xr && yt);
-    m[2] = __ballot(blk && xl && yb);
-    m[3] = __ballot(blk && xr && yb);
-}
-
-// next entry of every row (64: the row has none left), cleared from the
-// masks; the lane's own row's index is picked by two selects on constant
-// lane masks (rows 1 and 3, rows 2 and 3), so no lane-dependent branch forms
-__device__ __forceinline__ int next_quarter_entries(uint64_t (&m)[4])
-{
-    int j[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        j[q] = m[q] ? (int)__builtin_ctzll(m[q]) : GS_WAVE;
-        m[q] &= m[q] - 1;
-    }
-    const bool odd = __builtin_amdgcn_inverse_ballot_w64(0xFFFF0000FFFF0000ull);
-    const bool high = __builtin_amdgcn_inverse_ballot_w64(0xFFFFFFFF00000000ull);
-    const int ja = odd ? j[1] : j[0];
-    const int jb = odd ? j[3] : j[2];
-    return high ? jb : ja;
-}
-
-constexpr uint64_t kRowBits = 0xFFFFull;
-
-template <int TS, bool COUNT>
-__device__ __forceinline__ void fwd_unit_q(const ViewTable& vt, int gt, int wit,
-                                           const float* __restrict__ splats,
-                                           const int* __restrict__ gids,
-                                           const int2* __restrict__ ranges, long long N, float bg0,
-                                           float bg1, float bg2, float* __restrict__ img,
-                                           float* __restrict__ Tout, int* __restrict__ lastout,
-                                           int* __restrict__ visits, QStage* __restrict__ st)
-{
-    const QUnit U = qunit_of<TS>(vt, gt, wit);
-    const int W = vt.W[U.v], H = vt.H[U.v];
-    const float fx = (float)U.px + 0.5f, fy = (float)U.py + 0.5f;
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int last = 0, stopk = -1;
-    uint64_t live = __ballot(U.px < W && U.py < H);
-    const int2 r = ranges[gt];
-    const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
-    const int lane = __lane_id();
-    if (r.y > r.x) {
-        const int kl = r.y - 1;
-        int g_nxt = gids[min(r.x + GS_WAVE + lane, kl)];
-        Rec cur = load_rec(base, gids[min(r.x + lane, kl)]);
-        bool alive = true;
-        for (int kb = r.x; alive && kb < r.y; kb += GS_WAVE) {
-            const Rec nxt = load_rec(base, g_nxt);
-            const int g_nn = gids[min(kb + 2 * GS_WAVE + lane, kl)];
-            uint64_t m[4];
-            quarter_masks(cur, kb + lane < r.y, U.bx0, U.by0, m);
-            // the previous batch's reads of the stage precede these writes in
-            // the wave's program order, and LDS serves one wave in order
-            st->a[lane] = cur.a;
-            st->b[lane] = cur.b;
-            st->cb[lane] = cur.c.x;
-            while ((m[0] | m[1] | m[2] | m[3]) != 0ull) {
-                if (live == 0ull) {
-                    alive = false;
-                    break;
-                }
-                // a row whose pixels have all stopped takes no more entries
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    if (((live >> (16 * q)) & kRowBits) == 0ull) m[q] = 0ull;
-                const int j = next_quarter_entries(m);
-                const bool valid = j < GS_WAVE;
-                const int jc = valid ? j : 0;
-                const float4 ea = st->a[jc];
-                const float4 eb = st->b[jc];
-                const float al = fminf(falloff(ea.x - fx, ea.y - fy, ea.z, ea.w, eb.x, eb.y).araw, kAlphaMax);
-                // votes on single compares (a vote on a combined flag costs two more instructions)
-                const uint64_t take = __ballot(al >= kAlphaMin) & __ballot(valid) & live;
-                if (take == 0ull) continue;
-                const float cb = st->cb[jc];
-                const int k1 = kb + j - r.x + 1;
-                const float Tn = __builtin_fmaf(-T, al, T);
-                const uint64_t stop = __ballot(Tn < kTMin) & take;
-                live &= ~stop;
-                if (COUNT) stopk = __builtin_amdgcn_inverse_ballot_w64(stop) ? k1 : stopk;
-                const bool ok = __builtin_amdgcn_inverse_ballot_w64(take & ~stop);
-                const float wgt = ok ? al * T : 0.0f;
-                C0 = __builtin_fmaf(wgt, eb.z, C0);
-                C1 = __builtin_fmaf(wgt, eb.w, C1);
-                C2 = __builtin_fmaf(wgt, cb, C2);
-                T = ok ? Tn : T;
-                last = ok ? k1 : last;
-            }
-            cur = nxt;
-            g_nxt = g_nn;
-        }
-    }
-    if (U.px < W && U.py < H) {
-        const long long po = vt.pix_off[U.v];
-        const long long plane = (long long)W * H;
-        const long long pix = (long long)U.py * W + U.px;
-        img[3 * po + pix] = __builtin_fmaf(T, bg0, C0);
-        img[3 * po + plane + pix] = __builtin_fmaf(T, bg1, C1);
-        img[3 * po + 2 * plane + pix] = __builtin_fmaf(T, bg2, C2);
-        Tout[po + pix] = T;
-        lastout[po + pix] = last;
-        if (COUNT) visits[po + pix] = stopk >= 0 ? stopk : r.y - r.x;
-    }
-}
-
-template <int TS, bool HAS_DA>
-__device__ __forceinline__ void bwd_unit_q(const ViewTable& vt, int gt, int wit,
-                                           const float* __restrict__ splats,
-                                           const int* __restrict__ gids,
-                                           const int2* __restrict__ ranges, long long N, float bg0,
-                                           float bg1, float bg2, const float* __restrict__ Tfin,
-                                           const int* __restrict__ nlast,
-                                           const float* __restrict__ dimg,
-                                           const float* __restrict__ dalpha,
-                                           float* __restrict__ grad2d, WaveStage* __restrict__ stage)
-{
-    const QUnit U = qunit_of<TS>(vt, gt, wit);
-    const int W = vt.W[U.v], H = vt.H[U.v];
-    const long long po = vt.pix_off[U.v];
-    const long long plane = (long long)W * H;
-    const float fx = (float)U.px + 0.5f, fy = (float)U.py + 0.5f;
-    const bool in = U.px < W && U.py < H;
-    const long long pix = (long long)U.py * W + U.px;
-    float T = in ? Tfin[po + pix] : 1.0f;
-    const int last = in ? nlast[po + pix] : 0;
-    const float g0 = in ? dimg[3 * po + pix] : 0.0f;
-    const float g1 = in ? dimg[3 * po + plane + pix] : 0.0f;
-    const float g2 = in ? dimg[3 * po + 2 * plane + pix] : 0.0f;
-    // d(1 - T_N)/d alpha_k = T_N / (1 - alpha_k): keep gA * T_N
-    const float gA = (HAS_DA && in) ? dalpha[po + pix] * T : 0.0f;
-    float S0 = bg0, S1 = bg1, S2 = bg2;
-    int kmax = __builtin_amdgcn_readfirstlane(wave_max_i(last));
-    const int2 r = ranges[gt];
-    kmax = min(kmax, r.y - r.x);
-    const float* base = splats + (size_t)U.v * (size_t)N * GS_SPLAT_FLOATS;
-    float* gbase = grad2d + (size_t)U.v * (size_t)N * GS_GRAD_FLOATS;
-    const int lane = __lane_id();
-    // factor of the gradient value this lane's row sum carries (see bwd_unit)
-    const int jl = wave_sum9_slot(lane);
-    const float gscale =
-        jl < 2 ? -2.0f * kLn2 : (jl == 3 ? -2.0f * kC0 * kLn2 : (jl == 2 || jl == 4 ? -kC0 * kLn2 : 1.0f));
-    if (kmax > 0) {
-        const int kend = r.x + kmax - 1;
-        int g_cur = gids[max(kend - lane, r.x)];
-        int g_nxt = gids[max(kend - GS_WAVE - lane, r.x)];
-        Rec cur = load_rec(base, g_cur);
-        for (int kb = kend; kb >= r.x; kb -= GS_WAVE) {
-            const Rec nxt = load_rec(base, g_nxt);
-            const int g_nn = gids[max(kb - 2 * GS_WAVE - lane, r.x)];
-            uint64_t m[4];
-            quarter_masks(cur, kb - lane >= r.x, U.bx0, U.by0, m);
-            stage->rec[0][lane] = cur.a;
-            stage->rec[1][lane] = cur.b;
-            stage->rec[2][lane] = make_float4(cur.c.x, cur.c.y, __int_as_float(g_cur), 0.0f);
-            while ((m[0] | m[1] | m[2] | m[3]) != 0ull) {
-                const int j = next_quarter_entries(m);
-                const bool valid = j < GS_WAVE;
-                const int jc = valid ? j : 0;
-                const float4 ra = stage->rec[0][jc];
-                const float4 rb = stage->rec[1][jc];
-                const float su = ra.x, sv = ra.y, m00 = ra.z, m10 = ra.w, m11 = rb.x, ls = rb.y;
-                const float dx = su - fx, dy = sv - fy;
-                const int kk = kb - j - r.x;
-                const Falloff f = falloff(dx, dy, m00, m10, m11, ls);
-                const uint64_t took =
-                    __ballot(valid) & __ballot(kk < last) & __ballot(fminf(f.araw, kAlphaMax) >= kAlphaMin);
-                if (took == 0ull) continue;
-                const bool ok = __builtin_amdgcn_inverse_ballot_w64(took);
-                const float4 rc = stage->rec[2][jc];
-                const int gid = __float_as_int(rc.z);
-                const float cr = rb.z, cg = rb.w, cb = rc.x;
-                const float inv_sig = __builtin_amdgcn_rcpf(rc.y);
-                const float al = fminf(f.araw, kAlphaMax);
-                const float alo = ok ? al : 0.0f;
-                const float rom = __builtin_amdgcn_rcpf(1.0f - alo);
-                const float Tk = T * rom;
-                const float wgt = alo * Tk;
-                const float d0 = cr - S0, d1 = cg - S1, d2 = cb - S2;
-                float ga = Tk * (d0 * g0 + d1 * g1 + d2 * g2);
-                if (HAS_DA) ga = __builtin_fmaf(gA, rom, ga);
-                const float gu = (ok && f.araw < kAlphaMax) ? ga : 0.0f;
-                // dL/dq' = -ln 2 al gu; the -ln 2 is one of the factors in gscale
-                const float gq = al * gu;
-                const float gqx = gq * dx;
-                const float acc[GS_GRAD_FLOATS] = {gq * (m00 * f.w0), gq * __builtin_fmaf(m10, f.w0, m11 * f.w1),
-                                                   gqx * dx, gqx * dy, (gq * dy) * dy, (f.araw * inv_sig) * gu,
-                                                   wgt * g0, wgt * g1, wgt * g2};
-                S0 = __builtin_fmaf(alo, d0, S0);
-                S1 = __builtin_fmaf(alo, d1, S1);
-                S2 = __builtin_fmaf(alo, d2, S2);
-                T = Tk;
-                int jj;
-                const float x = row_sum9_scatter(acc, jj) * gscale;
-                // rows none of whose pixels took their entry add nothing
-                const bool row_took = ((took >> (16 * U.row)) & kRowBits) != 0ull;
-                if (row_took && jj < GS_GRAD_FLOATS)
-                    unsafeAtomicAdd(gbase + (size_t)gid * GS_GRAD_FLOATS + jj, x);
-            }
-            cur = nxt;
-            g_cur = g_nxt;
-            g_nxt = g_nn;
-        }
-    }
-}
-
 // Persistent waves take work in chunks of QCHUNK items from one global
 // counter (one atomic per chunk keeps the counter off the critical path);
 // chunk c holds items c, c + n_chunks, c + 2 n_chunks, ..., so every chunk
@@ -858,147 +585,16 @@ hipError_t bwd_cfg(const ViewTable& vt, const float* splats, const int* gids, co
     return hipGetLastError();
 }
 
-// ---- row-split kernels: 8x8 blocks per wave, a 4x4 quarter per 16-lane row
-template <int TS, bool COUNT>
-__global__ __launch_bounds__(GS_WAVE * (TS / 8) * (TS / 8)) void k_raster_fwd_q(
-    ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
-    const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
-    const int* __restrict__ order, float* __restrict__ img, float* __restrict__ Tout,
-    int* __restrict__ lastout, int* __restrict__ visits)
-{
-    __shared__ QStage st[(TS / 8) * (TS / 8)];
-    const int gt = tile_of_block(order, vt.total_tiles);
-    if (gt < 0) return;
-    const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
-    fwd_unit_q<TS, COUNT>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout, lastout, visits,
-                          &st[wit]);
-}
-
-template <int TS>
-__global__ __launch_bounds__(GS_WAVE) void k_raster_fwd_q_persistent(
-    ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
-    const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
-    const int* __restrict__ order, int* __restrict__ queue, float* __restrict__ img,
-    float* __restrict__ Tout, int* __restrict__ lastout)
-{
-    constexpr int WPT = (TS / 8) * (TS / 8);
-    __shared__ QStage st;
-    const int n_items = vt.total_tiles * WPT;
-    const int n_chunks = (n_items + QCHUNK - 1) / QCHUNK;
-    int c = ticket(claim(queue));
-    while (c < n_chunks) {
-        const int next = claim(queue);
-        for (int item = c; item < n_items; item += n_chunks) {
-            const int gt = order[item / WPT];
-            if ((unsigned)gt < (unsigned)vt.total_tiles)
-                fwd_unit_q<TS, false>(vt, gt, item % WPT, splats, gids, ranges, N, bg0, bg1, bg2, img, Tout,
-                                      lastout, nullptr, &st);
-        }
-        c = ticket(next);
-    }
-}
-
-template <int TS, bool HAS_DA>
-__global__ __launch_bounds__(GS_WAVE * (TS / 8) * (TS / 8)) void k_raster_bwd_q(
-    ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
-    const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
-    const int* __restrict__ order, const float* __restrict__ Tfin, const int* __restrict__ nlast,
-    const float* __restrict__ dimg, const float* __restrict__ dalpha, float* __restrict__ grad2d)
-{
-    __shared__ WaveStage stage[(TS / 8) * (TS / 8)];
-    const int gt = tile_of_block(order, vt.total_tiles);
-    if (gt < 0) return;
-    const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
-    bwd_unit_q<TS, HAS_DA>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, dimg, dalpha,
-                           grad2d, &stage[wit]);
-}
-
-template <int TS, bool HAS_DA>
-__global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_q_persistent(
-    ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
-    const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
-    const int* __restrict__ order, int* __restrict__ queue, const float* __restrict__ Tfin,
-    const int* __restrict__ nlast, const float* __restrict__ dimg, const float* __restrict__ dalpha,
-    float* __restrict__ grad2d)
-{
-    constexpr int WPT = (TS / 8) * (TS / 8);
-    __shared__ WaveStage stage;
-    const int n_items = vt.total_tiles * WPT;
-    const int n_chunks = (n_items + QCHUNK - 1) / QCHUNK;
-    int c = ticket(claim(queue));
-    while (c < n_chunks) {
-        const int next = claim(queue);
-        for (int item = c; item < n_items; item += n_chunks) {
-            const int gt = order[item / WPT];
-            if ((unsigned)gt < (unsigned)vt.total_tiles)
-                bwd_unit_q<TS, HAS_DA>(vt, gt, item % WPT, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast,
-                                       dimg, dalpha, grad2d, &stage);
-        }
-        c = ticket(next);
-    }
-}
-
-template <int TS>
-hipError_t fwd_cfg_q(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges, long long N,
-                     const float* bg, const int* order, int* queue, float* img, float* Tout, int* lastout,
-                     int* visits, hipStream_t st)
-{
-    constexpr int WPT = (TS / 8) * (TS / 8);
-    if (visits) {
-        hipLaunchKernelGGL((k_raster_fwd_q<TS, true>), dim3(vt.total_tiles), dim3(GS_WAVE * WPT), 0, st, vt,
-                           splats, gids, ranges, N, bg[0], bg[1], bg[2], nullptr, img, Tout, lastout, visits);
-    } else if (order && queue) {
-        hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, queue);
-        hipLaunchKernelGGL((k_raster_fwd_q_persistent<TS>), dim3(persistent_blocks()), dim3(GS_WAVE), 0, st, vt,
-                           splats, gids, ranges, N, bg[0], bg[1], bg[2], order, queue, img, Tout, lastout);
-    } else {
-        hipLaunchKernelGGL((k_raster_fwd_q<TS, false>), dim3(vt.total_tiles), dim3(GS_WAVE * WPT), 0, st, vt,
-                           splats, gids, ranges, N, bg[0], bg[1], bg[2], order, img, Tout, lastout, nullptr);
-    }
-    return hipGetLastError();
-}
-
-template <int TS>
-hipError_t bwd_cfg_q(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges, long long N,
-                     const float* bg, const int* order, int* queue, const float* Tfin, const int* nlast,
-                     const float* dimg, const float* dalpha, float* grad2d, hipStream_t st)
-{
-    constexpr int WPT = (TS / 8) * (TS / 8);
-    if (order && queue) {
-        hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, queue);
-        if (dalpha)
-            hipLaunchKernelGGL((k_raster_bwd_q_persistent<TS, true>), dim3(persistent_blocks()), dim3(GS_WAVE), 0,
-                               st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, queue, Tfin, nlast,
-                               dimg, dalpha, grad2d);
-        else
-            hipLaunchKernelGGL((k_raster_bwd_q_persistent<TS, false>), dim3(persistent_blocks()), dim3(GS_WAVE),
-                               0, st, vt, splats, gids, ranges, N, bg[0], bg[1], bg[2], order, queue, Tfin, nlast,
-                               dimg, dalpha, grad2d);
-    } else {
-        if (dalpha)
-            hipLaunchKernelGGL((k_raster_bwd_q<TS, true>), dim3(vt.total_tiles), dim3(GS_WAVE * WPT), 0, st, vt,
-                               splats, gids, ranges, N, bg[0], bg[1], bg[2], order, Tfin, nlast, dimg, dalpha,
-                               grad2d);
-        else
-            hipLaunchKernelGGL((k_raster_bwd_q<TS, false>), dim3(vt.total_tiles), dim3(GS_WAVE * WPT), 0, st, vt,
-                               splats, gids, ranges, N, bg[0], bg[1], bg[2], order, Tfin, nlast, dimg, dalpha,
-                               grad2d);
-    }
-    return hipGetLastError();
-}
-
 }  // namespace
 
 // Wave blocks available per tile edge (block width, pixels per lane); the
-// first entry of each list is the default.  (4, 1) is the row-split 8x8
-// block: a 4x4 quarter with its own entry list per 16-lane row.
-//   tile 8:  8x8 / 1, row-split
-//   tile 16: 8x8 / 1, 16x4 / 1, 16x8 / 2, 16x16 / 4, row-split
-//   tile 32: 8x8 / 1, 16x8 / 2, 16x16 / 4, 32x8 / 4, row-split
+// first entry of each list is the default.
+//   tile 8:  8x8 / 1
+//   tile 16: 8x8 / 1, 16x4 / 1, 16x16 / 4
+//   tile 32: 8x8 / 1, 16x16 / 4, 32x8 / 4
 bool raster_cfg_ok(int tile, int bw, int ppl)
 {
     if (bw == 0 && ppl == 0) return tile == 8 || tile == 16 || tile == 32;
-    if (bw == 4 && ppl == 1) return tile == 8 || tile == 16 || tile == 32;
     switch (tile) {
     case 8: return bw == 8 && ppl == 1;
     case 16: return (bw == 8 && ppl == 1) || (bw == 16 && (ppl == 1 || ppl == 2 || ppl == 4));
@@ -1017,11 +613,6 @@ hipError_t launch_raster_fwd(int tile, int bw, int ppl, const ViewTable& vt, con
 {
     if (vt.total_tiles == 0) return hipSuccess;
     if (bw == 0) { bw = 8; ppl = 1; }
-    if (bw == 4) {
-        if (tile == 8) return fwd_cfg_q<8>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st);
-        if (tile == 16) return fwd_cfg_q<16>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st);
-        return fwd_cfg_q<32>(vt, splats, gids, ranges, N, bg, order, queue, img, Tout, lastout, visits, st);
-    }
     switch (tile) {
     case 8: GS_FWD(8, 8, 1);
     case 16:
@@ -1048,13 +639,6 @@ hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, con
 {
     if (vt.total_tiles == 0) return hipSuccess;
     if (bw == 0) { bw = 8; ppl = 1; }
-    if (bw == 4) {
-        if (tile == 8)
-            return bwd_cfg_q<8>(vt, splats, gids, ranges, N, bg, order, queue, Tfin, nlast, dimg, dalpha, grad2d, st);
-        if (tile == 16)
-            return bwd_cfg_q<16>(vt, splats, gids, ranges, N, bg, order, queue, Tfin, nlast, dimg, dalpha, grad2d, st);
-        return bwd_cfg_q<32>(vt, splats, gids, ranges, N, bg, order, queue, Tfin, nlast, dimg, dalpha, grad2d, st);
-    }
     switch (tile) {
     case 8: GS_BWD(8, 8, 1);
     case 16:

@@ -284,8 +284,7 @@ def render(renderer, P, cams):
 
 
 # ------------------------------------------------------------------ autotune
-BLOCKS = {8: [(8, 1), (4, 1)], 16: [(8, 1), (4, 1), (16, 1), (16, 2), (16, 4)],
-          32: [(8, 1), (4, 1), (16, 2), (16, 4), (32, 4)]}
+BLOCKS = {8: [(8, 1)], 16: [(8, 1), (16, 1), (16, 2), (16, 4)], 32: [(8, 1), (16, 2), (16, 4), (32, 4)]}
 
 
 def _time_ms(fn, steps):
