@@ -359,7 +359,8 @@ def test_ssim_l1_parity(lam):
 BLOCKS = {8: [(8, 1)], 16: [(8, 1), (16, 1), (16, 2), (16, 4)], 32: [(8, 1), (16, 2), (16, 4), (32, 4)]}
 
 
-@pytest.mark.parametrize("name,tile", [("ragged", 16), ("multi", 16), ("ragged", 32), ("multi", 32)])
+@pytest.mark.parametrize("name,tile", [("ragged", 8), ("multi", 8), ("ragged", 16), ("multi", 16), ("ragged", 32),
+                                       ("multi", 32)])
 def test_raster_blocks_change_only_speed(name, tile):
     """Every wave-block configuration renders bit-identical images and the
     same gradients (up to atomic summation order)."""
@@ -384,6 +385,20 @@ def test_raster_blocks_change_only_speed(name, tile):
             e = G.rel_l2(g, ref[3])
             G.say(f"  block {blk} persistent {persistent}: grad2d rel L2 vs first {e:.1e}")
             assert e <= 1e-6
+    # with an alpha gradient as well
+    img, T, last = ref[0], ref[1], ref[2]
+    rng = np.random.default_rng(2)
+    dimg = rng.standard_normal(img.shape).astype(np.float32)
+    dalpha = rng.standard_normal(T.shape).astype(np.float32)
+    gref = None
+    for blk in BLOCKS[tile]:
+        for persistent in ("tile", "queue"):
+            g = G.gpu_raster_bwd(arrs["splats"], vals, ranges, s.sizes, tile, T, last, dimg, dalpha,
+                                 (0.1, 0.2, 0.3), persistent, blk)
+            if gref is None:
+                gref = g
+                continue
+            assert G.rel_l2(g, gref) <= 1e-6, (blk, persistent)
 
 
 def test_adam_parity_over_steps_and_graph_replay():
