@@ -200,7 +200,7 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
             "project_bwd": 2 * N * param + V * N + 36 * visible}
 
 
-def cpu_baseline(scene, tile, seed=0, frac=0.05, crop_frac=0.25):
+def cpu_baseline(scene, tile, seed=0, frac=0.2, crop_frac=0.5):
     """FP64 oracle on a bounded sample of the same step, scaled to the frame.
 
     Per-Gaussian work (projection + its backward) is timed on a seeded
