@@ -22,7 +22,7 @@ __global__ __launch_bounds__(L_THREADS) void k_l2_partial(const float* __restric
     float acc = 0.0f;
     for (long long i = (long long)blockIdx.x * L_THREADS + threadIdx.x; i < n; i += stride) {
         const float d = img[i] - tgt[i];
-        dimg[i] = scale * d;
+        nt_store(scale * d, &dimg[i]);
         acc = __builtin_fmaf(d, d, acc);
     }
     const float ws = wave_sum(acc);

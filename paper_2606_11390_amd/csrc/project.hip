@@ -473,7 +473,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     // two partial writes (seen and unseen lanes) that may each reach HBM
     if constexpr (SV)
         for (int j = 0; j < K; j++)
-            for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = Ysv[j] * gcsv[ch];
+            for (int ch = 0; ch < 3; ch++)
+                nt_store(Ysv[j] * gcsv[ch], &d_sh[((long long)j * 3 + ch) * N + g]);
 
     // M = R diag(s), s = exp(l):  dl_j = s_j sum_i dM_ij R_ij;  dR_ij = dM_ij s_j
     float gR[9];
@@ -493,13 +494,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     const float qd = w * gq[0] + x * gq[1] + y * gq[2] + zq * gq[3];
     const float sigma = any ? 1.0f / (1.0f + expf(-opac[g])) : 0.0f;
 
-    for (int i = 0; i < 3; i++) d_means[i * N + g] = any ? gmu[i] : 0.0f;
-    for (int i = 0; i < 3; i++) d_log_scales[i * N + g] = any ? gl[i] : 0.0f;
-    for (int k = 0; k < 4; k++) d_quats[k * N + g] = any ? (gq[k] - qh[k] * qd) * iq : 0.0f;
-    d_opac[g] = any ? gsig * sigma * (1.0f - sigma) : 0.0f;
+    for (int i = 0; i < 3; i++) nt_store(any ? gmu[i] : 0.0f, &d_means[i * N + g]);
+    for (int i = 0; i < 3; i++) nt_store(any ? gl[i] : 0.0f, &d_log_scales[i * N + g]);
+    for (int k = 0; k < 4; k++)
+        nt_store(any ? (gq[k] - qh[k] * qd) * iq : 0.0f, &d_quats[k * N + g]);
+    nt_store(any ? gsig * sigma * (1.0f - sigma) : 0.0f, &d_opac[g]);
     if constexpr (!SV)
         for (int j = 0; j < K; j++)
-            for (int ch = 0; ch < 3; ch++) d_sh[((long long)j * 3 + ch) * N + g] = gsh[3 * j + ch];
+            for (int ch = 0; ch < 3; ch++)
+                nt_store(gsh[3 * j + ch], &d_sh[((long long)j * 3 + ch) * N + g]);
 }
 
 }  // namespace

@@ -150,6 +150,47 @@ def test_bin_sort_depth_ties_keep_gaussian_order():
     np.testing.assert_array_equal(rg, ranges)
 
 
+def dense_tile_arrays(seed=5, tile=16):
+    """Two views with tile runs of every length class: more than 8192 entries
+    (20000 small splats over one corner tile), about 5000, several hundred
+    and a few dozen, with many equal depths."""
+    rng = np.random.default_rng(seed)
+    sizes = np.array([[640, 480], [320, 240]], np.int32)
+    V, N = 2, 30000
+    splats = np.zeros((V, N, 12), np.float32)
+    radii = np.zeros((V, N, 2), np.int32)
+    depths = np.zeros((V, N), np.float32)
+    rects = np.zeros((V, N, 2), np.int32)
+    for v in range(V):
+        W, H = (int(x) for x in sizes[v])
+        u, y = rng.uniform(0, W, N), rng.uniform(0, H, N)
+        r = rng.integers(1, 30, (N, 2))
+        u[:20000], y[:20000] = rng.uniform(1, 15, 20000), rng.uniform(1, 15, 20000)
+        r[:20000] = rng.integers(1, 3, (20000, 2))
+        u[20000:25000], y[20000:25000] = rng.uniform(161, 175, 5000), rng.uniform(81, 95, 5000)
+        r[20000:25000] = rng.integers(1, 3, (5000, 2))
+        r[29000:] = 0
+        splats[v, :, 0], splats[v, :, 1], radii[v] = u, y, r
+        depths[v] = np.round(rng.uniform(1, 50, N), 2)
+        rects[v] = G.pack_rects(oracle.tile_rects(splats[v, :, 0], splats[v, :, 1], r.T.copy(), tile, W, H))
+    return dict(splats=splats, depths=depths, radii=radii, rects=rects), sizes
+
+
+def test_bin_sort_long_runs_bit_exact():
+    arrs, sizes = dense_tile_arrays()
+    keys, vals, ranges, offs = G.oracle_binning(arrs, sizes, 16)
+    M = len(keys)
+    runs = ranges[:, 1] - ranges[:, 0]
+    G.say(f"[bin_sort long runs] M={M} longest runs {np.sort(runs)[-6:]}")
+    assert (runs > 8192).sum() >= 2 and ((runs > 512) & (runs <= 8192)).sum() >= 2
+    assert ((runs > 64) & (runs <= 512)).sum() >= 2 and ((runs > 1) & (runs <= 64)).sum() >= 2
+    it, ig, rg, info = G.gpu_bin_sort(arrs, sizes, 16, M + 5)
+    assert tuple(info[:3]) == (int((arrs["radii"][..., 0] > 0).sum()), M, 0)
+    np.testing.assert_array_equal(it[:M], (keys >> np.uint64(32)).astype(np.int32))
+    np.testing.assert_array_equal(ig[:M], vals)
+    np.testing.assert_array_equal(rg, ranges)
+
+
 def test_bin_sort_overflow_and_empty():
     s = scene("tiny")
     _, projs, arrs, keys, vals, ranges, offs = oracle_stage("tiny", 16)
@@ -159,6 +200,14 @@ def test_bin_sort_overflow_and_empty():
     assert info[1] == M and info[2] == 1
     assert rg.min() >= 0 and rg.max() <= cap
     assert np.all(np.diff(it[:cap]) >= 0)
+    # kept: the first `cap` intersections with the pairs in depth order (ties in
+    # Gaussian order) and each pair's tiles row-major, then sorted
+    ek, ev = oracle.bin_view(arrs["splats"][0, :, 0], arrs["splats"][0, :, 1], arrs["depths"][0],
+                             arrs["radii"][0].T.copy(), int(s.sizes[0][0]), int(s.sizes[0][1]), 16)
+    by_depth = np.argsort(ek & np.uint64(0xFFFFFFFF), kind="stable")[:cap]
+    kk, kv = oracle.sort_pairs(ek[by_depth], ev[by_depth])
+    np.testing.assert_array_equal(it[:cap], (kk >> np.uint64(32)).astype(np.int32))
+    np.testing.assert_array_equal(ig[:cap], kv)
     empty = {k: np.zeros_like(v) for k, v in arrs.items()}
     it, ig, rg, info = G.gpu_bin_sort(empty, s.sizes, 16, 64)
     assert tuple(info[:3]) == (0, 0, 0)
