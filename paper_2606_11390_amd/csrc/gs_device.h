@@ -47,6 +47,12 @@ __device__ __forceinline__ void nt_store(int4 v, int4* p)
     __builtin_nontemporal_store(x, reinterpret_cast<gs_nt_i4*>(p));
 }
 
+template <class T>
+__device__ __forceinline__ T nt_load(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 // Constants of the method (3D Gaussian Splatting compositing), float32.
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;

@@ -218,10 +218,10 @@ __global__ __launch_bounds__(256) void k_project(
     constexpr int K = (DEG + 1) * (DEG + 1);
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
-    const float mu[3] = {means[g], means[N + g], means[2 * N + g]};
-    const float ls[3] = {log_scales[g], log_scales[N + g], log_scales[2 * N + g]};
-    const float q[4] = {quats[g], quats[N + g], quats[2 * N + g], quats[3 * N + g]};
-    const float o = opac[g];
+    const float mu[3] = {nt_load(&means[g]), nt_load(&means[N + g]), nt_load(&means[2 * N + g])};
+    const float ls[3] = {nt_load(&log_scales[g]), nt_load(&log_scales[N + g]), nt_load(&log_scales[2 * N + g])};
+    const float q[4] = {nt_load(&quats[g]), nt_load(&quats[N + g]), nt_load(&quats[2 * N + g]), nt_load(&quats[3 * N + g])};
+    const float o = nt_load(&opac[g]);
     bool finite = isfinite(mu[0]) && isfinite(mu[1]) && isfinite(mu[2]) && isfinite(ls[0]) &&
                   isfinite(ls[1]) && isfinite(ls[2]) && isfinite(q[0]) && isfinite(q[1]) &&
                   isfinite(q[2]) && isfinite(q[3]) && isfinite(o);
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void k_project(
             if constexpr (!SV) {
                 if (!have_sh) {
                     for (int j = 0; j < K; j++)
-                        for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
+                        for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = nt_load(&sh[((long long)j * 3 + ch) * N + g]);
                     have_sh = true;
                 }
             }
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_project(
             for (int ch = 0; ch < 3; ch++) {
                 float acc = 0.0f;
                 for (int j = 0; j < K; j++)
-                    acc += (SV ? sh[((long long)j * 3 + ch) * N + g] : coef[SV ? 0 : 3 * j + ch]) * Y[j];
+                    acc += (SV ? nt_load(&sh[((long long)j * 3 + ch) * N + g]) : coef[SV ? 0 : 3 * j + ch]) * Y[j];
                 acc += 0.5f;
                 if (acc < 0.0f) fl |= (uint8_t)(GS_FLAG_CLAMP_R << ch);
                 col[ch] = fmaxf(acc, 0.0f);
@@ -361,9 +361,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     // contiguous, e.g. in Morton order)
     float mu[3] = {0.0f, 0.0f, 0.0f}, ls[3] = {0.0f, 0.0f, 0.0f}, q[4] = {1.0f, 0.0f, 0.0f, 0.0f};
     if (any) {
-        for (int i = 0; i < 3; i++) mu[i] = means[i * N + g];
-        for (int i = 0; i < 3; i++) ls[i] = log_scales[i * N + g];
-        for (int i = 0; i < 4; i++) q[i] = quats[i * N + g];
+        for (int i = 0; i < 3; i++) mu[i] = nt_load(&means[i * N + g]);
+        for (int i = 0; i < 3; i++) ls[i] = nt_load(&log_scales[i * N + g]);
+        for (int i = 0; i < 4; i++) q[i] = nt_load(&quats[i * N + g]);
     }
     const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     const float iq = any ? 1.0f / sqrtf(qn2) : 0.0f;
@@ -377,18 +377,18 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     float coef[SV ? 1 : 3 * K];
     if (!SV && any) {
         for (int j = 0; j < K; j++)
-            for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = sh[((long long)j * 3 + ch) * N + g];
+            for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = nt_load(&sh[((long long)j * 3 + ch) * N + g]);
     }
     // coefficient j, channel ch
-    auto cf = [&](int j, int ch) { return SV ? sh[((long long)j * 3 + ch) * N + g] : coef[SV ? 0 : 3 * j + ch]; };
+    auto cf = [&](int j, int ch) { return SV ? nt_load(&sh[((long long)j * 3 + ch) * N + g]) : coef[SV ? 0 : 3 * j + ch]; };
 
     for (int v = 0; any && v < (SV ? 1 : vt.n_views); v++) {
         const long long o_vg = (long long)v * N + g;
         const uint8_t fl = flags[o_vg];
         if (!(fl & GS_FLAG_VISIBLE)) continue;
         const float* gr = grad2d + o_vg * GS_GRAD_FLOATS;
-        const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4];
-        gsig += gr[5];
+        const float gu = nt_load(&gr[0]), gv = nt_load(&gr[1]), gA = nt_load(&gr[2]), gB = nt_load(&gr[3]), gC = nt_load(&gr[4]);
+        gsig += nt_load(&gr[5]);
         const Camera cam = load_camera(viewmats, intr, vt, v);
         Geo ge;
         geometry(cam, mu, M, eps2d, ge);
@@ -445,8 +445,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(
         d0 *= idn; d1 *= idn; d2 *= idn;
         float Y[K], sdot[K];
         sh_basis<DEG>(d0, d1, d2, Y);
-        const float gc[3] = {(fl & GS_FLAG_CLAMP_R) ? 0.0f : gr[6], (fl & GS_FLAG_CLAMP_G) ? 0.0f : gr[7],
-                             (fl & GS_FLAG_CLAMP_B) ? 0.0f : gr[8]};
+        const float gc[3] = {(fl & GS_FLAG_CLAMP_R) ? 0.0f : nt_load(&gr[6]), (fl & GS_FLAG_CLAMP_G) ? 0.0f : nt_load(&gr[7]),
+                             (fl & GS_FLAG_CLAMP_B) ? 0.0f : nt_load(&gr[8])};
         for (int j = 0; j < K; j++) {
             sdot[j] = cf(j, 0) * gc[0] + cf(j, 1) * gc[1] + cf(j, 2) * gc[2];
             if constexpr (SV) {
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     gq[3] = 2.0f * (-2.0f * zq * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0f * zq * gR[4] +
                     y * gR[5] + x * gR[6] + y * gR[7]);
     const float qd = w * gq[0] + x * gq[1] + y * gq[2] + zq * gq[3];
-    const float sigma = any ? 1.0f / (1.0f + expf(-opac[g])) : 0.0f;
+    const float sigma = any ? 1.0f / (1.0f + expf(-nt_load(&opac[g]))) : 0.0f;
 
     for (int i = 0; i < 3; i++) nt_store(any ? gmu[i] : 0.0f, &d_means[i * N + g]);
     for (int i = 0; i < 3; i++) nt_store(any ? gl[i] : 0.0f, &d_log_scales[i * N + g]);
