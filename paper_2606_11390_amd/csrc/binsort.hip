@@ -852,7 +852,8 @@ hipError_t launch_tile_schedule(const int2* ranges, long long total_tiles, void*
     uint32_t* order = (uint32_t*)base;
     uint32_t* hist = (uint32_t*)(base + align256(4 * t));
     uint32_t* dtot = (uint32_t*)(base + align256(4 * t) + align256(4ull * 256 * RS_MAX_BLOCKS));
-    const int nb = sort_blocks(t);
+    // one 2048-key chunk per block (a short, latency-bound pass)
+    const int nb = (int)min((unsigned long long)RS_MAX_BLOCKS, max(1ull, (t + RS_CHUNK - 1) / RS_CHUNK));
     // one stable 8-bit pass; only the tile ids (the values) are kept
     SortIO a{};
     a.ranges = ranges;
