@@ -331,15 +331,20 @@ def autotune(P, cams, targets, sh_degree, sizes, tiles=(8, 16, 32), steps=5, cac
         r = Renderer(n, sh_degree, sizes, tile=tile, capacity=1 << 20, order="heavy", order_bwd="queue")
         r.fit_capacity(P, cams)
         r.step(P, cams, targets, grads)
-        fwd_ms, bwd_ms = {}, {}
-        for order in ORDERS:
-            for blk in BLOCKS[tile]:
-                r.block = r.block_bwd = blk
-                r.order = r.order_bwd = order
-                r.raster_fwd()
-                fwd_ms[(order, blk)] = _time_ms(r.raster_fwd, steps)
-                r.raster_bwd(r.d_images)
-                bwd_ms[(order, blk)] = _time_ms(lambda: r.raster_bwd(r.d_images), steps)
+        # three interleaved rounds over the candidates, median per candidate:
+        # a drift of the clock during tuning then biases no candidate
+        fwd_t, bwd_t = {}, {}
+        for _ in range(3):
+            for order in ORDERS:
+                for blk in BLOCKS[tile]:
+                    r.block = r.block_bwd = blk
+                    r.order = r.order_bwd = order
+                    r.raster_fwd()
+                    fwd_t.setdefault((order, blk), []).append(_time_ms(r.raster_fwd, steps))
+                    r.raster_bwd(r.d_images)
+                    bwd_t.setdefault((order, blk), []).append(_time_ms(lambda: r.raster_bwd(r.d_images), steps))
+        fwd_ms = {k: float(np.median(v)) for k, v in fwd_t.items()}
+        bwd_ms = {k: float(np.median(v)) for k, v in bwd_t.items()}
         r.order, r.block = min(fwd_ms, key=fwd_ms.get)
         r.order_bwd, r.block_bwd = min(bwd_ms, key=bwd_ms.get)
         r.raster_fwd()

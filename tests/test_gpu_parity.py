@@ -191,6 +191,33 @@ def test_bin_sort_long_runs_bit_exact():
     np.testing.assert_array_equal(rg, ranges)
 
 
+@pytest.mark.parametrize("spread", ["log_wide", "constant", "two_values"])
+def test_bin_sort_depth_spans(spread):
+    """Depth sets of other spreads: log-uniform over seven decades with ties,
+    a constant depth, and two values far apart."""
+    s = scene("multi")
+    tile = 16
+    _, projs, arrs, *_ = oracle_stage("multi", tile)
+    arrs = dict(arrs)
+    rng = np.random.default_rng(11)
+    shape = arrs["depths"].shape
+    if spread == "log_wide":
+        z = np.exp(rng.uniform(np.log(1e-2), np.log(1e5), shape))
+        z[rng.random(shape) < 0.2] = 3.0   # ties as well
+    elif spread == "constant":
+        z = np.full(shape, 7.25)
+    else:
+        z = np.where(rng.random(shape) < 0.5, 0.5, 4096.0)
+    arrs["depths"] = z.astype(np.float32)
+    keys, vals, ranges, offs = G.oracle_binning(arrs, s.sizes, tile)
+    M = len(keys)
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, tile, M + 3)
+    assert info[1] == M and info[2] == 0
+    np.testing.assert_array_equal(it[:M], (keys >> np.uint64(32)).astype(np.int32))
+    np.testing.assert_array_equal(ig[:M], vals)
+    np.testing.assert_array_equal(rg, ranges)
+
+
 def test_bin_sort_overflow_and_empty():
     s = scene("tiny")
     _, projs, arrs, keys, vals, ranges, offs = oracle_stage("tiny", 16)
