@@ -173,9 +173,11 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
     the workload's counts (N Gaussians, V views, visible (view, Gaussian)
     pairs, M intersections, T tiles, P pixels).
 
-    project      every parameter read once (236 B at SH degree 3); per pair
-                 depth, radii, tile count and flags written (17 B); the 48-byte
-                 splat record written for visible pairs only
+    project      the means read for every Gaussian (12 B), the other
+                 parameters (224 B at SH degree 3) for the Gaussians some view
+                 sees (counted as min(N, visible pairs), exact for one view);
+                 per pair depth, radii, tile count, tile rectangle and flags
+                 written (25 B); the 48-byte splat record per visible pair
     bin_sort     LSD radix sort, 16 B (key + value, read + write) per element
                  per pass: 4 depth passes over visible pairs (the first reads
                  depth and tile count, 8 B per pair), emission (24 B read per
@@ -184,7 +186,9 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
                  intersection, 8 B written per tile)
     loss         image and target read, image gradient written: 12 B per
                  element
-    project_bwd  parameters read and their gradients written (2 x 236 B),
+    project_bwd  the gradients of every parameter written (236 B per
+                 Gaussian, zero where no view sees it), the parameters read
+                 for the Gaussians some view sees (min(N, visible pairs)),
                  flags read per pair, the 36-byte 2-D gradient per visible pair
     """
     N, V = scene.n, scene.n_views
@@ -194,10 +198,11 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
     tpasses = (tbits + 7) // 8
     sort = (8 * V * N + 8 * visible + 3 * 16 * visible + 24 * visible + 8 * isect + tpasses * 16 * isect +
             4 * isect + 8 * total_tiles)
-    return {"project": N * param + 17 * V * N + 48 * visible,
+    seen = min(N, visible)
+    return {"project": 12 * N + (param - 12) * seen + 25 * V * N + 48 * visible,
             "bin_sort": sort,
             "loss": 12 * 3 * scene.pixels,
-            "project_bwd": 2 * N * param + V * N + 36 * visible}
+            "project_bwd": N * param + seen * param + V * N + 36 * visible}
 
 
 def cpu_baseline(scene, tile, seed=0, frac=0.2, crop_frac=0.5):
