@@ -176,8 +176,8 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t* s_
     return before + inc - x;
 }
 
-// DBITS: the largest digit width a kernel instance handles (8 or 11 bits:
-// 256 or 2048 counters per wave in LDS); `bits` <= DBITS is the pass's width
+// DBITS: the largest digit width a kernel instance handles (8 or 9 bits:
+// 256 or 512 counters per wave in LDS); `bits` <= DBITS is the pass's width
 template <int SRC, int DBITS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortIO io, int shift, int bits,
                                                         uint32_t* __restrict__ hist)
