@@ -345,16 +345,32 @@ def autotune(P, cams, targets, sh_degree, sizes, tiles=(8, 16, 32), steps=5, cac
                     bwd_t.setdefault((order, blk), []).append(_time_ms(lambda: r.raster_bwd(r.d_images), steps))
         fwd_ms = {k: float(np.median(v)) for k, v in fwd_t.items()}
         bwd_ms = {k: float(np.median(v)) for k, v in bwd_t.items()}
-        r.order, r.block = min(fwd_ms, key=fwd_ms.get)
-        r.order_bwd, r.block_bwd = min(bwd_ms, key=bwd_ms.get)
-        r.raster_fwd()
-        r.capture(P, cams, targets, grads, warmup=1)
-        # the first replays include the graph's upload; the step is then timed
-        # over at least 10 replays (tile edges a few percent apart decide here)
+        # isolated launches see other cache states than the captured step: the
+        # two best forward and backward candidates are decided inside it, each
+        # combination captured once and timed in three interleaved rounds of
+        # at least 10 replays (the first replays include the graph's upload)
+        top_f = sorted(fwd_ms, key=fwd_ms.get)[:2]
+        top_b = sorted(bwd_ms, key=bwd_ms.get)[:2]
+        combos = [(f, b) for f in top_f for b in top_b]
+        graphs = []
+        for f, b in combos:
+            (r.order, r.block), (r.order_bwd, r.block_bwd) = f, b
+            r.raster_fwd()
+            graphs.append(r.capture(P, cams, targets, grads, warmup=1))
+            for _ in range(3):
+                r.replay()
+        step_t = [[] for _ in combos]
         for _ in range(3):
-            r.replay()
-        ms = _time_ms(r.replay, max(10, 2 * steps))
+            for i, g in enumerate(graphs):
+                step_t[i].append(_time_ms(g.replay, max(10, 2 * steps)))
+        step_med = [float(np.median(v)) for v in step_t]
+        i_best = int(np.argmin(step_med))
+        (r.order, r.block), (r.order_bwd, r.block_bwd) = combos[i_best]
+        ms = step_med[i_best]
+        del graphs
         trials[f"tile{tile}"] = {"step_ms": ms,
+                                 "in_step_ms": {f"{f[0]}/{f[1][0]}x{f[1][1]}+{b[0]}/{b[1][0]}x{b[1][1]}": v
+                                                for (f, b), v in zip(combos, step_med)},
                                  "fwd_ms": {f"{o}/{b[0]}x{b[1]}": v for (o, b), v in fwd_ms.items()},
                                  "bwd_ms": {f"{o}/{b[0]}x{b[1]}": v for (o, b), v in bwd_ms.items()}}
         if log:
