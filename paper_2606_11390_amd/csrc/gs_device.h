@@ -21,30 +21,12 @@ struct ViewTable {
     long long pix_off[GS_MAX_VIEWS + 1];  // prefix of W*H
 };
 
-// Non-temporal (streaming) stores for outputs that are not re-read from
-// cache: whole-line writes that bypass L2 allocation.
-typedef float gs_nt_f4 __attribute__((ext_vector_type(4)));
-typedef int gs_nt_i2 __attribute__((ext_vector_type(2)));
-typedef int gs_nt_i4 __attribute__((ext_vector_type(4)));
+// Non-temporal (streaming) loads and stores, for whole coalesced lines that
+// no later kernel of the step reads from cache.
 template <class T>
 __device__ __forceinline__ void nt_store(T v, T* p)
 {
     __builtin_nontemporal_store(v, p);
-}
-__device__ __forceinline__ void nt_store(float4 v, float4* p)
-{
-    const gs_nt_f4 x = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(x, reinterpret_cast<gs_nt_f4*>(p));
-}
-__device__ __forceinline__ void nt_store(int2 v, int2* p)
-{
-    const gs_nt_i2 x = {v.x, v.y};
-    __builtin_nontemporal_store(x, reinterpret_cast<gs_nt_i2*>(p));
-}
-__device__ __forceinline__ void nt_store(int4 v, int4* p)
-{
-    const gs_nt_i4 x = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(x, reinterpret_cast<gs_nt_i4*>(p));
 }
 
 template <class T>
