@@ -540,7 +540,8 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
                                                        const uint32_t* __restrict__ cnt,
                                                        const int2* __restrict__ srect, long long N,
                                                        ViewTable vt, uint32_t* __restrict__ keys_out,
-                                                       uint32_t* __restrict__ vals_out)
+                                                       uint32_t* __restrict__ vals_out, int hbits,
+                                                       uint32_t* __restrict__ hist0)
 {
     __shared__ uint32_t s_off[EMIT_SPAN + 1];
     __shared__ uint32_t s_gid[EMIT_SPAN + 1];
@@ -549,9 +550,19 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     __shared__ uint32_t s_tx[EMIT_SPAN + 1];
     __shared__ __align__(16) uint32_t s_src[EMIT_SPAN];   // source of each slot
     __shared__ uint32_t s_wmax[EMIT_THREADS / GS_WAVE];
+    __shared__ uint32_t s_h[1 << RS_MAX_BITS];
     const uint32_t m = cnt[1];
     const uint32_t start = blockIdx.x * (uint32_t)EMIT_SPAN;
-    if (start >= m) return;
+    // with hist0: this workgroup's column of the first tile pass's digit
+    // histogram (that pass then runs one EMIT_SPAN-slot chunk per block, so
+    // block = workgroup)
+    const int nd = hist0 ? 1 << hbits : 0;
+    const size_t nbk = gridDim.x;
+    for (int d = threadIdx.x; d < nd; d += EMIT_THREADS) s_h[d] = 0u;
+    if (start >= m) {
+        for (int d = threadIdx.x; d < nd; d += EMIT_THREADS) hist0[(size_t)d * nbk + blockIdx.x] = 0u;
+        return;
+    }
     const uint32_t end = min(m, start + (uint32_t)EMIT_SPAN);
     const int t = threadIdx.x, lane = __lane_id(), w = t / GS_WAVE;
     // sources of this workgroup's slots: from the one holding its first slot
@@ -617,14 +628,19 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     *reinterpret_cast<uint4*>(&s_src[8 * t]) = a;
     *reinterpret_cast<uint4*>(&s_src[8 * t + 4]) = b;
     __syncthreads();
+    const uint32_t hmask = (uint32_t)nd - 1u;
     for (uint32_t i = start + t; i < end; i += EMIT_THREADS) {
         const uint32_t lo = s_src[i - start];
         const uint32_t j = i - s_off[lo];
         const uint32_t wdt = s_wt[lo];
         const uint32_t row = j / wdt, col = j - row * wdt;
-        keys_out[i] = s_base[lo] + row * s_tx[lo] + col;
+        const uint32_t key = s_base[lo] + row * s_tx[lo] + col;
+        keys_out[i] = key;
         vals_out[i] = s_gid[lo];
+        if (nd) atomicAdd(&s_h[key & hmask], 1u);
     }
+    __syncthreads();
+    for (int d = threadIdx.x; d < nd; d += EMIT_THREADS) hist0[(size_t)d * nbk + blockIdx.x] = s_h[d];
 }
 
 // ---------------------------------------------------------------------------
@@ -689,17 +705,19 @@ int sort_blocks(unsigned long long n_max)
 
 template <int SRC>
 hipError_t radix_pass(const SortIO& io, int nb, int shift, int bits, uint32_t* hist, uint32_t* dtot,
-                      uint32_t* count_out, hipStream_t st)
+                      uint32_t* count_out, hipStream_t st, bool have_hist = false)
 {
     const int sp_threads = min(1024, ((nb + GS_WAVE - 1) / GS_WAVE) * GS_WAVE);
     if (bits <= 8) {
-        hipLaunchKernelGGL((k_rs_hist<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
+        if (!have_hist)
+            hipLaunchKernelGGL((k_rs_hist<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
         hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
         hipLaunchKernelGGL((k_rs_scatter<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
                            dtot, count_out);
     } else {
-        hipLaunchKernelGGL((k_rs_hist<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
-                           hist);
+        if (!have_hist)
+            hipLaunchKernelGGL((k_rs_hist<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
+                               hist);
         hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
         hipLaunchKernelGGL((k_rs_scatter<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
                            hist, dtot, count_out);
@@ -816,8 +834,11 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
     uint32_t *ek = (tpasses % 2 == 0) ? isect_tile : w.tk;
     uint32_t *ev = (tpasses % 2 == 0) ? isect_gid : w.tv;
     const unsigned emit_blocks = (unsigned)((cap + EMIT_SPAN - 1) / EMIT_SPAN);
+    // the emission counts the first tile digit when its workgroups fit the
+    // histogram's block columns
+    const bool fused = emit_blocks <= (unsigned)RS_MAX_BLOCKS;
     hipLaunchKernelGGL(k_emit, dim3(emit_blocks), dim3(EMIT_THREADS), 0, st, pids, w.offs, w.bsrc,
-                       bsrc_last(cap), w.cnt, w.srect, N, vt, ek, ev);
+                       bsrc_last(cap), w.cnt, w.srect, N, vt, ek, ev, tw[0], fused ? w.hist : nullptr);
     const int nb_t = sort_blocks(cap);
     uint32_t *tki = ek, *tvi = ev;
     uint32_t *tko = (ek == isect_tile) ? w.tk : isect_tile, *tvo = (ev == isect_gid) ? w.tv : isect_gid;
@@ -825,7 +846,10 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
         SortIO p{};
         p.keys_in = tki; p.vals_in = tvi; p.keys_out = tko; p.vals_out = tvo;
         p.n_dev = w.cnt + 1;
-        if ((e = radix_pass<SRC_PAIRS>(p, nb_t, shift, tw[pass], w.hist, w.dtot, nullptr, st)) != hipSuccess)
+        // a fused first pass takes the emission's histogram, one block per emission workgroup
+        const bool pre = fused && pass == 0;
+        const int nb = pre ? (int)emit_blocks : nb_t;
+        if ((e = radix_pass<SRC_PAIRS>(p, nb, shift, tw[pass], w.hist, w.dtot, nullptr, st, pre)) != hipSuccess)
             return e;
         uint32_t* tk = tki; tki = tko; tko = tk;
         uint32_t* tv = tvi; tvi = tvo; tvo = tv;

@@ -136,6 +136,19 @@ def test_bin_sort_bit_exact(name, tile):
     np.testing.assert_array_equal(rg, ranges)
 
 
+def test_bin_sort_large_capacity():
+    """A capacity above 4096 emission workgroups of 2048 slots (the first
+    tile pass then counts its own digits)."""
+    s = scene("multi")
+    _, projs, arrs, keys, vals, ranges, offs = oracle_stage("multi", 16)
+    M = len(keys)
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, 16, 4096 * 2048 + 12345)
+    assert info[1] == M and info[2] == 0
+    np.testing.assert_array_equal(it[:M], (keys >> np.uint64(32)).astype(np.int32))
+    np.testing.assert_array_equal(ig[:M], vals)
+    np.testing.assert_array_equal(rg, ranges)
+
+
 def test_bin_sort_depth_ties_keep_gaussian_order():
     s = scene("multi")
     tile = 16
