@@ -12,7 +12,8 @@
 //   1. depth passes (4 x 8 bits) over the visible (view, Gaussian) pairs
 //      (those with a non-empty tile rectangle), the first pass compacting
 //      them out of the projection outputs;
-//   2. the pairs' tile rectangles gathered into that order (the only random
+//   2. the pairs' tile rectangles gathered into that order (by the last
+//      depth pass, beside the pair indices it scatters: the only random
 //      access of the binning after the sort) and an exclusive scan of their
 //      tile counts;
 //   3. load-balanced emission of (global tile id, Gaussian) pairs, each
@@ -52,6 +53,7 @@ struct SortIO {
     float org[3], inv_cell[3];
     uint32_t* keys_out;
     uint32_t* vals_out;
+    int2* rects_out;           // gathering scatter: rects[value] at each output position
     uint32_t n_const;          // element count when n_dev is NULL
     const uint32_t* n_dev;     // device element count
 };
@@ -269,7 +271,10 @@ __device__ __forceinline__ uint32_t block_excl_scan_digits(uint32_t (&x)[DPT], u
     return total;
 }
 
-template <int SRC, int DBITS>
+// GATHER: the values are pair indices; each one's tile rectangle is read
+// with it and written beside it (io.rects -> io.rects_out), so that the scan
+// after the sort reads rectangles in order instead of gathering them
+template <int SRC, int DBITS, bool GATHER = false>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift, int bits,
                                                            const uint32_t* __restrict__ excl,
                                                            const uint32_t* __restrict__ dtot,
@@ -284,6 +289,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
     __shared__ uint32_t s_tmp[RS_WAVES];
     __shared__ uint32_t s_k[RS_CHUNK];
     __shared__ uint32_t s_v[RS_CHUNK];
+    __shared__ int2 s_r[GATHER ? RS_CHUNK : 1];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x, w = t / GS_WAVE, lane = __lane_id();
     const int nd = 1 << bits;
     const uint32_t mask = (1u << bits) - 1u;
@@ -311,6 +317,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
         for (int i = t; i < RS_WAVES * nd; i += RS_THREADS) s_wcnt[i >> bits][i & (nd - 1)] = 0;
         __syncthreads();
         uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
+        int2 rct[GATHER ? RS_ITEMS : 1];
         bool ok[RS_ITEMS];
         const uint32_t wb = cb + (uint32_t)w * RS_WAVE_SPAN;
 #pragma unroll
@@ -323,6 +330,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
             const uint32_t before = s_wcnt[w][d];
             rank[r] = before + (uint32_t)__popcll(peers & lt);
             if (ok[r] && (peers & lt) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
+            if (GATHER) rct[r] = ok[r] ? io.rects[val[r]] : make_int2(0, 0);
         }
         __syncthreads();
         // per digit: exclusive prefix across waves, chunk total, chunk digit start
@@ -354,6 +362,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
             const uint32_t pos = s_cex[d] + s_wcnt[w][d] + rank[r];
             s_k[pos] = key[r];
             s_v[pos] = val[r];
+            if (GATHER) s_r[pos] = rct[r];
         }
         __syncthreads();
         for (uint32_t j = t; j < ctot; j += RS_THREADS) {
@@ -362,6 +371,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
             const uint32_t dst = s_base[d] + j - s_cex[d];
             if (io.keys_out) io.keys_out[dst] = k;
             io.vals_out[dst] = s_v[j];
+            if (GATHER) io.rects_out[dst] = s_r[j];
         }
         __syncthreads();
 #pragma unroll
@@ -407,13 +417,11 @@ __device__ __forceinline__ unsigned long long block_excl_scan_256_u64(unsigned l
     return before + inc - x;
 }
 
-// gathers each visible pair's tile rectangle into depth order (the only
-// random access of the scan) and sums their tile counts per block (64-bit:
-// a pair may cover up to 2^32 - 1 tiles)
-__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ pids,
-                                                            const int2* __restrict__ rects,
-                                                            const uint32_t* __restrict__ n_dev,
-                                                            int2* __restrict__ srect,
+// sums the tile counts of the visible pairs' rectangles (in depth order, as
+// the last depth pass wrote them) per block (64-bit: a pair may cover up to
+// 2^32 - 1 tiles)
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ n_dev,
+                                                            const int2* __restrict__ srect,
                                                             unsigned long long* __restrict__ part)
 {
     __shared__ unsigned long long s_tmp[RS_WAVES];
@@ -422,21 +430,14 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __re
     block_span(*n_dev, nb, b, beg, end);
     unsigned long long s = 0;
     for (uint32_t cb = beg; cb < end; cb += SC_THREADS * SC_ITEMS) {
-        uint32_t x[SC_ITEMS];
+        int2 rc[SC_ITEMS];
 #pragma unroll
         for (int r = 0; r < SC_ITEMS; r++) {
             const uint32_t i = cb + (uint32_t)(r * SC_THREADS + t);
-            x[r] = i < end ? pids[i] : 0u;
+            rc[r] = i < end ? srect[i] : make_int2(0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < SC_ITEMS; r++) {
-            const uint32_t i = cb + (uint32_t)(r * SC_THREADS + t);
-            if (i < end) {
-                const int2 rc = rects[x[r]];
-                srect[i] = rc;
-                s += rect_count(rc);
-            }
-        }
+        for (int r = 0; r < SC_ITEMS; r++) s += rect_count(rc[r]);
     }
     unsigned long long tot;
     block_excl_scan_256_u64(s, s_tmp, tot);
@@ -712,15 +713,23 @@ hipError_t radix_pass(const SortIO& io, int nb, int shift, int bits, uint32_t* h
         if (!have_hist)
             hipLaunchKernelGGL((k_rs_hist<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
         hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
-        hipLaunchKernelGGL((k_rs_scatter<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
-                           dtot, count_out);
+        if (SRC == SRC_PAIRS && io.rects_out)
+            hipLaunchKernelGGL((k_rs_scatter<SRC, 8, true>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
+                               hist, dtot, count_out);
+        else
+            hipLaunchKernelGGL((k_rs_scatter<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
+                               dtot, count_out);
     } else {
         if (!have_hist)
             hipLaunchKernelGGL((k_rs_hist<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
                                hist);
         hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
-        hipLaunchKernelGGL((k_rs_scatter<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
-                           hist, dtot, count_out);
+        if (SRC == SRC_PAIRS && io.rects_out)
+            hipLaunchKernelGGL((k_rs_scatter<SRC, RS_MAX_BITS, true>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift,
+                               bits, hist, dtot, count_out);
+        else
+            hipLaunchKernelGGL((k_rs_scatter<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift,
+                               bits, hist, dtot, count_out);
     }
     return hipGetLastError();
 }
@@ -812,6 +821,10 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
         p.keys_in = ki; p.vals_in = vi; p.vals_out = vo;
         p.keys_out = pass + 1 < dpasses ? ko : nullptr;   // only the order of the last pass is used
         p.n_dev = w.cnt + 0;
+        if (pass + 1 == dpasses) {   // the last pass also lays out the rectangles in depth order
+            p.rects = rects;
+            p.rects_out = w.srect;
+        }
         if ((e = radix_pass<SRC_PAIRS>(p, nb_d, shift, dw[pass], w.hist, w.dtot, nullptr, st)) != hipSuccess)
             return e;
         uint32_t* tk = ki; ki = ko; ko = tk;
@@ -820,8 +833,7 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
     const uint32_t* pids = vi;   // visible pairs in (depth, view, Gaussian) order
 
     // 2. scan of tiles_touched in that order
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb_d), dim3(SC_THREADS), 0, st, pids, rects, w.cnt + 0, w.srect,
-                       w.part);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb_d), dim3(SC_THREADS), 0, st, w.cnt + 0, w.srect, w.part);
     hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, st, w.part, nb_d, w.part_ex, (uint32_t)cap,
                        w.cnt, info);
     hipLaunchKernelGGL(k_scan_down, dim3(nb_d), dim3(SC_THREADS), 0, st, w.srect, w.cnt + 0, w.part_ex,
