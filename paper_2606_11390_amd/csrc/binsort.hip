@@ -104,28 +104,31 @@ template <int SRC>
 __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t end, uint32_t& k,
                                         uint32_t& v)
 {
-    if (i >= end) return false;
+    // the loads are unconditional, so that a caller's loads can all be in
+    // flight at once: past the end (end >= 1 in every caller) they read the
+    // last element, which is then reported invalid
+    const bool in = i < end;
+    const uint32_t j = in ? i : end - 1u;
     if (SRC == SRC_PAIRS) {
-        k = io.keys_in[i];
-        v = io.vals_in[i];
-        return true;
+        k = io.keys_in[j];
+        v = io.vals_in[j];
+        return in;
     } else if (SRC == SRC_PROJ) {
-        // both loads are issued before the visibility test: a pair is binned
-        // when its tile rectangle is not empty
-        const int2 rc = io.rects[i];
-        k = __float_as_uint(io.depths[i]);
+        // a pair is binned when its tile rectangle is not empty
+        const int2 rc = io.rects[j];
+        k = __float_as_uint(io.depths[j]);
         v = i;
         const int w = (rc.y & 0xFFFF) - (rc.x & 0xFFFF), h = (int)((uint32_t)rc.y >> 16) - (int)((uint32_t)rc.x >> 16);
-        return w > 0 && h > 0;
+        return in && w > 0 && h > 0;
     } else if (SRC == SRC_MORTON) {
-        k = morton30(io.means, io.n_const, i, io.org, io.inv_cell);
+        k = morton30(io.means, io.n_const, j, io.org, io.inv_cell);
         v = i;
-        return true;
+        return in;
     } else {
         // longest lists first: 255 minus the list length rounded down to four
         // significant bits (a one-pass key; the order only decides which
         // tiles start first)
-        const int2 r = io.ranges[i];
+        const int2 r = io.ranges[j];
         const uint32_t len = (uint32_t)min(max(r.y - r.x, 0), 0xFFFF);
         uint32_t code = len;
         if (len >= 8u) {
@@ -134,7 +137,7 @@ __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t e
         }
         k = 0xFFu - code;
         v = i;
-        return true;
+        return in;
     }
 }
 
@@ -320,17 +323,26 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
         int2 rct[GATHER ? RS_ITEMS : 1];
         bool ok[RS_ITEMS];
         const uint32_t wb = cb + (uint32_t)w * RS_WAVE_SPAN;
+        // all loads of a thread are issued before any is used (and, when
+        // gathering, all rectangle reads before the ranking)
 #pragma unroll
         for (int r = 0; r < RS_ITEMS; r++) {
             key[r] = 0;
             val[r] = 0;
             ok[r] = load_kv<SRC>(io, wb + (uint32_t)(r * GS_WAVE + lane), end, key[r], val[r]);
+        }
+        if (GATHER) {
+            // every value is a pair index, also past the end (see load_kv)
+#pragma unroll
+            for (int r = 0; r < RS_ITEMS; r++) rct[r] = io.rects[val[r]];
+        }
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
             const uint32_t d = (key[r] >> shift) & mask;
             const uint64_t peers = match_digit(d, ok[r], bits);
             const uint32_t before = s_wcnt[w][d];
             rank[r] = before + (uint32_t)__popcll(peers & lt);
             if (ok[r] && (peers & lt) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
-            if (GATHER) rct[r] = ok[r] ? io.rects[val[r]] : make_int2(0, 0);
         }
         __syncthreads();
         // per digit: exclusive prefix across waves, chunk total, chunk digit start
