@@ -518,9 +518,13 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const int2* __restrict
         uint32_t x[SC_ITEMS];
         unsigned long long s = 0;
         const uint32_t i0 = cb + (uint32_t)t * SC_ITEMS;
+        // unconditional loads (clamped to the last element), all in flight at once
+        int2 rc[SC_ITEMS];
+#pragma unroll
+        for (int r = 0; r < SC_ITEMS; r++) rc[r] = srect[min(i0 + (uint32_t)r, end - 1u)];
 #pragma unroll
         for (int r = 0; r < SC_ITEMS; r++) {
-            x[r] = i0 + r < end ? rect_count(srect[i0 + r]) : 0u;
+            x[r] = i0 + r < end ? rect_count(rc[r]) : 0u;
             s += x[r];
         }
         unsigned long long tot;
@@ -593,10 +597,11 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     int2 rc[EMIT_SRC];
 #pragma unroll
     for (int q = 0; q < EMIT_SRC; q++) {
-        const uint32_t k = (uint32_t)(t + q * EMIT_THREADS);
-        pid[q] = k < ns ? pids[s0 + k] : 0u;
-        off[q] = k < ns ? offs[s0 + k] : 0u;
-        rc[q] = k < ns ? srect[s0 + k] : make_int2(0, 0);
+        // unconditional loads (clamped to the last source, ns >= 1), all in flight at once
+        const uint32_t k = min((uint32_t)(t + q * EMIT_THREADS), ns - 1u);
+        pid[q] = pids[s0 + k];
+        off[q] = offs[s0 + k];
+        rc[q] = srect[s0 + k];
     }
     for (int i = t; i < EMIT_SPAN; i += EMIT_THREADS) s_src[i] = 0u;
     __syncthreads();
