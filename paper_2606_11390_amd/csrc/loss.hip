@@ -10,7 +10,11 @@ namespace gs {
 namespace {
 
 constexpr int L_THREADS = 256;
+typedef float lf4 __attribute__((ext_vector_type(4)));
 
+// VEC: the three arrays are 16-byte aligned; four elements per thread and
+// step as one 16-byte load or store, the last n mod 4 by the first threads
+template <bool VEC>
 __global__ __launch_bounds__(L_THREADS) void k_l2_partial(const float* __restrict__ img,
                                                           const float* __restrict__ tgt,
                                                           long long n, float scale,
@@ -19,11 +23,33 @@ __global__ __launch_bounds__(L_THREADS) void k_l2_partial(const float* __restric
 {
     __shared__ double s_w[L_THREADS / GS_WAVE];
     const long long stride = (long long)gridDim.x * L_THREADS;
+    const long long first = (long long)blockIdx.x * L_THREADS + threadIdx.x;
     float acc = 0.0f;
-    for (long long i = (long long)blockIdx.x * L_THREADS + threadIdx.x; i < n; i += stride) {
-        const float d = img[i] - tgt[i];
-        nt_store(scale * d, &dimg[i]);
-        acc = __builtin_fmaf(d, d, acc);
+    if (VEC) {
+        const long long n4 = n / 4;
+        const lf4* __restrict__ a4 = reinterpret_cast<const lf4*>(img);
+        const lf4* __restrict__ b4 = reinterpret_cast<const lf4*>(tgt);
+        lf4* __restrict__ g4 = reinterpret_cast<lf4*>(dimg);
+        for (long long i = first; i < n4; i += stride) {
+            const lf4 d = a4[i] - b4[i];
+            __builtin_nontemporal_store(scale * d, &g4[i]);
+            acc = __builtin_fmaf(d.x, d.x, acc);
+            acc = __builtin_fmaf(d.y, d.y, acc);
+            acc = __builtin_fmaf(d.z, d.z, acc);
+            acc = __builtin_fmaf(d.w, d.w, acc);
+        }
+        if (first < n - 4 * n4) {
+            const long long i = 4 * n4 + first;
+            const float d = img[i] - tgt[i];
+            dimg[i] = scale * d;
+            acc = __builtin_fmaf(d, d, acc);
+        }
+    } else {
+        for (long long i = first; i < n; i += stride) {
+            const float d = img[i] - tgt[i];
+            nt_store(scale * d, &dimg[i]);
+            acc = __builtin_fmaf(d, d, acc);
+        }
     }
     const float ws = wave_sum(acc);
     if (__lane_id() == 0) s_w[threadIdx.x / GS_WAVE] = (double)ws;
@@ -66,8 +92,15 @@ hipError_t launch_loss_l2(const float* img, const float* tgt, long long n, float
                           void* ws, hipStream_t st)
 {
     const int nb = loss_blocks(n);
-    hipLaunchKernelGGL(k_l2_partial, dim3(nb), dim3(L_THREADS), 0, st, img, tgt, n,
-                       n > 0 ? (float)(2.0 / (double)n) : 0.0f, dimg, (double*)ws);
+    const float scale = n > 0 ? (float)(2.0 / (double)n) : 0.0f;
+    const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |
+                       reinterpret_cast<uintptr_t>(dimg)) & 15u) == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_l2_partial<true>, dim3(nb), dim3(L_THREADS), 0, st, img, tgt, n, scale, dimg,
+                           (double*)ws);
+    else
+        hipLaunchKernelGGL(k_l2_partial<false>, dim3(nb), dim3(L_THREADS), 0, st, img, tgt, n, scale, dimg,
+                           (double*)ws);
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(L_THREADS), 0, st, (const double*)ws, nb,
                        n > 0 ? 1.0 / (double)n : 0.0, loss);
     return hipGetLastError();

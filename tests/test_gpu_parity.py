@@ -401,7 +401,10 @@ def test_project_bwd_parity(name):
     assert max(errs.values()) <= GRAD_TOL
 
 
-def test_loss_parity():
+@pytest.mark.parametrize("offset", [0, 1])
+def test_loss_parity(offset):
+    """16-byte aligned buffers (vector path, n not a multiple of 4) and
+    buffers one element off alignment (element path)."""
     import torch
     from paper_2606_11390_amd import binding as B
     rng = np.random.default_rng(4)
@@ -409,12 +412,16 @@ def test_loss_parity():
     img = rng.uniform(0, 1, n).astype(np.float32)
     tgt = rng.uniform(0, 1, n).astype(np.float32)
     loss = torch.zeros(1, device="cuda")
-    d = torch.zeros(n, device="cuda")
+    di = torch.zeros(n + offset, device="cuda")[offset:]
     ws = torch.empty(B.loss_workspace_size(n), dtype=torch.uint8, device="cuda")
-    B.loss_l2(G.dev(img), G.dev(tgt), loss, d, ws)
+    ti = torch.zeros(n + offset, device="cuda")[offset:]
+    tt = torch.zeros(n + offset, device="cuda")[offset:]
+    ti.copy_(G.dev(img))
+    tt.copy_(G.dev(tgt))
+    B.loss_l2(ti, tt, loss, di, ws)
     L, (dref,) = oracle.l2_loss([img], [tgt])
     assert G.host(loss)[0] == pytest.approx(L, rel=1e-6)
-    assert G.rel_max(G.host(d), dref) <= 1e-6
+    assert G.rel_max(G.host(di), dref) <= 1e-6
 
 
 @pytest.mark.parametrize("lam", [0.2, 1.0])
