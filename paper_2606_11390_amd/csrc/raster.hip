@@ -16,9 +16,11 @@
 // its alpha >= 1/255 region; every lane tests its own entry against the
 // wave's block and a ballot leaves the entries that can touch it, which
 // cannot change any result since every pixel outside the box would have
-// skipped the entry anyway.  The wave then composites the surviving entries
-// in list order, broadcasting each record from its lane (readlane) so that
-// the per-pixel arithmetic takes it as uniform operands.  Waves of a tile
+// skipped the entry anyway.  The batch is copied to a wave-private LDS stage
+// and the wave composites the surviving entries in list order, reading each
+// record back with broadcast LDS loads (two fields by readlane in the
+// forward) so that the per-pixel arithmetic takes it as uniform operands
+// without spending vector issue slots on readlanes.  Waves of a tile
 // never synchronise; each stops as soon as all of its pixels have terminated
 // (ballot).  The backward walks the same list from the back in the same
 // batches, recovers T before each entry by dividing by (1 - alpha), and
@@ -188,10 +190,14 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                              !misses(__float_as_int(cur.c.w), U.by0, by1) &&
                              block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
-            // the previous batch's reads of the stage precede this write in
-            // the wave's program order, and LDS serves one wave in order
+            // lanes read each other's stage slots: the wave barriers order
+            // the previous batch's reads before these writes and the writes
+            // before this batch's reads (they emit no instruction; LDS
+            // operations of one wave complete in issue order)
+            __builtin_amdgcn_wave_barrier();
             cst->a[lane] = cur.a;
             cst->col[lane] = make_float4(cur.b.z, cur.b.w, cur.c.x, 0.0f);
+            __builtin_amdgcn_wave_barrier();
             while (mask) {
                 uint64_t any_live = 0;
 #pragma unroll
@@ -324,11 +330,12 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                              !misses(__float_as_int(cur.c.w), U.by0, by1) &&
                              block_may_take(cur, U.bx0, bx1, U.by0, by1);
             unsigned long long mask = __ballot(hit);
-            // the previous batch's reads of the stage precede these writes in
-            // the wave's program order, and LDS serves one wave in order
+            // cross-lane stage exchange, ordered by wave barriers as in the forward
+            __builtin_amdgcn_wave_barrier();
             stage->rec[0][lane] = cur.a;
             stage->rec[1][lane] = cur.b;
             stage->rec[2][lane] = make_float4(cur.c.x, cur.c.y, __int_as_float(g_cur), 0.0f);
+            __builtin_amdgcn_wave_barrier();
             while (mask) {
                 const int j = __builtin_ctzll(mask);
                 mask &= mask - 1;
