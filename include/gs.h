@@ -341,6 +341,24 @@ int gs_loss_l2(const float* images, const float* targets, int64_t n_elems, float
                float* d_images, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * gs_loss_l2_noalloc - gs_loss_l2 without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments,
+ * results and determinism as gs_loss_l2, for any n_elems >= 0: the partial
+ * sums (at most GS_LOSS_NOALLOC_PARTIALS doubles, 16 KiB) live in a device
+ * array inside the library, one copy per GPU, held until the process ends;
+ * the first call on a device looks up that copy's address.  The call never
+ * allocates or frees memory.  It runs on the current device (the stream
+ * must belong to it).  Calls that overlap in time on one GPU (several
+ * streams or threads) share the array and race: serialise them.  Returns
+ * GS_ERR_ARG for a negative n_elems or a null pointer, GS_ERR_HIP if the
+ * array's address cannot be obtained or the launch fails.
+ */
+#define GS_LOSS_NOALLOC_PARTIALS 2048
+int gs_loss_l2_noalloc(const float* images, const float* targets, int64_t n_elems, float* loss,
+                       float* d_images, void* stream);
+
+/*
  * gs_adam - fused Adam update of up to GS_ADAM_MAX_TENSORS parameter tensors
  * (paper Section 3.2: the backend's fused Adam; the rule is Kingma and Ba
  * 2015 with bias correction, as torch.optim.Adam without weight decay):

@@ -59,6 +59,7 @@ _SIGS = {
     "gs_loss_ssim_l1": (_int, [_p, _p, _int, _p, _f, _p, _p, _p, _sz, _p]),
     "gs_loss_workspace_size": (_sz, [_i64]),
     "gs_loss_l2": (_int, [_p, _p, _i64, _p, _p, _p, _sz, _p]),
+    "gs_loss_l2_noalloc": (_int, [_p, _p, _i64, _p, _p, _p]),
 }
 
 
@@ -229,6 +230,14 @@ def loss_l2(images, targets, loss, d_images, workspace):
                           _ptr(loss, F32, "loss"), _ptr(d_images, F32, "d_images"),
                           _ptr(workspace, U8, "workspace"), workspace.numel(), _stream())
     _check(rc, "gs_loss_l2")
+
+
+def loss_l2_noalloc(images, targets, loss, d_images):
+    """gs_loss_l2 with the library's own per-GPU partial-sum array (no
+    workspace; allocates nothing)."""
+    rc = lib().gs_loss_l2_noalloc(_ptr(images, F32, "images"), _ptr(targets, F32, "targets"), images.numel(),
+                                  _ptr(loss, F32, "loss"), _ptr(d_images, F32, "d_images"), _stream())
+    _check(rc, "gs_loss_l2_noalloc")
 
 
 def raster_visits(splats, isect_gid, tile_ranges, n, sizes, tile, images, T_final, n_contrib, visits):

@@ -51,6 +51,8 @@ hipError_t launch_adam(int n_tensors, float* const* params, const float* const* 
                        float beta2, float eps, int* step_dev, hipStream_t st);
 hipError_t launch_loss_l2(const float* img, const float* tgt, long long n, float* loss, float* dimg,
                           void* ws, hipStream_t st);
+hipError_t launch_loss_l2_noalloc(const float* img, const float* tgt, long long n, float* loss, float* dimg,
+                                  hipStream_t st);
 }  // namespace gs
 
 namespace {
@@ -281,6 +283,14 @@ int gs_loss_l2(const float* images, const float* targets, int64_t n_elems, float
     if (n_elems > 0 && (!images || !targets || !d_images)) return GS_ERR_ARG;
     if (workspace_bytes < gs::loss_workspace_size(n_elems)) return GS_ERR_WORKSPACE;
     return status(gs::launch_loss_l2(images, targets, n_elems, loss, d_images, workspace, as_stream(stream)));
+}
+
+int gs_loss_l2_noalloc(const float* images, const float* targets, int64_t n_elems, float* loss, float* d_images,
+                       void* stream)
+{
+    if (n_elems < 0 || !loss) return GS_ERR_ARG;
+    if (n_elems > 0 && (!images || !targets || !d_images)) return GS_ERR_ARG;
+    return status(gs::launch_loss_l2_noalloc(images, targets, n_elems, loss, d_images, as_stream(stream)));
 }
 
 int gs_adam(int n_tensors, float* const* params, const float* const* grads, float* const* exp_avg,

@@ -4,6 +4,8 @@
 // evaluated per camera.  loss = mean((img - target)^2) over every packed image
 // element; d_img = 2 (img - target) / n.  The sum is reduced in a fixed order
 // (per-block partials in double, then one block) so the loss is deterministic.
+#include <mutex>
+
 #include "gs_device.h"
 
 namespace gs {
@@ -76,12 +78,48 @@ __global__ __launch_bounds__(L_THREADS) void k_l2_final(const double* __restrict
     if (threadIdx.x == 0) loss[0] = (float)(s[0] * inv_n);
 }
 
+constexpr int L_MAX_BLOCKS = 2048;
+
 int loss_blocks(long long n)
 {
     long long nb = (n + L_THREADS * 16 - 1) / (L_THREADS * 16);
     if (nb < 1) nb = 1;
-    if (nb > 2048) nb = 2048;
+    if (nb > L_MAX_BLOCKS) nb = L_MAX_BLOCKS;
     return (int)nb;
+}
+
+}  // namespace
+
+// Partial sums of the allocation-free entry point: one double per block of
+// k_l2_partial (at most L_MAX_BLOCKS, whatever the element count).  Every GPU
+// the library runs on holds its own copy for the life of the process.
+static __device__ __align__(256) double scratch[L_MAX_BLOCKS];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (the array's name in host code is only a stand-in for the
+// symbol, never an address a kernel may use).
+hipError_t scratch_of_current_device(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -104,6 +142,16 @@ hipError_t launch_loss_l2(const float* img, const float* tgt, long long n, float
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(L_THREADS), 0, st, (const double*)ws, nb,
                        n > 0 ? 1.0 / (double)n : 0.0, loss);
     return hipGetLastError();
+}
+
+hipError_t launch_loss_l2_noalloc(const float* img, const float* tgt, long long n, float* loss, float* dimg,
+                                  hipStream_t st)
+{
+    if (loss_blocks(n) > L_MAX_BLOCKS) return hipErrorInvalidValue;
+    double* ws = nullptr;
+    const hipError_t e = scratch_of_current_device(&ws);
+    if (e != hipSuccess) return e;
+    return launch_loss_l2(img, tgt, n, loss, dimg, ws, st);
 }
 
 }  // namespace gs

@@ -79,6 +79,9 @@ def test_host_side_argument_checks():
     assert L.gs_rasterize_bwd(p, p, p, 10, 1, szp, 16, 8, 4, bg, None, None, p, p, p, None, p, 0, None) == -1
     assert L.gs_project_bwd(p, p, p, p, p, 10, 5, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, None) == -1
     assert L.gs_loss_l2(p, p, 10, p, p, p, 0, None) == -4
+    assert L.gs_loss_l2_noalloc(p, p, -1, p, p, None) == -1
+    assert L.gs_loss_l2_noalloc(p, p, 10, None, p, None) == -1
+    assert L.gs_loss_l2_noalloc(None, p, 10, p, p, None) == -1
     assert L.gs_tile_schedule(p, 0, p, 0, None) == -1
     assert L.gs_tile_order_xcd(100, 0, aligned, 4096, None) == -1
     assert L.gs_tile_order_xcd(100, 8, aligned, 8, None) == -4
