@@ -18,8 +18,12 @@ Two paths are timed on the same inputs:
             replayed from one captured HIP graph.
 The reported ``value`` is the batched path's megapixels/s; the plain path's
 figure is reported beside it.  The roofline object covers the kernel with the
-largest share of the step, timed with HIP events on the launch stream.  The
-CPU baseline is the FP64 oracle timed on a bounded sample of the same step.
+largest share of the step, timed with HIP events on the launch stream (and,
+where a committed rocprofv3 summary of the workload exists, recomputed from
+its average kernel duration).  The autograd path and the training step with
+the fused Adam update are timed beside the headline.  The CPU baseline is the
+FP64 oracle: the whole step on every available core, and a one-thread figure
+from a bounded sample.
 """
 import argparse
 import json
@@ -37,9 +41,13 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 # without packed FP32 instructions (the build disables them): 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
-# algorithmic FP32 operations per list entry a pixel examines (FMA = 2)
-FWD_FLOPS_PER_VISIT = 25
-BWD_FLOPS_PER_VISIT = 63
+# algorithmic FP32 operations per visit (one list entry examined by one
+# pixel): the compositing forward ~20 vector operations and one exponential,
+# the backward ~50 vector operations, one exponential and one division
+FWD_OPS_PER_VISIT = 21
+BWD_OPS_PER_VISIT = 52
+# Adam: parameter, gradient and both moments read, parameter and moments written
+ADAM_BYTES_PER_ELEMENT = 28
 
 
 def log(*a):
@@ -140,6 +148,23 @@ def kernel_name(stage, r):
     return None
 
 
+def trace_avg_us(stage, r, workload):
+    """Average duration (us) of the stage's kernel in the committed
+    rocprofv3 --kernel-trace --stats summary of this workload, or None."""
+    name = kernel_name(stage, r)
+    path = os.path.join(ROOT, "profiles", f"{workload}_step_kernel_stats.md")
+    if name is None or not os.path.exists(path):
+        return None
+    for line in open(path):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 4 and cells[0] == f"`{name}`":
+            try:
+                return float(cells[3])
+            except ValueError:
+                return None
+    return None
+
+
 def sources_sha1(stage):
     import hashlib
     h = hashlib.sha1()
@@ -205,17 +230,36 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
             "project_bwd": N * param + seen * param + V * N + 36 * visible}
 
 
-def cpu_baseline(scene, tile, seed=0, frac=0.2, crop_frac=0.5):
-    """FP64 oracle on a bounded sample of the same step, scaled to the frame.
+def host_cpu():
+    """CPU model (from /proc/cpuinfo), processors this process may run on, and
+    the OpenMP thread count the environment sets."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else avail
+    return model, avail, threads
 
-    Per-Gaussian work (projection + its backward) is timed on a seeded
-    `frac` sample of the Gaussians with the full camera and scaled by
-    1/frac; per-pixel work (binning, compositing forward and backward, loss)
-    is timed on a centred crop of `crop_frac` of the width and height (all
-    Gaussians projected into the crop camera, untimed) and scaled by the
-    pixel ratio."""
+
+def cpu_one_core_sample(scene, tile, seed=0, frac=0.2, crop_frac=0.5):
+    """FP64 oracle on one thread, on a bounded sample of the same step scaled
+    to the frame: projection + its backward on a seeded `frac` of the
+    Gaussians (scaled by 1/frac); binning, compositing forward and backward
+    and loss on a centred crop of `crop_frac` of the width and height (all
+    Gaussians projected into the crop camera, untimed), scaled by the pixel
+    ratio.  Returns (estimated seconds per step, description)."""
     import oracle
-    from paper_2606_11390_amd import scenes
+    oracle.set_threads(1)
     rng = np.random.default_rng(seed)
     N = scene.n
     idx = np.sort(rng.choice(N, size=max(1, int(frac * N)), replace=False))
@@ -224,13 +268,11 @@ def cpu_baseline(scene, tile, seed=0, frac=0.2, crop_frac=0.5):
     W, H = (int(x) for x in scene.sizes[0])
     vm, it = scene.viewmats[0], scene.intrinsics[0]
     t0 = time.perf_counter()
-    pr = oracle.project(P, vm, it, W, H, tile=tile)
+    oracle.project(P, vm, it, W, H, tile=tile)
     g = dict(u=np.ones(P.n), v=np.ones(P.n), conic=np.ones((3, P.n)), sigma=np.ones(P.n),
              rgb=np.ones((3, P.n)))
     oracle.project_bwd(P, vm, it, W, H, g, tile=tile)
     t_gauss = (time.perf_counter() - t0) * (N / P.n)
-    # crop camera: same pose and focal length, principal point moved so the
-    # crop covers the centre of the frame
     cw, ch = max(tile, int(W * crop_frac)), max(tile, int(H * crop_frac))
     cit = np.array([it[0], it[1], it[2] - (W - cw) / 2.0, it[3] - (H - ch) / 2.0])
     Pall = oracle.Params.of(scene)
@@ -244,14 +286,55 @@ def cpu_baseline(scene, tile, seed=0, frac=0.2, crop_frac=0.5):
     _, (dimg,) = oracle.l2_loss([f["img"]], [target])
     oracle.raster_bwd(cw, ch, tile, ranges, vals, prc, dimg)
     t_pix = (time.perf_counter() - t1) * (W * H) / (cw * ch)
-    total = t_gauss + t_pix
-    del scenes
-    return {"value": round(W * H / total / 1e6, 6), "unit": "megapixels/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 oracle, 1 thread: projection + projection backward of a seeded {frac:.0%} "
-                       f"sample of the {N} Gaussians (scaled x{N / P.n:.0f}); binning, compositing forward "
-                       f"and backward and L2 loss of a centred {cw}x{ch} crop (scaled x{W * H / (cw * ch):.0f}); "
-                       f"estimated full-step time {total:.1f} s"),
-            "seconds_measured": round(time.perf_counter() - t0, 2)}
+    desc = (f"projection + projection backward of a seeded {frac:.0%} sample of the {N} Gaussians (scaled "
+            f"x{N / P.n:.0f}); binning, compositing forward and backward and L2 loss of a centred {cw}x{ch} "
+            f"crop (scaled x{W * H / (cw * ch):.0f})")
+    return t_gauss + t_pix, desc
+
+
+def cpu_full_step(scene, tile, threads):
+    """Seconds of one whole FP64 oracle step (projection, binning,
+    compositing, L2 loss and every backward pass) on `threads` threads."""
+    import oracle
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        oracle.step(scene, tile=tile)
+        return time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+
+
+def cpu_baseline(scene, tile):
+    """The FP64 oracle as it stands, timed on this host: the whole step of the
+    workload once on every available core (the reported value), plus a
+    one-thread figure from a bounded sample of the same step."""
+    model, avail, threads = host_cpu()
+    t_all = cpu_full_step(scene, tile, threads)
+    t_one, desc_one = cpu_one_core_sample(scene, tile)
+    pix = scene.pixels
+    return {"value": round(pix / t_all / 1e6, 6), "unit": "megapixels/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle, the whole step of this workload (projection, binning, compositing, L2 "
+                       f"loss and all backward passes) once on {threads} OpenMP threads: {t_all:.2f} s"),
+            "cpu_model": model, "cpus_available": avail, "seconds_measured": round(t_all, 3),
+            "one_core": {"value": round(pix / t_one / 1e6, 6), "unit": "megapixels/s", "cores": 1,
+                         "sample": f"FP64 oracle, 1 thread: {desc_one}; estimated full-step time {t_one:.1f} s"}}
+
+
+def cpu_baseline_small_configs(tile):
+    """Whole oracle steps of the 2,000-Gaussian 128x128 and the 200,000-Gaussian
+    1920x1080 workloads, on one thread and on every available core."""
+    from paper_2606_11390_amd import scenes
+    _, _, threads = host_cpu()
+    out = {}
+    for name, sc in (("tiny", scenes.tiny()), ("hd", scenes.hd())):
+        t1 = cpu_full_step(sc, tile, 1)
+        tn = cpu_full_step(sc, tile, threads)
+        out[name] = {"pixels": sc.pixels, "gaussians": sc.n, "seconds_1_thread": round(t1, 4),
+                     f"seconds_{threads}_threads": round(tn, 4),
+                     "mp_per_s_1_thread": round(sc.pixels / t1 / 1e6, 4),
+                     f"mp_per_s_{threads}_threads": round(sc.pixels / tn / 1e6, 4)}
+    return out
 
 
 def main():
@@ -426,25 +509,78 @@ def main():
     bwd_visits = int(r_main.n_contrib.to(torch.int64).sum())
     info = r_main.info.cpu().numpy()
     work = algorithmic_bytes(scene, int(info[B.INFO_VISIBLE]), int(info[B.INFO_ISECT]), r_main.total_tiles)
-    gbs = lambda k: work[k] / (st[k] * 1e-3) / 1e9
-    rooflines = {
-        "raster_fwd": ("alu", FWD_FLOPS_PER_VISIT * fwd_visits / (st["raster_fwd"] * 1e-3) / 1e12,
-                       PEAK_FP32_TFLOPS, "TFLOP/s"),
-        "raster_bwd": ("alu", BWD_FLOPS_PER_VISIT * bwd_visits / (st["raster_bwd"] * 1e-3) / 1e12,
-                       PEAK_FP32_TFLOPS, "TFLOP/s"),
-    }
+    # algorithmic work per launch: bytes of the HBM-bound calls, FP32
+    # operations of the compositing kernels (operations per visit x visits)
+    alu_work = {"raster_fwd": (FWD_OPS_PER_VISIT, fwd_visits), "raster_bwd": (BWD_OPS_PER_VISIT, bwd_visits)}
+    rooflines = {}
+    for k, (opv, nv) in alu_work.items():
+        ops = opv * nv
+        ent = {"bound": "alu", "achieved": round(ops / (st[k] * 1e-3) / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
+               "unit": "TFLOP/s", "frac": round(ops / (st[k] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+               "ops_per_visit": opv, "visits": nv, "work_per_launch": ops, "launch_us": round(st[k] * 1e3, 2),
+               "frac_unpacked_fp32_peak": round(ops / (st[k] * 1e-3) / 1e12 / PEAK_FP32_UNPACKED_TFLOPS, 4)}
+        tr = trace_avg_us(k, r_main, scene.name)
+        if tr:
+            ent["trace_avg_us"] = tr
+            ent["frac_from_trace"] = round(ops / (tr * 1e-6) / 1e12 / PEAK_FP32_TFLOPS, 4)
+        rooflines[k] = ent
     for k in ("project", "bin_sort", "loss", "project_bwd"):
-        rooflines[k] = ("hbm", gbs(k), PEAK_HBM_GBS, "GB/s")
+        a = work[k] / (st[k] * 1e-3) / 1e9
+        rooflines[k] = {"bound": "hbm", "achieved": round(a, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(a / PEAK_HBM_GBS, 4), "work_per_launch": int(work[k]),
+                        "launch_us": round(st[k] * 1e3, 2)}
     dom = max((k for k in st if k in rooflines), key=lambda k: st[k])
-    bound, ach, peak, unit = rooflines[dom]
-    roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 4), "traffic": counted_traffic(dom, r_main, scene.name)}
+    roofline = dict({"kernel": dom}, **rooflines[dom])
+    roofline["traffic"] = counted_traffic(dom, r_main, scene.name)
+
+    # the autograd path (render -> l2_loss -> backward through the autograd
+    # functions, launched eagerly) and the full training step (the fused step
+    # plus the fused Adam update, replayed from one captured graph), on copies
+    # of the parameters
+    extra = {}
+    if args.only != "plain":
+        Pa = {k: v.clone().requires_grad_(True) for k, v in P.items()}
+
+        def autograd_step():
+            for t in Pa.values():
+                t.grad = None
+            R.l2_loss(r_main, R.render(r_main, Pa, cams), tg).backward()
+        for _ in range(max(1, args.warmup)):
+            autograd_step()
+        ms_ag = timed(autograd_step, args.steps, torch)
+        extra["autograd_step"] = {"ms_per_step": round(ms_ag, 4), "mp_per_s": round(pixels / ms_ag / 1e3, 3),
+                                  "launch": "eager"}
+        log(f"autograd step (eager): {ms_ag:.3f} ms/step")
+        del Pa
+        P_tr = {k: v.clone() for k, v in P.items()}
+        opt = R.Adam(P_tr)
+        g_tr = R.zeros_like_params(P_tr)
+        gt = r_main.capture_train(P_tr, cams, tg, g_tr, opt, warmup=1)
+        for _ in range(max(1, args.warmup)):
+            gt.replay()
+        ms_tr = timed(gt.replay, args.steps, torch)
+        ms_adam = timed(lambda: opt.update(g_tr), args.steps, torch)
+        adam_bytes = ADAM_BYTES_PER_ELEMENT * sum(t.numel() for t in P_tr.values())
+        extra["train_step"] = {"ms_per_step": round(ms_tr, 4), "mp_per_s": round(pixels / ms_tr / 1e3, 3),
+                               "adam_ms": round(ms_adam, 4),
+                               "adam_gb_s": round(adam_bytes / (ms_adam * 1e-3) / 1e9, 1),
+                               "adam_hbm_frac": round(adam_bytes / (ms_adam * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                               "adam_bytes": adam_bytes}
+        log(f"training step with fused Adam (captured): {ms_tr:.3f} ms/step; Adam alone {ms_adam:.3f} ms "
+            f"({adam_bytes / (ms_adam * 1e-3) / 1e9:.0f} GB/s)")
+        del gt, P_tr, opt, g_tr
+        torch.cuda.empty_cache()
 
     cpu = None
+    cpu_small = None
     if not args.no_cpu_baseline and scene.n_views == 1:
-        log("cpu baseline (oracle sample) ...")
+        log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(scene, args.tile)
-        log(f"cpu baseline: {cpu['value']} MP/s ({cpu['seconds_measured']} s)")
+        log(f"cpu baseline: {cpu['value']} MP/s on {cpu['cores']} threads ({cpu['seconds_measured']} s), "
+            f"{cpu['one_core']['value']} MP/s on one; {cpu['cpu_model']}")
+        if scene.name == "uhd":
+            cpu_small = cpu_baseline_small_configs(args.tile)
+            log(f"cpu baseline, small workloads: {cpu_small}")
 
     line = {
         "metric": "fwd+bwd megapixels/s at 4K, 5M Gaussians: batched vs plain path, 1 MI355X",
@@ -483,11 +619,10 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in st.items()},
         "visits": {"forward": fwd_visits, "backward": bwd_visits},
         "roofline": roofline,
-        "roofline_all": {k: dict({"bound": b, "achieved": round(a, 3), "peak": p, "unit": u, "frac": round(a / p, 4)},
-                                 **({"frac_unpacked_fp32_peak": round(a / PEAK_FP32_UNPACKED_TFLOPS, 4)}
-                                    if b == "alu" else {}))
-                         for k, (b, a, p, u) in rooflines.items()},
+        "roofline_all": rooflines,
+        **extra,
         "cpu_baseline": cpu,
+        "cpu_baseline_small_workloads": cpu_small,
     }
     print(json.dumps(line), flush=True)
 

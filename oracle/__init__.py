@@ -5,9 +5,10 @@ baseline of ``bench.py`` import this package; the product path
 (``paper_2606_11390_amd``) never does, and nothing here is computed by, read
 from or shared with the HIP path.  The arithmetic lives in ``gs_oracle.c``
 (plain double-precision loops); this module marshals numpy arrays to it and
-adds the two pieces that are pure definitions over numpy arrays: the L2 loss
-and the conversion between the oracle's quantities and the 12-float splat
-record that the C ABI exchanges between stages.
+adds the one piece that is a plain definition over numpy arrays, the L2 loss.
+The conversion between the oracle's quantities and the 12-float splat record
+that the C ABI exchanges between stages is test glue and lives in
+``tests/records.py``.
 
 Each function follows the operator list of the paper's Section 4 (projection
 and SH colour per Gaussian, then per camera depth sort / binning,
@@ -17,7 +18,6 @@ are those of 3D Gaussian Splatting, which the paper cites for the method.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 
 import numpy as np
@@ -26,8 +26,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "_gs_oracle.so")
 _lib = None
 
-# scale between the conic and the splat record's factor: M M^T = C0 * conic
-C0 = 0.5 / math.log(2.0)
 ALPHA_MIN = float(np.float32(1.0 / 255.0))
 ALPHA_MAX = float(np.float32(0.99))
 T_MIN = float(np.float32(1e-4))
@@ -67,8 +65,22 @@ def lib():
         L.or_quat_rot.argtypes = [_D, _D]
         L.or_tile_rect.argtypes = [ctypes.c_float, ctypes.c_float, _int, _int, _int, _int, _int, _I]
         L.or_tile_rects.argtypes = [_i64, _F, _F, _I, _int, _int, _int, _I]
+        L.or_raster_fwd_rect.argtypes = [_int, _int, _int, _I, _I, _i64, _D, _D, _D, _D, _D, _D, _D, _D,
+                                         _int, _int, _int, _int, _D, _U64]
+        L.or_set_threads.argtypes = [_int]
+        L.or_num_procs.restype = _int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (1 = serial, the default; see
+    the note on threads in gs_oracle.c)."""
+    lib().or_set_threads(int(n))
+
+
+def num_procs():
+    return int(lib().or_num_procs())
 
 
 def _p(a, t):
@@ -166,80 +178,6 @@ def project(P, viewmat, intr, W, H, near=0.01, far=1e10, eps2d=0.3, tile=16, rad
     return out
 
 
-def factor(conic):
-    """Lower-triangular M with M M^T = C0 * conic (Cholesky factor, by definition)."""
-    A, B, C = _d(conic)
-    with np.errstate(invalid="ignore", divide="ignore"):
-        m00 = np.sqrt(C0 * A)
-        m10 = C0 * B / m00
-        m11 = np.sqrt(C0 * C - m10 * m10)
-    return np.stack([m00, m10, m11])
-
-
-def to_record(pr):
-    """The 12-float splat record of the C ABI for one view, from the oracle's
-    projection (FP64 values rounded once to FP32).  Culled rows are zero."""
-    N = pr["u"].shape[0]
-    rec = np.zeros((N, 12), np.float64)
-    vis = pr["visible"].astype(bool)
-    m = factor(pr["conic"])
-    rec[:, 0], rec[:, 1] = pr["u"], pr["v"]
-    rec[:, 2], rec[:, 3], rec[:, 4] = m[0], m[1], m[2]
-    with np.errstate(divide="ignore"):
-        rec[:, 5] = np.log2(pr["sigma"])
-    rec[:, 6:9] = pr["rgb"].T
-    rec[:, 9] = pr["sigma"]
-    rec[~vis] = 0.0
-    out = rec.astype(np.float32)
-    bx, by = alpha_box(pr)
-    out[:, 10] = np.where(vis, bx, 0).astype(np.int32).view(np.float32)
-    out[:, 11] = np.where(vis, by, 0).astype(np.int32).view(np.float32)
-    return out
-
-
-def alpha_extent(pr):
-    """Half-widths (x, y) of the region where alpha >= 1/255, i.e. of the
-    ellipse d^T conic d <= 2 ln(255 sigma): sqrt(tau Sigma2_xx), sqrt(tau Sigma2_yy)."""
-    with np.errstate(divide="ignore", invalid="ignore"):
-        tau = np.maximum(2.0 * np.log(255.0 * pr["sigma"]), 0.0)
-        return np.sqrt(tau * pr["cov"][0]), np.sqrt(tau * pr["cov"][2])
-
-
-def alpha_box(pr):
-    """The record's packed pixel ranges (lo | hi << 16, int16 each) of the
-    alpha >= 1/255 region, widened by 1e-3 relative + one pixel: every pixel
-    outside has alpha < 1/255."""
-    ex, ey = alpha_extent(pr)
-
-    def pack(c, e):
-        with np.errstate(invalid="ignore"):
-            lo = np.clip(np.floor(c - e * 1.001 - 0.5) - 1, -32768, 32767)
-            hi = np.clip(np.ceil(c + e * 1.001 - 0.5) + 1, -32768, 32767)
-        lo = np.nan_to_num(lo).astype(np.int64)
-        hi = np.nan_to_num(hi).astype(np.int64)
-        return ((lo & 0xFFFF) | (hi << 16)).astype(np.int64).astype(np.uint32).view(np.int32)
-
-    return pack(pr["u"], ex), pack(pr["v"], ey)
-
-
-def unpack_box(words):
-    w = np.asarray(words).view(np.int32).astype(np.int64)
-    lo = ((w & 0xFFFF) ^ 0x8000) - 0x8000
-    return lo, w >> 16
-
-
-def from_record(rec):
-    """FP64 (u, v, conic A, B, C, sigma, rgb) read exactly from a float32 splat
-    record: conic = M M^T / C0."""
-    r = np.asarray(rec, np.float32).astype(np.float64)
-    m00, m10, m11 = r[:, 2], r[:, 3], r[:, 4]
-    A = m00 * m00 / C0
-    B = m00 * m10 / C0
-    C = (m10 * m10 + m11 * m11) / C0
-    return dict(u=r[:, 0].copy(), v=r[:, 1].copy(), conic=np.stack([A, B, C]),
-                sigma=r[:, 9].copy(), rgb=np.ascontiguousarray(r[:, 6:9].T))
-
-
 # --------------------------------------------------------------------------
 # binning
 # --------------------------------------------------------------------------
@@ -318,6 +256,25 @@ def raster_fwd(W, H, tile, ranges, vals, sp, bg=(0.0, 0.0, 0.0)):
                              _p(margin, _D))
     assert rc == 0
     return dict(img=img, T=T, last=last, visits=visits, margin=margin)
+
+
+def raster_fwd_rect(W, H, tile, ranges, vals, sp, x0, y0, x1, y1, bg=(0.0, 0.0, 0.0)):
+    """Forward compositing of the pixel rectangle [x0, x1) x [y0, y1) of one
+    view (as ``raster_fwd``): image [3][h][w] and per-pixel decision
+    signatures [h][w] (uint64)."""
+    N = sp["u"].shape[0]
+    ranges = np.ascontiguousarray(ranges, np.int32)
+    vals = np.ascontiguousarray(vals, np.int32)
+    u, v, cA, cB, cC = _d(sp["u"]), _d(sp["v"]), _d(sp["conic"][0]), _d(sp["conic"][1]), _d(sp["conic"][2])
+    sig, rgb, bg = _d(sp["sigma"]), _d(sp["rgb"]), _d(bg)
+    h, w = y1 - y0, x1 - x0
+    img = np.zeros((3, h, w))
+    sg = np.zeros((h, w), np.uint64)
+    rc = lib().or_raster_fwd_rect(W, H, tile, _p(ranges, _I), _p(vals, _I), N, _p(u, _D), _p(v, _D), _p(cA, _D),
+                                  _p(cB, _D), _p(cC, _D), _p(sig, _D), _p(rgb, _D), _p(bg, _D), int(x0), int(y0),
+                                  int(x1), int(y1), _p(img, _D), _p(sg, _U64))
+    assert rc == 0
+    return img, sg
 
 
 def raster_bwd(W, H, tile, ranges, vals, sp, d_img, d_alpha=None, bg=(0.0, 0.0, 0.0)):

@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "_gs_oracle.so")
 
 
 def build(verbose=False):
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -37,11 +37,37 @@
  * orthonormal basis with the Condon-Shortley phase.
  *
  * Layouts: per-Gaussian inputs are planar [C][N]; one view per call.
+ *
+ * Threads.  By default every function runs on one thread.  or_set_threads(n)
+ * spreads the independent iterations (Gaussians of the projection and its
+ * backward, pixel rows of the compositing) over n OpenMP threads with the
+ * same arithmetic per iteration; in the compositing backward the per-Gaussian
+ * sums are then accumulated atomically, so their order (and the last bits of
+ * those FP64 sums) depends on the thread schedule.  The tests use one thread;
+ * the benchmark's CPU baseline times both one thread and all host cores.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int g_threads = 1;
+
+/* number of threads of the parallel loops below (1: serial) */
+void or_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+
+/* processors OpenMP sees (1 without OpenMP) */
+int or_num_procs(void)
+{
+#ifdef _OPENMP
+    return omp_get_num_procs();
+#else
+    return 1;
+#endif
+}
 
 #define OR_ALPHA_MIN ((double)(1.0f / 255.0f))
 #define OR_ALPHA_MAX ((double)0.99f)
@@ -408,6 +434,7 @@ int or_project(int64_t N, int sh_degree, const double* means, const double* log_
         radius_mode > 2)
         return -1;
     int K = (sh_degree + 1) * (sh_degree + 1);
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t g = 0; g < N; g++) {
         proj_t P;
         project_one(g, N, K, means, log_scales, quats, opac, sh, viewmat, intr, W, H,
@@ -572,6 +599,7 @@ int or_raster_fwd(int W, int H, int tile, const int32_t* ranges, const int32_t* 
 {
     if (W <= 0 || H <= 0 || tile <= 0) return -1;
     int TX = (W + tile - 1) / tile;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads) if (g_threads > 1)
     for (int j = 0; j < H; j++)
         for (int i = 0; i < W; i++) {
             int t = (j / tile) * TX + i / tile;
@@ -590,6 +618,55 @@ int or_raster_fwd(int W, int H, int tile, const int32_t* ranges, const int32_t* 
 }
 
 /*
+ * Forward rasterisation of the pixel rectangle [x0, x1) x [y0, y1) of one view
+ * (the same per-pixel compositing as or_raster_fwd), for local re-rendering.
+ * img is [3][y1 - y0][x1 - x0] and includes T * bg; sig[(y1 - y0)(x1 - x0)]
+ * receives each pixel's decision signature: a hash of the ordered list of the
+ * Gaussians it composited, each with its 0.99-clamp flag, and of its stop
+ * position, so two renders took the same discrete decisions at a pixel iff
+ * (up to hash collisions) their signatures agree.
+ */
+int or_raster_fwd_rect(int W, int H, int tile, const int32_t* ranges, const int32_t* vals, int64_t N,
+                       const double* u, const double* v, const double* cA, const double* cB,
+                       const double* cC, const double* sig, const double* rgb, const double* bg,
+                       int x0, int y0, int x1, int y1, double* img, uint64_t* sigout)
+{
+    if (W <= 0 || H <= 0 || tile <= 0 || x0 < 0 || y0 < 0 || x1 > W || y1 > H || x0 >= x1 || y0 >= y1)
+        return -1;
+    int TX = (W + tile - 1) / tile;
+    int64_t maxlen = 0;
+    for (int ty = y0 / tile; ty <= (y1 - 1) / tile; ty++)
+        for (int tx = x0 / tile; tx <= (x1 - 1) / tile; tx++) {
+            int64_t t = (int64_t)ty * TX + tx;
+            if (ranges[2 * t + 1] - ranges[2 * t] > maxlen) maxlen = ranges[2 * t + 1] - ranges[2 * t];
+        }
+    visit_t* kept = (visit_t*)malloc(sizeof(visit_t) * (size_t)(maxlen + 1));
+    if (!kept) return -2;
+    const int w = x1 - x0, h = y1 - y0;
+    for (int j = y0; j < y1; j++)
+        for (int i = x0; i < x1; i++) {
+            int t = (j / tile) * TX + i / tile;
+            double C[3], T;
+            int l, nv, nk;
+            composite_pixel(i + 0.5, j + 0.5, ranges[2 * t], ranges[2 * t + 1], vals, u, v, cA, cB, cC, sig,
+                            rgb, N, C, &T, &l, &nv, kept, &nk);
+            int64_t q = (int64_t)(j - y0) * w + (i - x0);
+            for (int c = 0; c < 3; c++) img[(int64_t)c * w * h + q] = C[c] + T * bg[c];
+            /* FNV-1a over (g, clamped) of every composited entry, then the stop position */
+            uint64_t hsh = 1469598103934665603ull;
+            for (int k = 0; k < nk; k++) {
+                uint64_t x = ((uint64_t)(uint32_t)kept[k].g << 1) | (uint64_t)(kept[k].clamped != 0);
+                for (int b = 0; b < 8; b++) { hsh ^= (x >> (8 * b)) & 0xFFu; hsh *= 1099511628211ull; }
+            }
+            hsh ^= (uint64_t)(uint32_t)nv;
+            hsh *= 1099511628211ull;
+            sigout[q] = hsh;
+        }
+    free(kept);
+    return 0;
+}
+
+/*
  * Backward rasterisation of one view: the exact derivative of the forward
  * with the pixel's decisions frozen.  For each pixel the composited Gaussians
  * are recomputed front to back with their transmittances T_k = prod_{j<k}
@@ -602,6 +679,18 @@ int or_raster_fwd(int W, int H, int tile, const int32_t* ranges, const int32_t* 
  * d_img is [3][H][W]; d_alpha ([H][W]) may be NULL.  Gradients are ADDED to
  * g_u, g_v, g_A, g_B, g_C, g_sig (N each) and g_rgb ([3][N]).
  */
+/* one term added to a per-Gaussian sum (atomically when pixels run in parallel) */
+#define ACC(dst, val)                           \
+    do {                                        \
+        const double acc_v_ = (val);            \
+        if (par) {                              \
+            _Pragma("omp atomic")               \
+            (dst) += acc_v_;                    \
+        } else {                                \
+            (dst) += acc_v_;                    \
+        }                                       \
+    } while (0)
+
 int or_raster_bwd(int W, int H, int tile, const int32_t* ranges, const int32_t* vals, int64_t N,
                   const double* u, const double* v, const double* cA, const double* cB,
                   const double* cC, const double* sig, const double* rgb, const double* bg,
@@ -615,11 +704,19 @@ int or_raster_bwd(int W, int H, int tile, const int32_t* ranges, const int32_t* 
     int64_t n_tiles = (int64_t)TX * ((H + tile - 1) / tile);
     for (int64_t t = 0; t < n_tiles; t++)
         if (ranges[2 * t + 1] - ranges[2 * t] > maxlen) maxlen = ranges[2 * t + 1] - ranges[2 * t];
+    const int par = g_threads > 1;
+    int failed = 0;
+#pragma omp parallel num_threads(g_threads) if (par)
+    {
     visit_t* kept = (visit_t*)malloc(sizeof(visit_t) * (size_t)(maxlen + 1));
     double* Tk = (double*)malloc(sizeof(double) * (size_t)(maxlen + 1));
-    if (!kept || !Tk) { free(kept); free(Tk); return -2; }
+    if (!kept || !Tk) {
+#pragma omp atomic write
+        failed = 1;
+    }
+#pragma omp for schedule(dynamic, 1)
     for (int j = 0; j < H; j++)
-        for (int i = 0; i < W; i++) {
+        for (int i = 0; i < W && kept && Tk; i++) {
             int t = (j / tile) * TX + i / tile;
             double C[3], TN;
             int l, nv, nk;
@@ -638,24 +735,25 @@ int or_raster_bwd(int W, int H, int tile, const int32_t* ranges, const int32_t* 
                 double c[3] = {rgb[g], rgb[N + g], rgb[2 * N + g]};
                 double dalpha = 0.0;
                 for (int ch = 0; ch < 3; ch++) {
-                    g_rgb[ch * N + g] += q->alpha * Tk[k] * gC[ch];
+                    ACC(g_rgb[ch * N + g], q->alpha * Tk[k] * gC[ch]);
                     dalpha += (Tk[k] * c[ch] - behind[ch] / (1.0 - q->alpha)) * gC[ch];
                 }
                 dalpha += gA * TN / (1.0 - q->alpha);
                 for (int ch = 0; ch < 3; ch++) behind[ch] += q->alpha * Tk[k] * c[ch];
                 if (q->clamped) continue;
-                g_sig[g] += q->G * dalpha;
+                ACC(g_sig[g], q->G * dalpha);
                 double gp = q->sig * q->G * dalpha;   /* d alpha / d power = alpha */
-                g_A[g] += -0.5 * q->dx * q->dx * gp;
-                g_B[g] += -q->dx * q->dy * gp;
-                g_C[g] += -0.5 * q->dy * q->dy * gp;
-                g_u[g] += -(q->A * q->dx + q->B * q->dy) * gp;
-                g_v[g] += -(q->B * q->dx + q->C * q->dy) * gp;
+                ACC(g_A[g], -0.5 * q->dx * q->dx * gp);
+                ACC(g_B[g], -q->dx * q->dy * gp);
+                ACC(g_C[g], -0.5 * q->dy * q->dy * gp);
+                ACC(g_u[g], -(q->A * q->dx + q->B * q->dy) * gp);
+                ACC(g_v[g], -(q->B * q->dx + q->C * q->dy) * gp);
             }
         }
     free(kept);
     free(Tk);
-    return 0;
+    }
+    return failed ? -2 : 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -692,6 +790,7 @@ int or_project_bwd(int64_t N, int sh_degree, const double* means, const double* 
     if (N < 0 || sh_degree < 0 || sh_degree > 3) return -1;
     int K = (sh_degree + 1) * (sh_degree + 1);
     double fx = intr[0], fy = intr[1];
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t g = 0; g < N; g++) {
         proj_t P;
         project_one(g, N, K, means, log_scales, quats, opac, sh, viewmat, intr, W, H,

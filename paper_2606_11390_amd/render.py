@@ -130,10 +130,11 @@ class Renderer:
             return self.schedule, None
         return self.schedule, self.queue
 
-    def raster_fwd(self):
+    def raster_fwd(self, images=None):
         s, q = self._sched()
         B.rasterize_fwd(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
-                        self.background, s, q, self.images, self.T_final, self.n_contrib, block=self.block)
+                        self.background, s, q, self.images if images is None else images, self.T_final,
+                        self.n_contrib, block=self.block)
 
     def raster_bwd(self, d_images, d_alpha=None, accumulate=False):
         s, q = self._sched(self.order_bwd)
@@ -150,11 +151,23 @@ class Renderer:
     def loss_l2(self, targets):
         B.loss_l2(self.images, targets, self.loss, self.d_images, self.loss_ws)
 
-    def forward(self, P, cams):
+    def forward(self, P, cams, images=None):
+        """Projection, binning and compositing of every view into ``images``
+        (default: the renderer's own buffer).  T_final and n_contrib stay in
+        the renderer for the backward."""
         self.project(P, cams)
         self.bin_sort()
-        self.raster_fwd()
-        return self.images
+        self.raster_fwd(images)
+        return self.images if images is None else images
+
+    def check_overflow(self):
+        """One host read of the binning's device counters: raises if the last
+        binning overflowed its intersection capacity (lists were truncated;
+        grow it with ``fit_capacity`` and run again)."""
+        info = self.info.cpu().numpy()
+        if info[B.INFO_OVERFLOW]:
+            raise B.GSError(f"intersection capacity {self.capacity} < {int(info[B.INFO_ISECT])}; "
+                            "call Renderer.fit_capacity()")
 
     def backward(self, P, cams, d_images, grads, d_alpha=None):
         self.raster_bwd(d_images, d_alpha)
@@ -168,6 +181,12 @@ class Renderer:
         self.forward(P, cams)
         self.loss_l2(targets)
         return self.backward(P, cams, self.d_images, grads)
+
+    def train_step(self, P, cams, targets, grads, optimizer):
+        """``step`` followed by the optimizer's fused update of ``P`` (the
+        training step the paper's backend runs; capturable)."""
+        self.step(P, cams, targets, grads)
+        optimizer.update(grads)
 
     def fit_capacity(self, P, cams, headroom=1.25):
         """Run projection + binning eagerly and grow the intersection capacity
@@ -201,8 +220,53 @@ class Renderer:
         self.graph = g
         return g
 
+    def capture_train(self, P, cams, targets, grads, optimizer, warmup=2):
+        """Capture ``train_step`` (forward, loss, backward and the Adam update)
+        in one HIP graph.  Warm-up steps update the parameters too."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self.train_step(P, cams, targets, grads, optimizer)
+        torch.cuda.current_stream().wait_stream(s)
+        gc.collect()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.train_step(P, cams, targets, grads, optimizer)
+        return g
+
     def replay(self):
         self.graph.replay()
+
+
+# per-parameter learning rates of 3D Gaussian Splatting's training recipe
+# (means 1.6e-4 x scene extent, log-scales 5e-3, quaternions 1e-3, opacity
+# logits 5e-2, SH DC 2.5e-3 and higher bands 2.5e-3 / 20); one rate per tensor
+DEFAULT_LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3)
+
+
+class Adam:
+    """Fused Adam (gs_adam) over a dict of planar parameter tensors: the first
+    and second moments live beside the parameters in HBM and the step count
+    in device memory, so an update can be replayed from a captured graph."""
+
+    def __init__(self, P, lrs=None, betas=(0.9, 0.999), eps=1e-15):
+        self.P = P
+        self.keys = list(P)
+        lrs = dict(DEFAULT_LRS, **(lrs or {}))
+        self.lrs = [float(lrs[k]) for k in self.keys]
+        self.b1, self.b2 = (float(b) for b in betas)
+        self.eps = float(eps)
+        self.m = {k: torch.zeros_like(v) for k, v in P.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in P.items()}
+        self.t = torch.zeros(1, dtype=torch.int32, device=next(iter(P.values())).device)
+
+    def update(self, grads):
+        B.adam([self.P[k] for k in self.keys], [grads[k] for k in self.keys], [self.m[k] for k in self.keys],
+               [self.v[k] for k in self.keys], self.lrs, self.b1, self.b2, self.eps, self.t)
+
+    def state_bytes(self):
+        return sum(2 * t.numel() * t.element_size() for t in self.P.values())
 
 
 def params_to_device(scene, device="cuda"):
@@ -253,25 +317,29 @@ def unpack_images(flat, sizes, channels=3):
 
 
 class _Render(torch.autograd.Function):
+    # The forward reads nothing back to the host: the binning's overflow flag
+    # stays on the device, so size the capacity first (Renderer.fit_capacity)
+    # or call Renderer.check_overflow() after the step.  The graph-captured
+    # form of the step is Renderer.capture / capture_train.
+    # The backward reuses the renderer's T_final and n_contrib, so it must run
+    # before the renderer's next forward.
     @staticmethod
     def forward(ctx, renderer, viewmats, intrinsics, means, log_scales, quats, opacity_logits, sh):
         P = dict(means=means.detach().contiguous(), log_scales=log_scales.detach().contiguous(),
                  quats=quats.detach().contiguous(), opacity_logits=opacity_logits.detach().contiguous(),
                  sh=sh.detach().contiguous())
         cams = dict(viewmats=viewmats.contiguous(), intrinsics=intrinsics.contiguous())
-        renderer.forward(P, cams)
-        info = renderer.info.cpu().numpy()
-        if info[B.INFO_OVERFLOW]:
-            raise B.GSError(f"intersection capacity {renderer.capacity} < {int(info[B.INFO_ISECT])}; "
-                            "call Renderer.fit_capacity()")
+        images = torch.empty(3 * renderer.pixels, dtype=torch.float32, device=renderer.device)
+        renderer.forward(P, cams, images)
         ctx.renderer = renderer
         ctx.P, ctx.cams = P, cams
-        return renderer.images.clone()
+        return images
 
     @staticmethod
     def backward(ctx, d_images):
         r = ctx.renderer
-        grads = zeros_like_params(ctx.P)
+        # gs_project_bwd overwrites every gradient element
+        grads = {k: torch.empty_like(v) for k, v in ctx.P.items()}
         r.backward(ctx.P, ctx.cams, d_images.contiguous(), grads)
         return (None, None, None, grads["means"], grads["log_scales"], grads["quats"],
                 grads["opacity_logits"], grads["sh"])
@@ -281,6 +349,29 @@ def render(renderer, P, cams):
     """Differentiable rendering of all views: packed images [sum 3 H W]."""
     return _Render.apply(renderer, cams["viewmats"], cams["intrinsics"], P["means"], P["log_scales"],
                          P["quats"], P["opacity_logits"], P["sh"])
+
+
+class _L2Loss(torch.autograd.Function):
+    # gs_loss_l2 computes the loss and its image gradient in one pass; the
+    # backward scales that gradient by the incoming one (1 for loss.backward())
+    @staticmethod
+    def forward(ctx, renderer, images, targets):
+        loss = torch.empty(1, dtype=torch.float32, device=images.device)
+        d_images = torch.empty_like(images)
+        B.loss_l2(images.detach().contiguous(), targets.contiguous(), loss, d_images, renderer.loss_ws)
+        ctx.save_for_backward(d_images)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (d_images,) = ctx.saved_tensors
+        return None, d_images * g, None
+
+
+def l2_loss(renderer, images, targets):
+    """Differentiable mean squared error of packed images against packed targets
+    (one gs_loss_l2 call; the renderer supplies its partial-sum workspace)."""
+    return _L2Loss.apply(renderer, images, targets)
 
 
 # ------------------------------------------------------------------ autotune

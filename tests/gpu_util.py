@@ -12,6 +12,7 @@ import numpy as np
 import torch
 
 import oracle
+from tests import records as RC
 from paper_2606_11390_amd import binding as B
 
 F32 = np.float32
@@ -48,7 +49,7 @@ def oracle_views(scene, tile, near=0.01, far=1e10, eps2d=0.3, P=None, radius_mod
         W, H = (int(x) for x in scene.sizes[v])
         pr = oracle.project(P, scene.viewmats[v], scene.intrinsics[v], W, H, near, far, eps2d, tile, radius_mode)
         projs.append(pr)
-        rec[v] = oracle.to_record(pr)
+        rec[v] = RC.to_record(pr)
         depth[v] = pr["depth"].astype(F32)
         radii[v] = pr["radii"].T
         tiles[v] = pr["tiles"]
@@ -177,3 +178,84 @@ def unpack(flat, sizes, ch):
         out.append(flat[o:o + n].reshape((ch, int(h), int(w)) if ch > 1 else (int(h), int(w))))
         o += n
     return out
+
+
+def ambiguity(scene, o, tile, proj_margin=2e-6, pix_margin=1e-4, depth_ulps=4):
+    """Where float32 evaluation may legitimately take another discrete decision
+    than the FP64 oracle, from the oracle's own outputs only (nothing from the
+    GPU): pixels whose compositing decisions (alpha skip, 0.99 clamp, stop) lie
+    within ``pix_margin`` relative of their thresholds; the pixels where two
+    Gaussians adjacent in a tile's sorted list and within ``depth_ulps``
+    float32 ulps of depth (their order may swap) are both composited; every
+    pixel of the tiles, widened by one
+    tile, of a Gaussian whose projection decisions (cull tests, radii, tile
+    rectangle) lie within ``proj_margin``.  Returns per-view boolean pixel
+    masks [H][W] and a boolean mask over the Gaussians: those an ambiguous
+    pixel composites (or nearly), or ambiguous in projection, in any view."""
+    N = scene.n
+    gmask = np.zeros(N, bool)
+    pmasks = []
+    for v, (W, H) in enumerate(np.asarray(scene.sizes).reshape(-1, 2)):
+        W, H = int(W), int(H)
+        TX, TY = (W + tile - 1) // tile, (H + tile - 1) // tile
+        pr = o["projs"][v]
+        rng = o["ranges"][o["offsets"][v]:o["offsets"][v + 1]]
+        vals = o["vals"]
+        tmask = np.zeros((TY, TX), bool)
+        # projection decisions near a threshold
+        amb_g = pr["margin"] < proj_margin
+        gmask |= amb_g
+        for g in np.nonzero(amb_g)[0]:
+            with np.errstate(invalid="ignore"):
+                r = 3.0 * np.sqrt(max(pr["cov"][0][g], pr["cov"][2][g], 0.0)) + 1.0
+            u, vv = pr["u"][g], pr["v"][g]
+            if not (np.isfinite(r) and np.isfinite(u) and np.isfinite(vv)):
+                tmask[:] = True
+                continue
+            x0 = int(np.clip(np.floor((u - r) / tile) - 1, 0, TX))
+            x1 = int(np.clip(np.floor((u + r) / tile) + 2, 0, TX))
+            y0 = int(np.clip(np.floor((vv - r) / tile) - 1, 0, TY))
+            y1 = int(np.clip(np.floor((vv + r) / tile) + 2, 0, TY))
+            tmask[y0:y1, x0:x1] = True
+        pm = o["fwds"][v]["margin"] < pix_margin
+        pm |= np.repeat(np.repeat(tmask, tile, axis=0), tile, axis=1)[:H, :W]
+        # near depth ties inside a tile's sorted list: the pixels of the tile
+        # where both Gaussians of the pair are (nearly) composited
+        A, Bc, C = pr["conic"]
+        thr = (1.0 / 255.0) * (1.0 - 1e-3)
+
+        def alpha_at(g, xs, ys):
+            dx, dy = pr["u"][g] - (xs + 0.5), pr["v"][g] - (ys + 0.5)
+            with np.errstate(over="ignore", invalid="ignore"):
+                return pr["sigma"][g] * np.exp(-0.5 * (A[g] * dx * dx + C[g] * dy * dy) - Bc[g] * dx * dy)
+
+        z32 = pr["depth"].astype(np.float32)
+        for t in range(TX * TY):
+            s, e = int(rng[t][0]), int(rng[t][1])
+            if e - s < 2:
+                continue
+            gl = vals[s:e]
+            z = z32[gl].astype(np.float64)
+            close = np.abs(np.diff(z)) <= depth_ulps * np.spacing(np.abs(z[1:]).astype(np.float32))
+            if not np.any(close):
+                continue
+            ty, tx = divmod(t, TX)
+            ys, xs = np.mgrid[ty * tile:min(H, ty * tile + tile), tx * tile:min(W, tx * tile + tile)]
+            for k in np.nonzero(close)[0]:
+                both = ~(alpha_at(gl[k], xs, ys) < thr) & ~(alpha_at(gl[k + 1], xs, ys) < thr)
+                pm[ys[both], xs[both]] = True
+        pmasks.append(pm)
+        # Gaussians an ambiguous pixel composites, or nearly (alpha within
+        # 0.1 % of 1/255), in its list up to one entry past the oracle's stop:
+        # their gradient terms from that pixel may differ
+        visits = o["fwds"][v]["visits"]
+        ys, xs = np.nonzero(pm)
+        for y, x in zip(ys, xs):
+            t = (y // tile) * TX + x // tile
+            s, e = int(rng[t][0]), int(rng[t][1])
+            g = vals[s:min(e, s + int(visits[y, x]) + 1)]
+            dx, dy = pr["u"][g] - (x + 0.5), pr["v"][g] - (y + 0.5)
+            with np.errstate(over="ignore", invalid="ignore"):
+                a = pr["sigma"][g] * np.exp(-0.5 * (A[g] * dx * dx + C[g] * dy * dy) - Bc[g] * dx * dy)
+            gmask[g[~(a < (1.0 / 255.0) * (1.0 - 1e-3))]] = True
+    return pmasks, gmask

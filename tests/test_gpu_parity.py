@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import records as RC
 from paper_2606_11390_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -63,7 +64,7 @@ def oracle_fwd(name, tile, bg):
     out = []
     for v in range(s.n_views):
         W, H = (int(x) for x in s.sizes[v])
-        sp = oracle.from_record(arrs["splats"][v])
+        sp = RC.from_record(arrs["splats"][v])
         out.append((sp, oracle.raster_fwd(W, H, tile, ranges[offs[v]:offs[v + 1]], vals, sp, bg)))
     return out
 
@@ -93,7 +94,7 @@ def test_project_parity(name, tile):
         rec = g["splats"][v][m].astype(np.float64)
         full = np.zeros((m.sum(), 12))
         full[:, 0], full[:, 1] = pr["u"][m], pr["v"][m]
-        fac = oracle.factor(pr["conic"])[:, m].T
+        fac = RC.factor(pr["conic"])[:, m].T
         full[:, 2:5] = fac
         with np.errstate(divide="ignore"):
             full[:, 5] = np.log2(pr["sigma"][m])
@@ -112,14 +113,16 @@ def test_project_parity(name, tile):
               f"factor max {e_fac.max() if m.any() else 0:.2e} p99.9 {np.quantile(e_fac, 0.999) if m.any() else 0:.2e} "
               f"rgb {e_rgb:.2e} sigma {e_sig:.2e} log2sigma {e_ls:.2e}")
         # the alpha >= 1/255 box is conservative: it contains the oracle's exact box
-        ex, ey = oracle.alpha_extent(pr)
-        xl, xh = oracle.unpack_box(g["splats"][v][m][:, 10])
-        yl, yh = oracle.unpack_box(g["splats"][v][m][:, 11])
+        ex, ey = RC.alpha_extent(pr)
+        xl, xh = RC.unpack_box(g["splats"][v][m][:, 10])
+        yl, yh = RC.unpack_box(g["splats"][v][m][:, 11])
         assert np.all(xl <= np.ceil(pr["u"][m] - ex[m] - 0.5)) and np.all(xh >= np.floor(pr["u"][m] + ex[m] - 0.5))
         assert np.all(yl <= np.ceil(pr["v"][m] - ey[m] - 0.5)) and np.all(yh >= np.floor(pr["v"][m] + ey[m] - 0.5))
         assert e_uv <= IMG_TOL and e_z <= IMG_TOL and e_rgb <= IMG_TOL
         assert e_sig <= IMG_TOL and e_ls <= IMG_TOL
-        assert (e_fac.max() if m.any() else 0) <= 1e-3
+        # measured <= 2.3e-6 (the 2-D covariance and its determinant are formed
+        # without cancellation, so the factor is good to a few float32 ulps)
+        assert (e_fac.max() if m.any() else 0) <= 1e-5
 
 
 @pytest.mark.parametrize("name,tile", CASES + [("wide", 8)])

@@ -19,7 +19,6 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-EPS32 = 2.0 ** -24
 
 
 def _run_step(s, tile=16, persistent=False, capacity=1 << 16, order=None, order_bwd=None):
@@ -34,36 +33,45 @@ def _run_step(s, tile=16, persistent=False, capacity=1 << 16, order=None, order_
     return r, P, cams, tg, grads
 
 
-def _e2e_tol(s):
-    # pixel coordinates carry ~4 ulp(max(W, H)) of float32 error; the falloff
-    # exponent's sensitivity to the mean is |Q d| <= sqrt(2 q / eps2d) <= 9 px^-1
-    # over the composited support, and colour errors add linearly over at most
-    # a few dozen significant layers: a 1e-5-scale budget per unit ulp.
-    w = float(np.max(s.sizes))
-    return 64 * 4 * EPS32 * w * 9
-
-
 @pytest.mark.parametrize("name", ["tiny", "ragged"])
 def test_end_to_end_against_oracle(name):
+    """The whole GPU step (projection feeding binning, compositing, loss and
+    both backward passes) against the all-FP64 oracle at the target
+    tolerances: images within 1e-5 (max |x - y| / max |y|) and every parameter
+    gradient within 1e-4 (relative L2), outside the set where float32 may
+    legitimately take another discrete decision.  That set comes from the
+    oracle's own decision margins (``gpu_util.ambiguity``); its size is
+    reported and bounded, and its pixels must still lie within one decision
+    flip of the oracle."""
     s = scenes.tiny() if name == "tiny" else scenes.tiny(seed=21, n_gaussians=1500, width=100, height=75,
                                                          focal=90.0)
     G.say(f"[e2e] {name}")
     r, P, cams, tg, grads = _run_step(s)
     o = oracle.step(s)
-    img = G.host(r.images)
-    ref = np.concatenate([i.reshape(-1) for i in o["imgs"]])
-    e_img = G.rel_max(img, ref)
+    pmasks, gmask = G.ambiguity(s, o, 16)
+    W, H = (int(x) for x in s.sizes[0])
+    img = G.host(r.images).reshape(3, H, W)
+    ref = o["imgs"][0]
+    keep = ~pmasks[0]
+    e_img = float(np.max(np.abs(img - ref)[:, keep]) / np.max(np.abs(ref)))
+    e_all = float(np.max(np.abs(img - ref)) / np.max(np.abs(ref)))
     loss = float(G.host(r.loss)[0])
     gn = {k: G.host(v) for k, v in grads.items()}
-    errs = {k: G.rel_l2(gn[k2], o["grads"][k]) for k, k2 in
-            (("means", "means"), ("log_scales", "log_scales"), ("quats", "quats"), ("opac", "opacity_logits"),
-             ("sh", "sh"))}
-    tol = _e2e_tol(s)
-    G.say(f"  image {e_img:.2e} (bound {tol:.1e}), loss {loss:.6f} vs {o['loss']:.6f}, grads " +
-          " ".join(f"{k} {e:.1e}" for k, e in errs.items()))
-    assert e_img <= tol
-    assert loss == pytest.approx(o["loss"], rel=1e-4)
-    assert max(errs.values()) <= 20 * tol
+    pairs = (("means", "means"), ("log_scales", "log_scales"), ("quats", "quats"), ("opac", "opacity_logits"),
+             ("sh", "sh"))
+    errs = {k: G.rel_l2(gn[k2][..., ~gmask], o["grads"][k][..., ~gmask]) for k, k2 in pairs}
+    errs_all = {k: G.rel_l2(gn[k2], o["grads"][k]) for k, k2 in pairs}
+    G.say(f"  ambiguous: {int(pmasks[0].sum())} of {W * H} pixels, {int(gmask.sum())} of {s.n} Gaussians")
+    G.say(f"  image {e_img:.2e} outside them ({e_all:.2e} everywhere), loss {loss:.7f} vs {o['loss']:.7f}")
+    G.say("  grads outside: " + " ".join(f"{k} {e:.1e}" for k, e in errs.items()) +
+          "; everywhere: " + " ".join(f"{k} {e:.1e}" for k, e in errs_all.items()))
+    assert pmasks[0].mean() <= 0.005
+    assert gmask.mean() <= 0.2
+    assert e_img <= 1e-5
+    assert max(errs.values()) <= 1e-4
+    # one decision flip changes a pixel by at most ~sigma alpha |dc|: < 2e-2
+    assert e_all <= 2e-2
+    assert loss == pytest.approx(o["loss"], rel=1e-5)
 
 
 def _multi():
@@ -213,12 +221,68 @@ def test_autograd_matches_fused_step():
         assert G.rel_l2(G.host(Pt[k].grad), G.host(grads[k])) <= 1e-5, k
 
 
+def test_autograd_l2_matches_fused_step():
+    """render -> l2_loss -> backward through the autograd functions (eager)
+    against the fused step."""
+    s = scenes.tiny(seed=10, n_gaussians=3000, width=160, height=96, focal=110.0)
+    G.say("[autograd l2]")
+    r, P, cams, tg, grads = _run_step(s)
+    ref_loss = float(G.host(r.loss)[0])
+    ref = {k: G.host(v).copy() for k, v in grads.items()}
+    Pt = {k: v.clone().requires_grad_(True) for k, v in P.items()}
+    loss = R.l2_loss(r, R.render(r, Pt, cams), tg)
+    loss.backward()
+    assert float(loss.detach()) == pytest.approx(ref_loss, rel=1e-6)
+    for k in ref:
+        assert G.rel_l2(G.host(Pt[k].grad), ref[k]) <= 1e-5, k
+
+
+@pytest.mark.skip(reason="capturing loss.backward() through the autograd functions in a HIP graph ended in a "
+                         "segmentation fault inside torch's capture_end on the GPU box; the cause is not shown, "
+                         "so the captured form of the step stays Renderer.capture / capture_train")
+def test_autograd_graph_capture():
+    pass
+
+
+def test_captured_train_step_matches_eager():
+    """forward, loss, backward and the fused Adam update replayed from one
+    graph (one warm-up step, then two replays) against three eager training
+    steps from the same start: parameters and both Adam moments agree."""
+    s = scenes.blobs(12, 20000, 32, 10.0, [(320, 180, 250.0)], name="hd_small")
+    G.say("[train step graph]")
+    P0, cams = R.params_to_device(s)
+    tg = R.packed_targets(s)
+    r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=16, capacity=1 << 16, order="heavy")
+    r.fit_capacity(P0, cams)
+    PA = {k: v.clone() for k, v in P0.items()}
+    PB = {k: v.clone() for k, v in P0.items()}
+    oa, ob = R.Adam(PA), R.Adam(PB)
+    ga, gb = R.zeros_like_params(PA), R.zeros_like_params(PB)
+    for _ in range(3):
+        r.train_step(PA, cams, tg, ga, oa)
+    g = r.capture_train(PB, cams, tg, gb, ob, warmup=1)
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    assert int(G.host(oa.t)[0]) == 3 and int(G.host(ob.t)[0]) == 3
+    for k in P0:
+        p0 = G.host(P0[k]).astype(np.float64)
+        da, db = G.host(PA[k]) - p0, G.host(PB[k]) - p0
+        assert np.linalg.norm(da) > 0, k
+        # the updates (not the parameters, which barely move) agree
+        assert G.rel_l2(db, da) <= 1e-3, k
+        assert G.rel_l2(G.host(ob.m[k]), G.host(oa.m[k])) <= 1e-4, k
+        assert G.rel_l2(G.host(ob.v[k]), G.host(oa.v[k])) <= 1e-4, k
+
+
 def test_renderer_reports_overflow():
     s = scenes.tiny()
     r = R.Renderer(s.n, s.sh_degree, s.sizes, capacity=100)
     P, cams = R.params_to_device(s)
+    R.render(r, P, cams)
     with pytest.raises(B.GSError):
-        R.render(r, P, cams)
+        r.check_overflow()
     m = r.fit_capacity(P, cams)
     assert r.capacity >= m
     R.render(r, P, cams)
+    r.check_overflow()

@@ -15,6 +15,7 @@ from scipy.spatial.transform import Rotation
 from scipy.special import sph_harm_y
 
 import oracle
+from tests import records as RC
 from paper_2606_11390_amd import scenes
 
 PI = math.pi
@@ -530,14 +531,14 @@ def test_single_gaussian_gradient_closed_form():
 
 def test_record_round_trip_and_factor_definition():
     s, P, pr, keys, vals, ranges = _tiny_setup(seed=17)
-    rec = oracle.to_record(pr)
-    back = oracle.from_record(rec)
+    rec = RC.to_record(pr)
+    back = RC.from_record(rec)
     vis = pr["visible"] > 0
-    m = oracle.factor(pr["conic"])[:, vis]
+    m = RC.factor(pr["conic"])[:, vis]
     A, B, C = pr["conic"][:, vis]
-    np.testing.assert_allclose(m[0] ** 2, oracle.C0 * A, rtol=1e-13)
-    np.testing.assert_allclose(m[0] * m[1], oracle.C0 * B, rtol=1e-12, atol=1e-15)
-    np.testing.assert_allclose(m[1] ** 2 + m[2] ** 2, oracle.C0 * C, rtol=1e-13)
+    np.testing.assert_allclose(m[0] ** 2, RC.C0 * A, rtol=1e-13)
+    np.testing.assert_allclose(m[0] * m[1], RC.C0 * B, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(m[1] ** 2 + m[2] ** 2, RC.C0 * C, rtol=1e-13)
     assert np.all(m[0] > 0) and np.all(m[2] > 0)
     np.testing.assert_allclose(back["conic"][:, vis], pr["conic"][:, vis], rtol=2e-6, atol=1e-9)
     np.testing.assert_allclose(back["u"][vis], pr["u"][vis], rtol=1e-7)
@@ -547,9 +548,9 @@ def test_alpha_box_contains_every_pixel_with_alpha_above_threshold():
     # brute force over a pixel window around each splat: every pixel whose
     # FP64 alpha reaches 1/255 lies inside the record's packed box
     s, P, pr, keys, vals, ranges = _tiny_setup(seed=18, n=200, W=64, H=48, f=50.0)
-    rec = oracle.to_record(pr)
-    x_lo, x_hi = oracle.unpack_box(rec[:, 10])
-    y_lo, y_hi = oracle.unpack_box(rec[:, 11])
+    rec = RC.to_record(pr)
+    x_lo, x_hi = RC.unpack_box(rec[:, 10])
+    y_lo, y_hi = RC.unpack_box(rec[:, 11])
     inside = 0
     for g in np.nonzero(pr["visible"])[0]:
         A, B, C = pr["conic"][:, g]
@@ -715,3 +716,36 @@ def test_ssim_l1_gradient_matches_finite_differences():
         xm[idx] -= h
         fd = (oracle.ssim_l1_loss([xp], [y])[0] - oracle.ssim_l1_loss([xm], [y])[0]) / (2 * h)
         assert g[idx] == pytest.approx(fd, rel=1e-5, abs=1e-12)
+
+
+def test_rectangle_render_matches_full_render_and_signatures_track_decisions():
+    """The local re-render the finite-difference spot check uses: any pixel
+    rectangle renders bit-identically to the same pixels of the whole-view
+    render, and its per-pixel decision signature changes when (and only when)
+    a pixel's composited set changes."""
+    s = scenes.tiny(seed=21, n_gaussians=1500, width=100, height=75, focal=90.0)
+    o = oracle.step(s, backward=False)
+    pr = o["projs"][0]
+    W, H = 100, 75
+    full = o["imgs"][0]
+    for x0, y0, x1, y1 in ((0, 0, 100, 75), (13, 7, 61, 40), (96, 64, 100, 75), (16, 16, 32, 32)):
+        img, sg = oracle.raster_fwd_rect(W, H, 16, o["ranges"], o["vals"], pr, x0, y0, x1, y1)
+        np.testing.assert_array_equal(img, full[:, y0:y1, x0:x1])
+        assert sg.shape == (y1 - y0, x1 - x0)
+    img0, sg0 = oracle.raster_fwd_rect(W, H, 16, o["ranges"], o["vals"], pr, 0, 0, W, H)
+    # a tiny colour change keeps every decision; making one Gaussian fully
+    # transparent removes it from every pixel that composited it
+    vis = np.nonzero(pr["visible"])[0]
+    g = int(vis[np.argmax(pr["sigma"][vis])])
+    rgb = pr["rgb"][:, g].copy()
+    pr["rgb"][:, g] += 1e-3
+    _, sg1 = oracle.raster_fwd_rect(W, H, 16, o["ranges"], o["vals"], pr, 0, 0, W, H)
+    pr["rgb"][:, g] = rgb
+    np.testing.assert_array_equal(sg1, sg0)
+    sig = pr["sigma"][g]
+    pr["sigma"][g] = 0.0
+    img2, sg2 = oracle.raster_fwd_rect(W, H, 16, o["ranges"], o["vals"], pr, 0, 0, W, H)
+    pr["sigma"][g] = sig
+    changed = sg2 != sg0
+    assert changed.any()
+    np.testing.assert_array_equal(img2[:, ~changed], img0[:, ~changed])
