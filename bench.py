@@ -352,6 +352,9 @@ def main():
                     help="JSON file for the autotuner's choice: written on first use, reused after")
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all",
                     help="restrict to one path (for profiler runs)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the headline step (no radius / layout variants, no autograd or training "
+                         "step): short runs under a profiler")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB three times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -468,6 +471,7 @@ def main():
             result["batched_same_tile"].pop("step_ms", None)
             del r16
             torch.cuda.empty_cache()
+    if args.only in ("all", "batched") and not args.main_only:
         # the same step with the opacity-aware screen box: identical images and
         # gradients from fewer intersections (reported beside the headline)
         ro, mo, mso, _ = run_path(tuned, True, radius_mode=B.RADIUS_OPACITY)
@@ -485,6 +489,7 @@ def main():
         P = P_m
         del rg
         torch.cuda.empty_cache()
+    if args.only in ("all", "batched"):
         r_main, m, ms_main, step_main = run_path(tuned, True)
         # per-step spread of the same step (after the timed block)
         per = per_step_ms(step_main, args.steps, torch)
@@ -538,7 +543,7 @@ def main():
     # plus the fused Adam update, replayed from one captured graph), on copies
     # of the parameters
     extra = {}
-    if args.only != "plain":
+    if args.only != "plain" and not args.main_only:
         Pa = {k: v.clone().requires_grad_(True) for k, v in P.items()}
 
         def autograd_step():

@@ -50,7 +50,7 @@ def lib():
             _b.build()
         L = ctypes.CDLL(_LIB_PATH)
         L.or_project.argtypes = [_i64, _int, _D, _D, _D, _D, _D, _D, _D, _int, _int, _dbl, _dbl, _dbl,
-                                 _int, _int, _D, _D, _D, _D, _D, _D, _D, _I, _I, _U8, _U8, _D]
+                                 _int, _int, _D, _D, _D, _D, _D, _D, _D, _I, _I, _U8, _U8, _D, _D]
         L.or_bin_emit.argtypes = [_i64, _F, _F, _F, _I, _int, _int, _int, _i64, _U64, _I, _i64]
         L.or_bin_emit.restype = _i64
         L.or_sort_pairs.argtypes = [_i64, _U64, _I]
@@ -167,13 +167,14 @@ def project(P, viewmat, intr, W, H, near=0.01, far=1e10, eps2d=0.3, tile=16, rad
     out = dict(u=np.zeros(N), v=np.zeros(N), depth=np.zeros(N), cov=np.zeros((3, N)),
                conic=np.zeros((3, N)), sigma=np.zeros(N), rgb=np.zeros((3, N)),
                radii=np.zeros((2, N), np.int32), tiles=np.zeros(N, np.int32),
-               clamp=np.zeros(N, np.uint8), visible=np.zeros(N, np.uint8), margin=np.zeros(N))
+               clamp=np.zeros(N, np.uint8), visible=np.zeros(N, np.uint8), margin=np.zeros(N),
+               margin_img=np.zeros(N))
     rc = lib().or_project(N, P.deg, _p(P.means, _D), _p(P.log_scales, _D), _p(P.quats, _D),
                           _p(P.opac, _D), _p(P.sh, _D), _p(vm, _D), _p(it, _D), int(W), int(H),
                           float(near), float(far), float(eps2d), int(tile), int(radius_mode),
                           *[_p(out[k], _D) for k in ("u", "v", "depth", "cov", "conic", "sigma", "rgb")],
                           _p(out["radii"], _I), _p(out["tiles"], _I), _p(out["clamp"], _U8),
-                          _p(out["visible"], _U8), _p(out["margin"], _D))
+                          _p(out["visible"], _U8), _p(out["margin"], _D), _p(out["margin_img"], _D))
     assert rc == 0
     return out
 

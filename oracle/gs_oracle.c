@@ -254,6 +254,9 @@ typedef struct {
     int tiles;
     int visible;
     double margin;             /* smallest relative distance to a decision boundary */
+    double margin_img;         /* the same over the decisions that can change an image discontinuously
+                                  (visibility, radii, tile rectangle); the Jacobian and colour clamps
+                                  are continuous in value */
     /* quantities reused by the backward */
     double R[9], s[3], qn[4], qnorm, Wr[9], J[6], Sc[9], dirv[3], dnorm, d[3];
     int clx, cly;
@@ -267,6 +270,7 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
 {
     memset(P, 0, sizeof(*P));
     P->margin = INFINITY;
+    P->margin_img = INFINITY;
     double mu[3] = {means[g], means[N + g], means[2 * N + g]};
     double ls[3] = {log_scales[g], log_scales[N + g], log_scales[2 * N + g]};
     double q[4] = {quats[g], quats[N + g], quats[2 * N + g], quats[3 * N + g]};
@@ -288,11 +292,13 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
     P->x = p[0]; P->y = p[1]; P->z = p[2];
     double z = p[2];
     P->margin = fmin(P->margin, rel_margin(z, near_));
+    P->margin_img = fmin(P->margin_img, rel_margin(z, near_));
     if (z <= near_ || z >= far_) return;
 
     /* opacity */
     P->sigma = 1.0 / (1.0 + exp(-o));
     P->margin = fmin(P->margin, rel_margin(P->sigma, OR_ALPHA_MIN));
+    P->margin_img = fmin(P->margin_img, rel_margin(P->sigma, OR_ALPHA_MIN));
     if (P->sigma < OR_ALPHA_MIN) return;
 
     /* 3-D covariance Sigma = R S S^T R^T */
@@ -356,7 +362,9 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
         ex = ey = 3.0 * sqrt(m + sqrt(fmax(m * m - det, 0.1)));
     }
     P->margin = fmin(P->margin, int_margin(ex));
+    P->margin_img = fmin(P->margin_img, int_margin(ex));
     P->margin = fmin(P->margin, int_margin(ey));
+    P->margin_img = fmin(P->margin_img, int_margin(ey));
     P->rx = (int)fmin(ceil(ex), 1073741824.0);   /* radii saturate at 2^30 px */
     P->ry = (int)fmin(ceil(ey), 1073741824.0);
     if (radius_mode == 1) {
@@ -364,7 +372,9 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
         tau = (tau > 0.0 ? tau : 0.0) * 1.001 + 0.01;
         double ax = sqrt(tau * a), ay = sqrt(tau * c);
         P->margin = fmin(P->margin, int_margin(ax));
+        P->margin_img = fmin(P->margin_img, int_margin(ax));
         P->margin = fmin(P->margin, int_margin(ay));
+        P->margin_img = fmin(P->margin_img, int_margin(ay));
         int qx = (int)fmin(ceil(ax), 1073741823.0) + 1, qy = (int)fmin(ceil(ay), 1073741823.0) + 1;
         if (qx < P->rx) P->rx = qx;
         if (qy < P->ry) P->ry = qy;
@@ -385,6 +395,7 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
             double mag = e < 2 ? fabs((double)uf) : fabs((double)vf);
             double d = fabs(edges[e] - nearbyint(edges[e])) * ts;
             P->margin = fmin(P->margin, d / (mag > ts ? mag : ts));
+            P->margin_img = fmin(P->margin_img, d / (mag > ts ? mag : ts));
         }
     }
     int r[4];
@@ -420,7 +431,10 @@ static void project_one(int64_t g, int64_t N, int K, const double* means, const 
  * Forward projection of N Gaussians into one view.  Outputs (N each unless
  * stated): u, v, depth, cov [3][N] (a, b, c of Sigma2), conic [3][N] (A, B, C),
  * sigma, rgb [3][N], radii [2][N], tiles, clamp (bit c = channel c clamped),
- * visible, margin.  Culled Gaussians have visible = 0, radii = 0, tiles = 0.
+ * visible, margin (smallest relative distance of any decision to its
+ * threshold) and, if not NULL, margin_img (the same over the decisions that
+ * can change an image discontinuously: visibility, radii, tile rectangle).
+ * Culled Gaussians have visible = 0, radii = 0, tiles = 0.
  */
 int or_project(int64_t N, int sh_degree, const double* means, const double* log_scales,
                const double* quats, const double* opac, const double* sh,
@@ -428,7 +442,7 @@ int or_project(int64_t N, int sh_degree, const double* means, const double* log_
                double near_, double far_, double eps2d, int tile, int radius_mode,
                double* u, double* v, double* depth, double* cov, double* conic,
                double* sigma, double* rgb, int32_t* radii, int32_t* tiles,
-               uint8_t* clamp, uint8_t* visible, double* margin)
+               uint8_t* clamp, uint8_t* visible, double* margin, double* margin_img)
 {
     if (N < 0 || sh_degree < 0 || sh_degree > 3 || W <= 0 || H <= 0 || tile <= 0 || radius_mode < 0 ||
         radius_mode > 2)
@@ -452,6 +466,7 @@ int or_project(int64_t N, int sh_degree, const double* means, const double* log_
         clamp[g] = (uint8_t)(P.clamp[0] | (P.clamp[1] << 1) | (P.clamp[2] << 2));
         visible[g] = (uint8_t)P.visible;
         margin[g] = P.margin;
+        if (margin_img) margin_img[g] = P.margin_img;
     }
     return 0;
 }

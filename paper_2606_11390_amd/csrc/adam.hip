@@ -34,6 +34,29 @@ __device__ __forceinline__ void adam1(float& p, float g, float& m, float& v, flo
     p -= step * m / (sqrtf(v) * rbc2 + eps);
 }
 
+// chunks a thread handles per loop step (all their loads in flight at once)
+constexpr int ADAM_UNROLL = 4;
+typedef float af4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void adam4(af4& p, af4 g, af4& m, af4& v, float b1, float b2, float step, float rbc2,
+                                      float eps)
+{
+    float pp[4] = {p.x, p.y, p.z, p.w}, mm[4] = {m.x, m.y, m.z, m.w}, vv[4] = {v.x, v.y, v.z, v.w};
+    const float gg[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) adam1(pp[e], gg[e], mm[e], vv[e], b1, b2, step, rbc2, eps);
+    p = af4{pp[0], pp[1], pp[2], pp[3]};
+    m = af4{mm[0], mm[1], mm[2], mm[3]};
+    v = af4{vv[0], vv[1], vv[2], vv[3]};
+}
+
+__device__ __forceinline__ int tensor_of(const AdamList& L, long long c)
+{
+    int k = 0;
+    while (k + 1 < L.count && L.chunk_off[k + 1] <= c) k++;
+    return k;
+}
+
 __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, float eps,
                                               const int* __restrict__ step_dev)
 {
@@ -44,30 +67,51 @@ __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, fl
     // the form keeps full relative precision for b close to 1 (b2 = 0.999)
     const float bc1 = -expm1f(t * log1pf(b1 - 1.0f));
     const float rbc2 = 1.0f / sqrtf(-expm1f(t * log1pf(b2 - 1.0f)));
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
-        int k = 0;
-        while (k + 1 < L.count && L.chunk_off[k + 1] <= c) k++;
-        const long long i = 4 * (c - L.chunk_off[k]);
-        const float step = L.lr[k] / bc1;
-        if (i + 4 <= L.n[k]) {
-            float4 p = *reinterpret_cast<float4*>(L.p[k] + i);
-            const float4 g = *reinterpret_cast<const float4*>(L.g[k] + i);
-            float4 m = *reinterpret_cast<float4*>(L.m[k] + i);
-            float4 v = *reinterpret_cast<float4*>(L.v[k] + i);
-            adam1(p.x, g.x, m.x, v.x, b1, b2, step, rbc2, eps);
-            adam1(p.y, g.y, m.y, v.y, b1, b2, step, rbc2, eps);
-            adam1(p.z, g.z, m.z, v.z, b1, b2, step, rbc2, eps);
-            adam1(p.w, g.w, m.w, v.w, b1, b2, step, rbc2, eps);
-            *reinterpret_cast<float4*>(L.p[k] + i) = p;
-            *reinterpret_cast<float4*>(L.m[k] + i) = m;
-            *reinterpret_cast<float4*>(L.v[k] + i) = v;
-        } else {
-            for (long long e = i; e < L.n[k]; e++) {
-                float p = L.p[k][e], m = L.m[k][e], v = L.v[k][e];
-                adam1(p, L.g[k][e], m, v, b1, b2, step, rbc2, eps);
-                L.p[k][e] = p;
-                L.m[k][e] = m;
-                L.v[k][e] = v;
+    // every element is read and written once per step: streaming
+    // (non-temporal) accesses; ADAM_UNROLL chunks c, c + stride, ... per
+    // thread and step, so that 4 x ADAM_UNROLL 16-byte loads are in flight
+    for (long long c0 = (long long)blockIdx.x * blockDim.x + threadIdx.x; c0 < total;
+         c0 += ADAM_UNROLL * stride) {
+        af4 p[ADAM_UNROLL], g[ADAM_UNROLL], m[ADAM_UNROLL], v[ADAM_UNROLL];
+        int kk[ADAM_UNROLL];
+        long long ii[ADAM_UNROLL];
+        bool full[ADAM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < ADAM_UNROLL; u++) {
+            const long long c = c0 + u * stride;
+            const int k = c < total ? tensor_of(L, c) : 0;
+            const long long i = 4 * (c - L.chunk_off[k]);
+            kk[u] = k;
+            ii[u] = i;
+            full[u] = c < total && i + 4 <= L.n[k];
+            if (full[u]) {
+                p[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.p[k] + i));
+                g[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.g[k] + i));
+                m[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.m[k] + i));
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.v[k] + i));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ADAM_UNROLL; u++) {
+            const long long c = c0 + u * stride;
+            if (c >= total) continue;
+            const int k = kk[u];
+            const long long i = ii[u];
+            const float step = L.lr[k] / bc1;
+            if (full[u]) {
+                adam4(p[u], g[u], m[u], v[u], b1, b2, step, rbc2, eps);
+                __builtin_nontemporal_store(p[u], reinterpret_cast<af4*>(L.p[k] + i));
+                __builtin_nontemporal_store(m[u], reinterpret_cast<af4*>(L.m[k] + i));
+                __builtin_nontemporal_store(v[u], reinterpret_cast<af4*>(L.v[k] + i));
+            } else {
+                // the ragged tail of a tensor, element by element
+                for (long long e = i; e < L.n[k]; e++) {
+                    float pe = L.p[k][e], me = L.m[k][e], ve = L.v[k][e];
+                    adam1(pe, L.g[k][e], me, ve, b1, b2, step, rbc2, eps);
+                    L.p[k][e] = pe;
+                    L.m[k][e] = me;
+                    L.v[k][e] = ve;
+                }
             }
         }
     }

@@ -186,12 +186,13 @@ def ambiguity(scene, o, tile, proj_margin=2e-6, pix_margin=1e-4, depth_ulps=4):
     GPU): pixels whose compositing decisions (alpha skip, 0.99 clamp, stop) lie
     within ``pix_margin`` relative of their thresholds; the pixels where two
     Gaussians adjacent in a tile's sorted list and within ``depth_ulps``
-    float32 ulps of depth (their order may swap) are both composited; every
-    pixel of the tiles, widened by one
-    tile, of a Gaussian whose projection decisions (cull tests, radii, tile
-    rectangle) lie within ``proj_margin``.  Returns per-view boolean pixel
+    float32 ulps of depth (their order may swap) are both composited; the
+    pixels, in its tile rectangle widened by one tile, where a Gaussian whose
+    image-changing projection decisions (cull tests, radii, tile rectangle)
+    lie within ``proj_margin`` reaches (nearly) alpha 1/255.  Returns per-view boolean pixel
     masks [H][W] and a boolean mask over the Gaussians: those an ambiguous
-    pixel composites (or nearly), or ambiguous in projection, in any view."""
+    pixel composites (or nearly), or with any projection decision within
+    ``proj_margin``, in any view."""
     N = scene.n
     gmask = np.zeros(N, bool)
     pmasks = []
@@ -202,25 +203,13 @@ def ambiguity(scene, o, tile, proj_margin=2e-6, pix_margin=1e-4, depth_ulps=4):
         rng = o["ranges"][o["offsets"][v]:o["offsets"][v + 1]]
         vals = o["vals"]
         tmask = np.zeros((TY, TX), bool)
-        # projection decisions near a threshold
-        amb_g = pr["margin"] < proj_margin
-        gmask |= amb_g
-        for g in np.nonzero(amb_g)[0]:
-            with np.errstate(invalid="ignore"):
-                r = 3.0 * np.sqrt(max(pr["cov"][0][g], pr["cov"][2][g], 0.0)) + 1.0
-            u, vv = pr["u"][g], pr["v"][g]
-            if not (np.isfinite(r) and np.isfinite(u) and np.isfinite(vv)):
-                tmask[:] = True
-                continue
-            x0 = int(np.clip(np.floor((u - r) / tile) - 1, 0, TX))
-            x1 = int(np.clip(np.floor((u + r) / tile) + 2, 0, TX))
-            y0 = int(np.clip(np.floor((vv - r) / tile) - 1, 0, TY))
-            y1 = int(np.clip(np.floor((vv + r) / tile) + 2, 0, TY))
-            tmask[y0:y1, x0:x1] = True
-        pm = o["fwds"][v]["margin"] < pix_margin
-        pm |= np.repeat(np.repeat(tmask, tile, axis=0), tile, axis=1)[:H, :W]
-        # near depth ties inside a tile's sorted list: the pixels of the tile
-        # where both Gaussians of the pair are (nearly) composited
+        # projection decisions near a threshold: every one of them for the
+        # gradients (the clamps of the Jacobian and of the colour put kinks in
+        # them), those that can change an image discontinuously (visibility,
+        # radii, tile rectangle) for the pixels
+        gmask |= pr["margin"] < proj_margin
+        # the pixels such a Gaussian can change: inside its tile rectangle
+        # widened by one tile, where its alpha is (nearly) 1/255 or more
         A, Bc, C = pr["conic"]
         thr = (1.0 / 255.0) * (1.0 - 1e-3)
 
@@ -228,6 +217,28 @@ def ambiguity(scene, o, tile, proj_margin=2e-6, pix_margin=1e-4, depth_ulps=4):
             dx, dy = pr["u"][g] - (xs + 0.5), pr["v"][g] - (ys + 0.5)
             with np.errstate(over="ignore", invalid="ignore"):
                 return pr["sigma"][g] * np.exp(-0.5 * (A[g] * dx * dx + C[g] * dy * dy) - Bc[g] * dx * dy)
+
+        pm = o["fwds"][v]["margin"] < pix_margin
+        for g in np.nonzero(pr["margin_img"] < proj_margin)[0]:
+            with np.errstate(invalid="ignore"):
+                r = 3.0 * np.sqrt(max(pr["cov"][0][g], pr["cov"][2][g], 0.0)) + 1.0
+            u, vv = pr["u"][g], pr["v"][g]
+            if not (np.isfinite(r) and np.isfinite(u) and np.isfinite(vv)) or pr["sigma"][g] <= 0:
+                # no projection to go by (culled before it): the whole view
+                tmask[:] = True
+                continue
+            x0 = int(np.clip(np.floor((u - r) / tile) - 1, 0, TX)) * tile
+            x1 = min(W, int(np.clip(np.floor((u + r) / tile) + 2, 0, TX)) * tile)
+            y0 = int(np.clip(np.floor((vv - r) / tile) - 1, 0, TY)) * tile
+            y1 = min(H, int(np.clip(np.floor((vv + r) / tile) + 2, 0, TY)) * tile)
+            if x1 <= x0 or y1 <= y0:
+                continue
+            ys, xs = np.mgrid[y0:y1, x0:x1]
+            near = ~(alpha_at(g, xs, ys) < thr)
+            pm[ys[near], xs[near]] = True
+        pm |= np.repeat(np.repeat(tmask, tile, axis=0), tile, axis=1)[:H, :W]
+        # near depth ties inside a tile's sorted list: the pixels of the tile
+        # where both Gaussians of the pair are (nearly) composited
 
         z32 = pr["depth"].astype(np.float32)
         for t in range(TX * TY):

@@ -169,6 +169,71 @@ def test_batched_equals_plain_views():
         assert e <= 1e-5
 
 
+def _sixteen():
+    """The 16-view workload's layout at reduced size: 16 view sizes drawn as
+    for the 20M-Gaussian benchmark, each scaled by 1/8 per axis (80x60 ...
+    480x270, fx = 0.78125 W), 60,000 Gaussians from 256 blobs in a 50 m cube."""
+    rng = np.random.default_rng(4 + 1000)
+    picks = rng.integers(0, len(scenes.VIEW_SIZES), size=16)
+    views = [(scenes.VIEW_SIZES[i][0] // 8, scenes.VIEW_SIZES[i][1] // 8, 0.78125 * scenes.VIEW_SIZES[i][0] / 8)
+             for i in picks]
+    return scenes.blobs(4, 60_000, 256, 25.0, views, name="sixteen")
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_sixteen_views_batched_equals_plain_and_oracle(tile):
+    """All 16 views in one launch per call against 16 one-view runs (images and
+    every tile list bit-identical, summed gradients to float32 accumulation
+    order) and against the FP64 oracle (images outside the ambiguity set within
+    1e-5 plus the float32 rounding of the projected mean)."""
+    s = _sixteen()
+    G.say(f"[16 views, tile {tile}]")
+    rb, P, cams, tg, gb = _run_step(s, tile=tile, capacity=1 << 18, order="heavy", order_bwd="heavy")
+    assert int(G.host(rb.info)[2]) == 0
+    imgs_b = G.unpack(G.host(rb.images), s.sizes, 3)
+    ranges_b = G.host(rb.ranges).reshape(-1, 2)
+    gid_b = G.host(rb.isect_gid)
+    _, toff, _ = B.tile_grid(s.sizes, tile)
+    gsum = {k: np.zeros_like(G.host(v)) for k, v in gb.items()}
+    for v in range(s.n_views):
+        sv = scenes.Scene(s.means, s.log_scales, s.quats, s.opacity_logits, s.sh, s.sh_degree,
+                          s.viewmats[v:v + 1], s.intrinsics[v:v + 1], s.sizes[v:v + 1], [s.targets[v]])
+        r1, _, _, _, g1 = _run_step(sv, tile=tile, capacity=1 << 16)
+        np.testing.assert_array_equal(G.host(r1.images).reshape(imgs_b[v].shape), imgs_b[v])
+        r1r = G.host(r1.ranges).reshape(-1, 2)
+        rbv = ranges_b[toff[v]:toff[v + 1]]
+        np.testing.assert_array_equal(r1r[:, 1] - r1r[:, 0], rbv[:, 1] - rbv[:, 0])
+        gid1 = G.host(r1.isect_gid)
+        for t in np.nonzero(r1r[:, 1] > r1r[:, 0])[0]:
+            np.testing.assert_array_equal(gid1[r1r[t, 0]:r1r[t, 1]], gid_b[rbv[t, 0]:rbv[t, 1]])
+        scale = (3 * int(s.sizes[v][0]) * int(s.sizes[v][1])) / (3 * s.pixels)
+        for k in gsum:
+            gsum[k] += G.host(g1[k]) * scale
+    for k in gsum:
+        e = G.rel_l2(G.host(gb[k]), gsum[k])
+        G.say(f"  grad {k}: rel L2 {e:.1e}")
+        assert e <= 1e-5
+    # against the oracle: besides its discrete decisions, the image carries
+    # the float32 rounding of the projected mean (the record's pixel
+    # coordinates), which moves the falloff exponent of a compact splat by up
+    # to ~2 |Q d| ulp(u) with |Q d| <= ~3.3 / px (the 0.3 px^2 dilation bounds
+    # the conic's eigenvalues by 1 / 0.3): a few ulps of the view's largest
+    # coordinate, relative
+    o = oracle.step(s, tile=tile, backward=False)
+    pm, _ = G.ambiguity(s, o, tile)
+    errs = []
+    for v in range(s.n_views):
+        ref = o["imgs"][v]
+        keep = ~pm[v]
+        e = float(np.max(np.abs(imgs_b[v] - ref)[:, keep]) / np.max(np.abs(ref)))
+        bound = 1e-5 + 4.0 * float(np.spacing(np.float32(max(s.sizes[v]))))
+        errs.append((e, bound))
+    G.say(f"  images vs oracle outside {sum(int(m.sum()) for m in pm)} ambiguous pixels: " +
+          " ".join(f"{e:.1e}/{b:.1e}" for e, b in errs))
+    assert sum(int(m.sum()) for m in pm) <= 0.005 * s.pixels
+    assert all(e <= b for e, b in errs)
+
+
 @pytest.mark.parametrize("order,order_bwd", [("queue", "queue"), ("xcd", "heavy"), ("heavy", "xcd")])
 def test_tile_orders_equal_grid(order, order_bwd):
     s = _multi()
