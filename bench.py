@@ -573,7 +573,31 @@ def main():
                                "adam_bytes": adam_bytes}
         log(f"training step with fused Adam (captured): {ms_tr:.3f} ms/step; Adam alone {ms_adam:.3f} ms "
             f"({adam_bytes / (ms_adam * 1e-3) / 1e9:.0f} GB/s)")
-        del gt, P_tr, opt, g_tr
+        ms_pb = timed(lambda: r_main.project_bwd(P_tr, cams, g_tr), args.steps, torch)
+        del gt, opt, g_tr
+        torch.cuda.empty_cache()
+        # the same step with the update fused into the projection backward
+        # (gs_project_bwd_adam): no gradient tensors are written or read
+        opt_f = R.Adam(P_tr)
+        gf = r_main.capture_train(P_tr, cams, tg, None, opt_f, warmup=1, fused=True)
+        for _ in range(max(1, args.warmup)):
+            gf.replay()
+        ms_trf = timed(gf.replay, args.steps, torch)
+        ms_pba = timed(lambda: opt_f.update_fused(r_main, P_tr, cams), args.steps, torch)
+        # per element: parameter and both moments read and written (24 B);
+        # per (view, Gaussian): flags, and the 2-D gradients where visible
+        n_el = sum(t.numel() for t in P_tr.values())
+        fused_bytes = 24 * n_el + scene.n_views * scene.n + 36 * int(r_main.info.cpu()[B.INFO_VISIBLE])
+        extra["train_step"].update({
+            "fused": {"ms_per_step": round(ms_trf, 4), "mp_per_s": round(pixels / ms_trf / 1e3, 3),
+                      "project_bwd_adam_ms": round(ms_pba, 4),
+                      "unfused_project_bwd_plus_adam_ms": round(ms_pb + ms_adam, 4),
+                      "project_bwd_adam_gb_s": round(fused_bytes / (ms_pba * 1e-3) / 1e9, 1),
+                      "project_bwd_adam_bytes": fused_bytes}})
+        log(f"training step, Adam fused into the projection backward (captured): {ms_trf:.3f} ms/step; "
+            f"fused kernel {ms_pba:.3f} ms against {ms_pb:.3f} + {ms_adam:.3f} ms unfused "
+            f"({fused_bytes / (ms_pba * 1e-3) / 1e9:.0f} GB/s)")
+        del gf, P_tr, opt_f
         torch.cuda.empty_cache()
 
     cpu = None

@@ -297,6 +297,31 @@ int gs_project_bwd(const float* means, const float* log_scales, const float* qua
                    void* stream);
 
 /*
+ * gs_project_bwd_adam - gs_project_bwd followed by gs_adam over the five
+ * parameter tensors, fused: the thread that forms a Gaussian's gradient
+ * applies the Adam step to its parameters in place, so the gradient is never
+ * written to or read back from memory (paper Section 3.2: fused optimizer
+ * over the Gaussian parameters; Section 4: backward of the SH and projection
+ * operators).  The update is that of gs_adam with t = *step + 1, for the
+ * tensors means[3][N], log_scales[3][N], quats[4][N], opacity_logits[N] and
+ * sh[K][3][N] in this order, which are READ AND OVERWRITTEN (device).
+ * exp_avg and exp_avg_sq are host arrays of five device pointers to the
+ * moments, each shaped like its parameter tensor; lrs is a host array of the
+ * five learning rates.  Gaussians that no view sees get a zero gradient and
+ * are still updated (their moments decay).  step (device int32) is
+ * incremented on the stream after the update, so a captured graph replays
+ * consecutive steps.  The parameters, moments, flags and grad2d must not
+ * overlap one another.  N <= 2^30.  Errors: GS_ERR_ARG for null pointers
+ * (when N > 0), betas outside [0, 1), eps <= 0, a non-finite rate, N above
+ * 2^30 or the other gs_project_bwd argument checks.
+ */
+int gs_project_bwd_adam(float* means, float* log_scales, float* quats, float* opacity_logits, float* sh,
+                        int64_t n, int sh_degree, const float* viewmats, const float* intrinsics,
+                        const int32_t* sizes, int n_views, float eps2d, const uint8_t* flags, const float* grad2d,
+                        float* const* exp_avg, float* const* exp_avg_sq, const float* lrs, float beta1,
+                        float beta2, float eps, int32_t* step, void* stream);
+
+/*
  * gs_densify_stats - per-Gaussian statistics of the adaptive density control
  * of 3D Gaussian Splatting (Kerbl et al. 2023; the paper densifies to larger
  * Gaussian counts with it, Section 5), gathered from one step's 2-D gradients.

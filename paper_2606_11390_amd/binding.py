@@ -50,6 +50,8 @@ _SIGS = {
                                 _int, _p]),
     "gs_project_bwd": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
                               _p, _p, _p, _p]),
+    "gs_project_bwd_adam": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p, _p,
+                                   _f, _f, _f, _p, _p]),
     "gs_raster_visits": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p]),
     "gs_adam": (_int, [_int, _p, _p, _p, _p, _p, _p, _f, _f, _f, _p, _p]),
     "gs_morton_workspace_size": (_sz, [_i64]),
@@ -219,6 +221,28 @@ def project_bwd(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmat
                               _ptr(d_quats, F32, "d_quats"), _ptr(d_opacity_logits, F32, "d_opacity_logits"),
                               _ptr(d_sh, F32, "d_sh"), _stream())
     _check(rc, "gs_project_bwd")
+
+
+def project_bwd_adam(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes, eps2d,
+                     flags, grad2d, exp_avg, exp_avg_sq, lrs, beta1, beta2, eps, step):
+    """gs_project_bwd and gs_adam in one pass: updates the five parameter
+    tensors and their moments (lists in the order means, log_scales, quats,
+    opacity_logits, sh) in place and advances ``step``."""
+    if len(exp_avg) != 5 or len(exp_avg_sq) != 5 or len(lrs) != 5:
+        raise GSError("project_bwd_adam takes five moments and rates (means, log_scales, quats, "
+                      "opacity_logits, sh)")
+    n = means.shape[1]
+    sz, szp = _host_i32(sizes)
+    M = (ctypes.c_void_p * 5)(*[_ptr(t, F32, "exp_avg") for t in exp_avg])
+    V = (ctypes.c_void_p * 5)(*[_ptr(t, F32, "exp_avg_sq") for t in exp_avg_sq])
+    lr = (ctypes.c_float * 5)(*[float(x) for x in lrs])
+    rc = lib().gs_project_bwd_adam(_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
+                                   _ptr(quats, F32, "quats"), _ptr(opacity_logits, F32, "opacity_logits"),
+                                   _ptr(sh, F32, "sh"), n, int(sh_degree), _ptr(viewmats, F32, "viewmats"),
+                                   _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(eps2d),
+                                   _ptr(flags, U8, "flags"), _ptr(grad2d, F32, "grad2d"), M, V, lr, float(beta1),
+                                   float(beta2), float(eps), _ptr(step, I32, "step"), _stream())
+    _check(rc, "gs_project_bwd_adam")
 
 
 def loss_workspace_size(n_elems):

@@ -9,7 +9,9 @@
 // concatenated 16-byte chunks (one HBM read of p, g, m, v and one write of p,
 // m, v per element: 28 bytes, the algorithmic minimum).  The step count t is
 // read from device memory and advanced by a one-thread kernel afterwards, so
-// a captured graph replays successive steps correctly.
+// a captured graph replays successive steps correctly.  The same element
+// update (adam_elem) is applied inside the projection backward by
+// gs_project_bwd_adam, which then needs no gradient tensors.
 #include "gs_device.h"
 
 namespace gs {
@@ -26,14 +28,6 @@ struct AdamList {
     int count;
 };
 
-__device__ __forceinline__ void adam1(float& p, float g, float& m, float& v, float b1, float b2, float step,
-                                      float rbc2, float eps)
-{
-    m = __builtin_fmaf(b1, m, (1.0f - b1) * g);
-    v = __builtin_fmaf(b2, v, (1.0f - b2) * g * g);
-    p -= step * m / (sqrtf(v) * rbc2 + eps);
-}
-
 // chunks a thread handles per loop step (all their loads in flight at once)
 constexpr int ADAM_UNROLL = 4;
 typedef float af4 __attribute__((ext_vector_type(4)));
@@ -44,7 +38,7 @@ __device__ __forceinline__ void adam4(af4& p, af4 g, af4& m, af4& v, float b1, f
     float pp[4] = {p.x, p.y, p.z, p.w}, mm[4] = {m.x, m.y, m.z, m.w}, vv[4] = {v.x, v.y, v.z, v.w};
     const float gg[4] = {g.x, g.y, g.z, g.w};
 #pragma unroll
-    for (int e = 0; e < 4; e++) adam1(pp[e], gg[e], mm[e], vv[e], b1, b2, step, rbc2, eps);
+    for (int e = 0; e < 4; e++) adam_elem(pp[e], gg[e], mm[e], vv[e], b1, b2, step, rbc2, eps);
     p = af4{pp[0], pp[1], pp[2], pp[3]};
     m = af4{mm[0], mm[1], mm[2], mm[3]};
     v = af4{vv[0], vv[1], vv[2], vv[3]};
@@ -62,11 +56,8 @@ __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, fl
 {
     const long long total = L.chunk_off[L.count];
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const float t = (float)(*step_dev + 1);
-    // 1 - b^t = -expm1(t log1p(b - 1)): b - 1 is exact for b in [0.5, 1], and
-    // the form keeps full relative precision for b close to 1 (b2 = 0.999)
-    const float bc1 = -expm1f(t * log1pf(b1 - 1.0f));
-    const float rbc2 = 1.0f / sqrtf(-expm1f(t * log1pf(b2 - 1.0f)));
+    const AdamCoef ac = adam_coef(*step_dev, b1, b2);
+    const float rbc2 = ac.rbc2;
     // every element is read and written once per step: streaming
     // (non-temporal) accesses; ADAM_UNROLL chunks c, c + stride, ... per
     // thread and step, so that 4 x ADAM_UNROLL 16-byte loads are in flight
@@ -97,7 +88,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, fl
             if (c >= total) continue;
             const int k = kk[u];
             const long long i = ii[u];
-            const float step = L.lr[k] / bc1;
+            const float step = L.lr[k] * ac.step_scale;
             if (full[u]) {
                 adam4(p[u], g[u], m[u], v[u], b1, b2, step, rbc2, eps);
                 __builtin_nontemporal_store(p[u], reinterpret_cast<af4*>(L.p[k] + i));
@@ -107,7 +98,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, fl
                 // the ragged tail of a tensor, element by element
                 for (long long e = i; e < L.n[k]; e++) {
                     float pe = L.p[k][e], me = L.m[k][e], ve = L.v[k][e];
-                    adam1(pe, L.g[k][e], me, ve, b1, b2, step, rbc2, eps);
+                    adam_elem(pe, L.g[k][e], me, ve, b1, b2, step, rbc2, eps);
                     L.p[k][e] = pe;
                     L.m[k][e] = me;
                     L.v[k][e] = ve;
@@ -120,6 +111,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, fl
 __global__ void k_step_advance(int* step_dev) { step_dev[0] += 1; }
 
 }  // namespace
+
+hipError_t launch_step_advance(int* step_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, st, step_dev);
+    return hipGetLastError();
+}
 
 hipError_t launch_adam(int n_tensors, float* const* params, const float* const* grads, float* const* exp_avg,
                        float* const* exp_avg_sq, const int64_t* numel, const float* lrs, float beta1,
@@ -143,8 +140,8 @@ hipError_t launch_adam(int n_tensors, float* const* params, const float* const* 
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, L, beta1, beta2, eps, step_dev);
     }
-    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, st, step_dev);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_step_advance(step_dev, st);
 }
 
 }  // namespace gs

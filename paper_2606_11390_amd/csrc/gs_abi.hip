@@ -19,6 +19,11 @@ hipError_t launch_project_bwd(int deg, const float* means, const float* log_scal
                               float eps2d, const uint8_t* flags, const float* grad2d,
                               float* d_means, float* d_log_scales, float* d_quats, float* d_opac,
                               float* d_sh, hipStream_t stream);
+hipError_t launch_project_bwd_adam(int deg, float* means, float* log_scales, float* quats, float* opac, float* sh,
+                                   long long N, const float* viewmats, const float* intr, const ViewTable& vt,
+                                   float eps2d, const uint8_t* flags, const float* grad2d, float* const* exp_avg,
+                                   float* const* exp_avg_sq, const float* lrs, float beta1, float beta2, float eps,
+                                   int* step_dev, hipStream_t stream);
 size_t bin_sort_workspace_size(unsigned long long vn, unsigned long long cap);
 hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, const ViewTable& vt,
                            unsigned long long cap, void* workspace, uint32_t* isect_tile,
@@ -253,6 +258,30 @@ int gs_project_bwd(const float* means, const float* log_scales, const float* qua
     return status(gs::launch_project_bwd(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
                                          intrinsics, vt, eps2d, flags, grad2d, d_means, d_log_scales, d_quats,
                                          d_opacity_logits, d_sh, as_stream(stream)));
+}
+
+int gs_project_bwd_adam(float* means, float* log_scales, float* quats, float* opacity_logits, float* sh,
+                        int64_t n, int sh_degree, const float* viewmats, const float* intrinsics,
+                        const int32_t* sizes, int n_views, float eps2d, const uint8_t* flags, const float* grad2d,
+                        float* const* exp_avg, float* const* exp_avg_sq, const float* lrs, float beta1,
+                        float beta2, float eps, int32_t* step, void* stream)
+{
+    ViewTable vt;
+    // N <= 2^30: the kernel addresses a parameter plane with a 32-bit byte
+    // offset (4 N bytes)
+    if (n < 0 || n > (1ll << 30) || sh_degree < 0 || sh_degree > 3 || !make_views(sizes, n_views, 16, vt))
+        return GS_ERR_ARG;
+    if (!(eps2d >= 0.0f) || !exp_avg || !exp_avg_sq || !lrs || !step) return GS_ERR_ARG;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) return GS_ERR_ARG;
+    float* const params[5] = {means, log_scales, quats, opacity_logits, sh};
+    for (int k = 0; k < 5; k++) {
+        if (!std::isfinite(lrs[k])) return GS_ERR_ARG;
+        if (n > 0 && (!params[k] || !exp_avg[k] || !exp_avg_sq[k])) return GS_ERR_ARG;
+    }
+    if (n > 0 && (!viewmats || !intrinsics || !flags || !grad2d)) return GS_ERR_ARG;
+    return status(gs::launch_project_bwd_adam(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
+                                              intrinsics, vt, eps2d, flags, grad2d, exp_avg, exp_avg_sq, lrs, beta1,
+                                              beta2, eps, step, as_stream(stream)));
 }
 
 int gs_raster_visits(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges, int64_t n,

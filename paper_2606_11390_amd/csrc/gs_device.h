@@ -159,6 +159,41 @@ __device__ __forceinline__ float wave_sum9_scatter(const float* a, int& j)
     return e;
 }
 
+// Adam (Kingma and Ba 2015) with bias correction, one element; shared by the
+// stand-alone update and the one fused into the projection backward, so the
+// two give the same bits.  Every multiply-add is written out as an fma, so no
+// file's contraction setting changes the result.
+struct AdamCoef {
+    float step_scale;   // 1 / (1 - b1^t), multiplied by the tensor's rate
+    float rbc2;         // 1 / sqrt(1 - b2^t)
+};
+
+// t = step + 1.  1 - b^t = -expm1(t log1p(b - 1)): b - 1 is exact for b in
+// [0.5, 1], and the form keeps full relative precision for b near 1.
+__device__ __forceinline__ AdamCoef adam_coef(int step, float b1, float b2)
+{
+    const float t = (float)(step + 1);
+    AdamCoef c;
+    c.step_scale = 1.0f / -expm1f(t * log1pf(b1 - 1.0f));
+    c.rbc2 = 1.0f / sqrtf(-expm1f(t * log1pf(b2 - 1.0f)));
+    return c;
+}
+
+// m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+// p <- p - lr / (1 - b1^t) m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+// The square root and the reciprocal are the hardware's (v_sqrt_f32,
+// v_rcp_f32: about 1 ulp each) instead of the correctly rounded expansions,
+// which cost some 25 more instructions per element; the update's relative
+// error stays a few ulp.
+__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, float b1, float b2, float step,
+                                          float rbc2, float eps)
+{
+    m = __builtin_fmaf(b1, m, (1.0f - b1) * g);
+    v = __builtin_fmaf(b2, v, ((1.0f - b2) * g) * g);
+    const float den = __builtin_fmaf(__builtin_amdgcn_sqrtf(v), rbc2, eps);
+    p = __builtin_fmaf(-(step * m), __builtin_amdgcn_rcpf(den), p);
+}
+
 __device__ __forceinline__ int wave_max_i(int x)
 {
     for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o));

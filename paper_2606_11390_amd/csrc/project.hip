@@ -18,6 +18,8 @@
 // the Cholesky factor of the conic computed from it:
 //   m00 = sqrt(c0 c / D), m10 = -b sqrt(c0 / (c D)), m11 = sqrt(c0 / c)
 // for Sigma2 = [[a, b], [b, c]], D = det Sigma2, c0 = log2(e)/2.
+#include <type_traits>
+
 #include "gs_device.h"
 
 namespace gs {
@@ -330,16 +332,68 @@ __global__ __launch_bounds__(256) void k_project(
 // only the 16 basis values and 3 colour gradients are kept (not 48 sums), and
 // the coefficients are read where they are used instead of being cached
 // across views.
-template <int DEG, bool SV>
+//
+// ADAM: instead of storing the gradients, the same thread applies the Adam
+// step to its Gaussian's parameters in place (the gradient never reaches
+// HBM); the parameters are then read and written through the same pointers.
+template <bool ADAM>
+using ParamPtr = typename std::conditional<ADAM, float*, const float*>::type;
+
+// Adam hyperparameters; the moments of the five parameter tensors (means,
+// log-scales, quaternions, opacity logits, SH coefficients) are kernel
+// arguments of their own, declared non-aliasing, so that the moment loads of
+// later elements may be issued before the stores of earlier ones.
+struct AdamState {
+    float lr[5];
+    float b1, b2, eps;
+    const int* step;
+};
+
+// Element at byte offset boff of a plane whose base is uniform: the address is
+// a scalar base plus one 32-bit lane offset that every plane shares, so the
+// Adam variant does not keep a 64-bit address per parameter plane live in
+// vector registers (it needs N <= 2^30, which its entry point checks).
+template <class T>
+__device__ __forceinline__ T* at(T* plane, uint32_t boff)
+{
+    return reinterpret_cast<T*>(reinterpret_cast<typename std::conditional<std::is_const<T>::value, const char, char>::type*>(plane) + boff);
+}
+
+// one parameter element (plane c): gradient gr, either stored or applied by
+// Adam to the parameter value p
+template <bool ADAM>
+__device__ __forceinline__ void emit_grad(float gr, float p, float* p_base, float* d_base, float* m_base,
+                                          float* v_base, long long c, long long N, long long g, uint32_t boff,
+                                          float step, float rbc2, const AdamState& as)
+{
+    if constexpr (ADAM) {
+        float* const mp = at(m_base + c * N, boff);
+        float* const vp = at(v_base + c * N, boff);
+        float m = nt_load(mp), v = nt_load(vp);
+        adam_elem(p, gr, m, v, as.b1, as.b2, step, rbc2, as.eps);
+        nt_store(p, at(p_base + c * N, boff));
+        nt_store(m, mp);
+        nt_store(v, vp);
+    } else {
+        nt_store(gr, &d_base[c * N + g]);
+    }
+}
+
+template <int DEG, bool SV, bool ADAM>
 __global__ __launch_bounds__(256) void k_project_bwd(
-    const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
+    ParamPtr<ADAM> __restrict__ means, ParamPtr<ADAM> __restrict__ log_scales,
+    ParamPtr<ADAM> __restrict__ quats, ParamPtr<ADAM> __restrict__ opac, ParamPtr<ADAM> __restrict__ sh,
     long long N, const float* __restrict__ viewmats, const float* __restrict__ intr, ViewTable vt,
     float eps2d, const uint8_t* __restrict__ flags, const float* __restrict__ grad2d,
     float* __restrict__ d_means, float* __restrict__ d_log_scales, float* __restrict__ d_quats,
-    float* __restrict__ d_opac, float* __restrict__ d_sh)
+    float* __restrict__ d_opac, float* __restrict__ d_sh, AdamState as, float* __restrict__ m0,
+    float* __restrict__ m1, float* __restrict__ m2, float* __restrict__ m3, float* __restrict__ m4,
+    float* __restrict__ v0, float* __restrict__ v1, float* __restrict__ v2, float* __restrict__ v3,
+    float* __restrict__ v4)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
+    // coefficients held in registers: several views, or the Adam update
+    constexpr bool CACHE = !SV || ADAM;
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
 
@@ -359,11 +413,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     // a Gaussian no view sees gets zero gradients without reading its
     // parameters (whole cache lines are skipped when such Gaussians are
     // contiguous, e.g. in Morton order)
+    // (the Adam update needs every parameter whatever the gradient)
+    uint32_t boff = ADAM ? (uint32_t)g * 4u : 0u;
+    auto ldp = [&](const float* base, long long c) {
+        return ADAM ? nt_load(at(base + c * N, boff)) : nt_load(&base[c * N + g]);
+    };
     float mu[3] = {0.0f, 0.0f, 0.0f}, ls[3] = {0.0f, 0.0f, 0.0f}, q[4] = {1.0f, 0.0f, 0.0f, 0.0f};
-    if (any) {
-        for (int i = 0; i < 3; i++) mu[i] = nt_load(&means[i * N + g]);
-        for (int i = 0; i < 3; i++) ls[i] = nt_load(&log_scales[i * N + g]);
-        for (int i = 0; i < 4; i++) q[i] = nt_load(&quats[i * N + g]);
+    if (ADAM || any) {
+        for (int i = 0; i < 3; i++) mu[i] = ldp(means, i);
+        for (int i = 0; i < 3; i++) ls[i] = ldp(log_scales, i);
+        for (int i = 0; i < 4; i++) q[i] = ldp(quats, i);
     }
     const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     const float iq = any ? 1.0f / sqrtf(qn2) : 0.0f;
@@ -374,13 +433,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
 
-    float coef[SV ? 1 : 3 * K];
-    if (!SV && any) {
+    float coef[CACHE ? 3 * K : 1];
+    if (CACHE && (ADAM || any)) {
         for (int j = 0; j < K; j++)
-            for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = nt_load(&sh[((long long)j * 3 + ch) * N + g]);
+            for (int ch = 0; ch < 3; ch++) coef[3 * j + ch] = ldp(sh, j * 3 + ch);
     }
     // coefficient j, channel ch
-    auto cf = [&](int j, int ch) { return SV ? nt_load(&sh[((long long)j * 3 + ch) * N + g]) : coef[SV ? 0 : 3 * j + ch]; };
+    auto cf = [&](int j, int ch) {
+        return CACHE ? coef[CACHE ? 3 * j + ch : 0] : nt_load(&sh[((long long)j * 3 + ch) * N + g]);
+    };
 
     for (int v = 0; any && v < (SV ? 1 : vt.n_views); v++) {
         const long long o_vg = (long long)v * N + g;
@@ -469,12 +530,24 @@ __global__ __launch_bounds__(256) void k_project_bwd(
         }
     }
 
+    float a_step[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, rbc2 = 0.0f;
+    if constexpr (ADAM) {
+        // the update's addresses are formed afresh from the lane offset (an
+        // opaque copy), instead of the compiler keeping the 64-bit address of
+        // every coefficient plane live from the loads above
+        asm volatile("" : "+v"(boff));
+        const AdamCoef ac = adam_coef(*as.step, as.b1, as.b2);
+        for (int k = 0; k < 5; k++) a_step[k] = as.lr[k] * ac.step_scale;
+        rbc2 = ac.rbc2;
+    }
+
     // every lane of the wave stores each SH plane at once: whole lines, not
     // two partial writes (seen and unseen lanes) that may each reach HBM
     if constexpr (SV)
         for (int j = 0; j < K; j++)
             for (int ch = 0; ch < 3; ch++)
-                nt_store(Ysv[j] * gcsv[ch], &d_sh[((long long)j * 3 + ch) * N + g]);
+                emit_grad<ADAM>(Ysv[j] * gcsv[ch], CACHE ? coef[CACHE ? 3 * j + ch : 0] : 0.0f, (float*)sh, d_sh,
+                                m4, v4, j * 3 + ch, N, g, boff, a_step[4], rbc2, as);
 
     // M = R diag(s), s = exp(l):  dl_j = s_j sum_i dM_ij R_ij;  dR_ij = dM_ij s_j
     float gR[9];
@@ -492,17 +565,25 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     gq[3] = 2.0f * (-2.0f * zq * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0f * zq * gR[4] +
                     y * gR[5] + x * gR[6] + y * gR[7]);
     const float qd = w * gq[0] + x * gq[1] + y * gq[2] + zq * gq[3];
-    const float sigma = any ? 1.0f / (1.0f + expf(-nt_load(&opac[g]))) : 0.0f;
+    const float ologit = (ADAM || any) ? ldp(opac, 0) : 0.0f;
+    const float sigma = any ? 1.0f / (1.0f + expf(-ologit)) : 0.0f;
 
-    for (int i = 0; i < 3; i++) nt_store(any ? gmu[i] : 0.0f, &d_means[i * N + g]);
-    for (int i = 0; i < 3; i++) nt_store(any ? gl[i] : 0.0f, &d_log_scales[i * N + g]);
+    for (int i = 0; i < 3; i++)
+        emit_grad<ADAM>(any ? gmu[i] : 0.0f, mu[i], (float*)means, d_means, m0, v0, i, N, g, boff, a_step[0], rbc2,
+                        as);
+    for (int i = 0; i < 3; i++)
+        emit_grad<ADAM>(any ? gl[i] : 0.0f, ls[i], (float*)log_scales, d_log_scales, m1, v1, i, N, g, boff,
+                        a_step[1], rbc2, as);
     for (int k = 0; k < 4; k++)
-        nt_store(any ? (gq[k] - qh[k] * qd) * iq : 0.0f, &d_quats[k * N + g]);
-    nt_store(any ? gsig * sigma * (1.0f - sigma) : 0.0f, &d_opac[g]);
+        emit_grad<ADAM>(any ? (gq[k] - qh[k] * qd) * iq : 0.0f, q[k], (float*)quats, d_quats, m2, v2, k, N, g, boff,
+                        a_step[2], rbc2, as);
+    emit_grad<ADAM>(any ? gsig * sigma * (1.0f - sigma) : 0.0f, ologit, (float*)opac, d_opac, m3, v3, 0, N, g, boff,
+                    a_step[3], rbc2, as);
     if constexpr (!SV)
         for (int j = 0; j < K; j++)
             for (int ch = 0; ch < 3; ch++)
-                nt_store(gsh[3 * j + ch], &d_sh[((long long)j * 3 + ch) * N + g]);
+                emit_grad<ADAM>(gsh[3 * j + ch], coef[3 * j + ch], (float*)sh, d_sh, m4, v4, j * 3 + ch, N, g, boff,
+                                a_step[4], rbc2, as);
 }
 
 }  // namespace
@@ -534,15 +615,39 @@ hipError_t launch_project(int deg, const float* means, const float* log_scales, 
     return hipGetLastError();
 }
 
-#define GS_PROJ_BWD_LAUNCH(DEG)                                                                        \
-    if (vt.n_views == 1)                                                                               \
-        hipLaunchKernelGGL((k_project_bwd<DEG, true>), dim3(blocks), dim3(256), 0, stream, means,         \
-                           log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,     \
-                           d_means, d_log_scales, d_quats, d_opac, d_sh);                                \
-    else                                                                                               \
-        hipLaunchKernelGGL((k_project_bwd<DEG, false>), dim3(blocks), dim3(256), 0, stream, means,        \
-                           log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,     \
-                           d_means, d_log_scales, d_quats, d_opac, d_sh)
+namespace {
+
+template <bool ADAM>
+hipError_t launch_bwd(int deg, ParamPtr<ADAM> means, ParamPtr<ADAM> log_scales, ParamPtr<ADAM> quats,
+                      ParamPtr<ADAM> opac, ParamPtr<ADAM> sh, long long N, const float* viewmats, const float* intr,
+                      const ViewTable& vt, float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
+                      float* d_log_scales, float* d_quats, float* d_opac, float* d_sh, const AdamState& as,
+                      float* const* mo, float* const* vo, hipStream_t stream)
+{
+    if (N == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((N + 255) / 256);
+#define GS_PROJ_BWD_LAUNCH(DEG)                                                                         \
+    if (vt.n_views == 1)                                                                                \
+        hipLaunchKernelGGL((k_project_bwd<DEG, true, ADAM>), dim3(blocks), dim3(256), 0, stream, means,    \
+                           log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,      \
+                           d_means, d_log_scales, d_quats, d_opac, d_sh, as, mo[0], mo[1], mo[2], mo[3], mo[4], \
+                           vo[0], vo[1], vo[2], vo[3], vo[4]);                                           \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_project_bwd<DEG, false, ADAM>), dim3(blocks), dim3(256), 0, stream, means,   \
+                           log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,      \
+                           d_means, d_log_scales, d_quats, d_opac, d_sh, as, mo[0], mo[1], mo[2], mo[3], mo[4], \
+                           vo[0], vo[1], vo[2], vo[3], vo[4])
+    switch (deg) {
+    case 0: GS_PROJ_BWD_LAUNCH(0); break;
+    case 1: GS_PROJ_BWD_LAUNCH(1); break;
+    case 2: GS_PROJ_BWD_LAUNCH(2); break;
+    default: GS_PROJ_BWD_LAUNCH(3); break;
+    }
+#undef GS_PROJ_BWD_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace
 
 hipError_t launch_project_bwd(int deg, const float* means, const float* log_scales,
                               const float* quats, const float* opac, const float* sh, long long N,
@@ -551,15 +656,30 @@ hipError_t launch_project_bwd(int deg, const float* means, const float* log_scal
                               float* d_means, float* d_log_scales, float* d_quats, float* d_opac,
                               float* d_sh, hipStream_t stream)
 {
-    if (N == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((N + 255) / 256);
-    switch (deg) {
-    case 0: GS_PROJ_BWD_LAUNCH(0); break;
-    case 1: GS_PROJ_BWD_LAUNCH(1); break;
-    case 2: GS_PROJ_BWD_LAUNCH(2); break;
-    default: GS_PROJ_BWD_LAUNCH(3); break;
-    }
-    return hipGetLastError();
+    const AdamState none = {};
+    float* const no_moments[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    return launch_bwd<false>(deg, means, log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,
+                             d_means, d_log_scales, d_quats, d_opac, d_sh, none, no_moments, no_moments, stream);
+}
+
+hipError_t launch_step_advance(int* step_dev, hipStream_t st);
+
+hipError_t launch_project_bwd_adam(int deg, float* means, float* log_scales, float* quats, float* opac, float* sh,
+                                   long long N, const float* viewmats, const float* intr, const ViewTable& vt,
+                                   float eps2d, const uint8_t* flags, const float* grad2d, float* const* exp_avg,
+                                   float* const* exp_avg_sq, const float* lrs, float beta1, float beta2, float eps,
+                                   int* step_dev, hipStream_t stream)
+{
+    AdamState as;
+    for (int k = 0; k < 5; k++) as.lr[k] = lrs[k];
+    as.b1 = beta1;
+    as.b2 = beta2;
+    as.eps = eps;
+    as.step = step_dev;
+    const hipError_t e = launch_bwd<true>(deg, means, log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d,
+                                          flags, grad2d, nullptr, nullptr, nullptr, nullptr, nullptr, as, exp_avg,
+                                          exp_avg_sq, stream);
+    return e != hipSuccess ? e : launch_step_advance(step_dev, stream);
 }
 
 }  // namespace gs

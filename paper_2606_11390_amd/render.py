@@ -182,11 +182,19 @@ class Renderer:
         self.loss_l2(targets)
         return self.backward(P, cams, self.d_images, grads)
 
-    def train_step(self, P, cams, targets, grads, optimizer):
+    def train_step(self, P, cams, targets, grads, optimizer, fused=False):
         """``step`` followed by the optimizer's fused update of ``P`` (the
-        training step the paper's backend runs; capturable)."""
-        self.step(P, cams, targets, grads)
-        optimizer.update(grads)
+        training step the paper's backend runs; capturable).  ``fused``: the
+        projection backward applies the update itself (gs_project_bwd_adam)
+        and ``grads`` is neither written nor read."""
+        if not fused:
+            self.step(P, cams, targets, grads)
+            optimizer.update(grads)
+            return
+        self.forward(P, cams)
+        self.loss_l2(targets)
+        self.raster_bwd(self.d_images)
+        optimizer.update_fused(self, P, cams)
 
     def fit_capacity(self, P, cams, headroom=1.25):
         """Run projection + binning eagerly and grow the intersection capacity
@@ -220,19 +228,19 @@ class Renderer:
         self.graph = g
         return g
 
-    def capture_train(self, P, cams, targets, grads, optimizer, warmup=2):
+    def capture_train(self, P, cams, targets, grads, optimizer, warmup=2, fused=False):
         """Capture ``train_step`` (forward, loss, backward and the Adam update)
         in one HIP graph.  Warm-up steps update the parameters too."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             for _ in range(warmup):
-                self.train_step(P, cams, targets, grads, optimizer)
+                self.train_step(P, cams, targets, grads, optimizer, fused=fused)
         torch.cuda.current_stream().wait_stream(s)
         gc.collect()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.train_step(P, cams, targets, grads, optimizer)
+            self.train_step(P, cams, targets, grads, optimizer, fused=fused)
         return g
 
     def replay(self):
@@ -242,6 +250,7 @@ class Renderer:
 # per-parameter learning rates of 3D Gaussian Splatting's training recipe
 # (means 1.6e-4 x scene extent, log-scales 5e-3, quaternions 1e-3, opacity
 # logits 5e-2, SH DC 2.5e-3 and higher bands 2.5e-3 / 20); one rate per tensor
+PARAM_KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 DEFAULT_LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3)
 
 
@@ -264,6 +273,19 @@ class Adam:
     def update(self, grads):
         B.adam([self.P[k] for k in self.keys], [grads[k] for k in self.keys], [self.m[k] for k in self.keys],
                [self.v[k] for k in self.keys], self.lrs, self.b1, self.b2, self.eps, self.t)
+
+    def update_fused(self, renderer, P, cams):
+        """The renderer's projection backward (from its 2-D gradients of the
+        last rasteriser backward) fused with this update: same result as
+        ``renderer.project_bwd`` into gradient tensors, then ``update``."""
+        if P is not self.P and any(P[k] is not self.P[k] for k in PARAM_KEYS):
+            raise B.GSError("update_fused: P is not the optimizer's parameter set")
+        lr = dict(zip(self.keys, self.lrs))
+        r = renderer
+        B.project_bwd_adam(*[self.P[k] for k in PARAM_KEYS], r.deg, cams["viewmats"], cams["intrinsics"], r.sizes,
+                           r.eps2d, r.flags, r.grad2d, [self.m[k] for k in PARAM_KEYS],
+                           [self.v[k] for k in PARAM_KEYS], [lr[k] for k in PARAM_KEYS], self.b1, self.b2, self.eps,
+                           self.t)
 
     def state_bytes(self):
         return sum(2 * t.numel() * t.element_size() for t in self.P.values())

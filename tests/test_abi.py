@@ -78,6 +78,18 @@ def test_host_side_argument_checks():
     assert L.gs_rasterize_bwd(p, p, p, 10, 1, szp, 16, 0, 0, bg, None, None, p, p, None, None, p, 0, None) == -1
     assert L.gs_rasterize_bwd(p, p, p, 10, 1, szp, 16, 8, 4, bg, None, None, p, p, p, None, p, 0, None) == -1
     assert L.gs_project_bwd(p, p, p, p, p, 10, 5, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, None) == -1
+    # gs_project_bwd_adam: N above 2^30, bad betas / eps / rate, a missing moment
+    five = (ctypes.c_void_p * 5)(*([16] * 5))
+    hole = (ctypes.c_void_p * 5)(16, 16, None, 16, 16)
+    rates = (ctypes.c_float * 5)(1e-3, 1e-3, 1e-3, 1e-3, 1e-3)
+    bad_rate = (ctypes.c_float * 5)(1e-3, float("inf"), 1e-3, 1e-3, 1e-3)
+    fused = lambda **kw: [p, p, p, p, p, kw.get("n", 10), 3, p, p, szp, 1, 0.3, p, p, kw.get("m", five), five,
+                          kw.get("lr", rates), kw.get("b1", 0.9), 0.999, kw.get("eps", 1e-15), p, None]
+    assert L.gs_project_bwd_adam(*fused(n=(1 << 30) + 1)) == -1
+    assert L.gs_project_bwd_adam(*fused(b1=1.0)) == -1
+    assert L.gs_project_bwd_adam(*fused(eps=0.0)) == -1
+    assert L.gs_project_bwd_adam(*fused(lr=bad_rate)) == -1
+    assert L.gs_project_bwd_adam(*fused(m=hole)) == -1
     assert L.gs_loss_l2(p, p, 10, p, p, p, 0, None) == -4
     assert L.gs_loss_l2_noalloc(p, p, -1, p, p, None) == -1
     assert L.gs_loss_l2_noalloc(p, p, 10, None, p, None) == -1

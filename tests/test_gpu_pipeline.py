@@ -340,6 +340,52 @@ def test_captured_train_step_matches_eager():
         assert G.rel_l2(G.host(ob.v[k]), G.host(oa.v[k])) <= 1e-4, k
 
 
+@pytest.mark.parametrize("which", ["one view", "four views"])
+def test_fused_projection_backward_adam_equals_unfused(which):
+    """gs_project_bwd_adam against gs_project_bwd followed by gs_adam on the
+    same 2-D gradients, over three steps (the third replayed from a graph):
+    parameters and both Adam moments agree element by element, including the
+    Gaussians no view sees (zero gradient; their moments decay and their
+    parameters keep moving)."""
+    s = (scenes.blobs(13, 20000, 24, 10.0, [(320, 180, 250.0)], name="hd_small") if which == "one view"
+         else _multi())
+    G.say(f"[fused projection backward + Adam, {which}]")
+    r, P, cams, tg, grads = _run_step(s)
+    unseen = int(np.sum(~np.any(G.host(r.flags).reshape(len(s.sizes), s.n) & B.FLAG_VISIBLE, axis=0)))
+    assert 0 < unseen < s.n, unseen
+    PA = {k: v.clone() for k, v in P.items()}
+    PB = {k: v.clone() for k, v in P.items()}
+    oa, ob = R.Adam(PA), R.Adam(PB)
+    ga = R.zeros_like_params(PA)
+    graph = None
+    for step in range(3):
+        r.project_bwd(PA, cams, ga)
+        oa.update(ga)
+        if step < 2:
+            ob.update_fused(r, PB, cams)
+        else:
+            graph = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.graph(graph, stream=side):
+                ob.update_fused(r, PB, cams)
+            graph.replay()
+    torch.cuda.synchronize()
+    assert int(G.host(oa.t)[0]) == 3 and int(G.host(ob.t)[0]) == 3
+    # the two forms run the same float32 operations (explicit fmas, the same
+    # gradient code), so every parameter and moment is the same bits
+    for k in R.PARAM_KEYS:
+        p0 = G.host(P[k])
+        assert np.linalg.norm(G.host(PA[k]).astype(np.float64) - p0) > 0, k
+        for name, a, b in (("p", PA[k], PB[k]), ("m", oa.m[k], ob.m[k]), ("v", oa.v[k], ob.v[k])):
+            a, b = G.host(a), G.host(b)
+            diff = int(np.sum(a != b))
+            if diff:
+                G.say(f"  {k}.{name}: {diff} of {a.size} differ, rel_max {G.rel_max(b, a):.2e}")
+            np.testing.assert_array_equal(b, a, err_msg=f"{k}.{name}")
+    G.say(f"  all parameters and moments bit-identical; {unseen} of {s.n} Gaussians unseen")
+
+
 def test_renderer_reports_overflow():
     s = scenes.tiny()
     r = R.Renderer(s.n, s.sh_degree, s.sizes, capacity=100)
