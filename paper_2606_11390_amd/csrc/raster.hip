@@ -209,6 +209,9 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                 const int j = __builtin_ctzll(mask);
                 mask &= mask - 1;
                 const float4 ea = cst->a[j];
+                // the colour is read with the geometry, so a taken entry waits
+                // for one LDS round trip, not two
+                const float4 cc = cst->col[j];
                 const float su = ea.x, sv = ea.y, m00 = ea.z, m10 = ea.w;
                 const float m11 = lane_f(cur.b.x, j), ls = lane_f(cur.b.y, j);
                 const float dy = sv - fy;
@@ -222,8 +225,10 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
                     take[p] = __ballot(alp[p] >= kAlphaMin) & live[p];
                     any_take |= take[p];
                 }
+                // keeps the colour load above the branch (it would otherwise be
+                // sunk into the taken path and issued only there)
+                asm volatile("" ::"v"(cc.x), "v"(cc.y), "v"(cc.z));
                 if (any_take == 0ull) continue;
-                const float4 cc = cst->col[j];
                 const float cr = cc.x, cg = cc.y, cb = cc.z;
 #pragma unroll
                 for (int p = 0; p < P; p++) {
@@ -341,6 +346,9 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                 mask &= mask - 1;
                 const float4 ra = stage->rec[0][j];
                 const float4 rb = stage->rec[1][j];
+                // colour, opacity and index are read with the geometry: one LDS
+                // round trip per composited entry instead of two
+                const float4 rc = stage->rec[2][j];
                 const float su = ra.x, sv = ra.y, m00 = ra.z, m10 = ra.w, m11 = rb.x, ls = rb.y;
                 const float dy = sv - fy;
                 const int kk = kb - j - r.x;
@@ -353,8 +361,9 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                     okp[p] = kk < last[p] && fminf(fp[p].araw, kAlphaMax) >= kAlphaMin;
                     any = any || okp[p];
                 }
+                // keeps those loads above the branch
+                asm volatile("" ::"v"(rb.z), "v"(rb.w), "v"(rc.x), "v"(rc.y), "v"(rc.z));
                 if (__ballot(any) == 0ull) continue;
-                const float4 rc = stage->rec[2][j];
                 const int gid = __builtin_amdgcn_readfirstlane(__float_as_int(rc.z));
                 const float cr = rb.z, cg = rb.w, cb = rc.x;
                 const float inv_sig = __builtin_amdgcn_rcpf(rc.y);
