@@ -133,23 +133,58 @@ __device__ __forceinline__ float bfly0(float x, bool hi)
 // Wave-wide sums of nine values, scattered: afterwards lane l (l < 16) holds
 // the total of value j(l) = b3 + 2 b2 + 4 b0 + 8 b1 (b_k = bit k of l), a
 // permutation of 0..15 in which 9..15 carry zeros.  The four in-row steps
-// pair lanes across bit 3 (row mirror), bit 2 (half-row mirror), bit 0 and
-// bit 1 (quad permutes); two shuffles then add the four rows.  About 40 VALU
-// operations instead of nine full reductions.
+// pair lanes across bit 3 (row mirror, bank-masked adds), bit 2 (half-row
+// mirror, bank-masked adds), bit 0 and bit 1 (quad permutes, selects); two
+// shuffles then add the four rows.  About 24 vector operations and two
+// shuffles instead of nine full reductions.
 // the value index j(l) whose total lane l holds after wave_sum9_scatter
 __device__ __forceinline__ int wave_sum9_slot(int l)
 {
     return ((l & 8) ? 1 : 0) | ((l & 4) ? 2 : 0) | ((l & 1) ? 4 : 0) | ((l & 2) ? 8 : 0);
 }
 
+// Butterfly steps across lane bit 3 (row mirror) and bit 2 (half-row mirror)
+// written as two bank-masked DPP adds per pair: a DPP bank is lane bits 2-3,
+// so the lanes that keep the even member are written by one add and the
+// others by the second, and no selects are needed (two instructions per pair
+// instead of three).  The compiler has no form for a bank-masked add that
+// keeps the other lanes, hence the asm; it reads and writes registers only.
+// Each DPP read waits two cycles after the last vector write of its source
+// (the gfx9 DPP hazard; s_nop 1), since the compiler does not see inside.
+#define GS_DPP_ADD_FIRST(t, x, CTRL, BANK)                                                          \
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 " CTRL " row_mask:0xf bank_mask:" BANK " bound_ctrl:1" \
+        : "=&v"(t)                                                                               \
+        : "v"(x))
+#define GS_DPP_ADD_REST(t, x, CTRL, BANK)                                                           \
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 " CTRL " row_mask:0xf bank_mask:" BANK " bound_ctrl:1" \
+        : "+v"(t)                                                                                \
+        : "v"(x))
+
+// t = x + x[partner] on the lanes with the bit clear, y + y[partner] on the others
+__device__ __forceinline__ float bfly_mirror(float x, float y)
+{
+    float t;
+    GS_DPP_ADD_FIRST(t, x, "row_mirror", "0x3");
+    GS_DPP_ADD_REST(t, y, "row_mirror", "0xc");
+    return t;
+}
+
+__device__ __forceinline__ float bfly_half_mirror(float x, float y)
+{
+    float t;
+    GS_DPP_ADD_FIRST(t, x, "row_half_mirror", "0x5");
+    GS_DPP_ADD_REST(t, y, "row_half_mirror", "0xa");
+    return t;
+}
+
 __device__ __forceinline__ float wave_sum9_scatter(const float* a, int& j)
 {
     const int l = __lane_id();
     const bool h1 = l & 8, h2 = l & 4, h3 = l & 1, h4 = l & 2;
-    const float b0 = bfly<0x140>(a[0], a[1], h1), b1 = bfly<0x140>(a[2], a[3], h1);
-    const float b2 = bfly<0x140>(a[4], a[5], h1), b3 = bfly<0x140>(a[6], a[7], h1);
+    const float b0 = bfly_mirror(a[0], a[1]), b1 = bfly_mirror(a[2], a[3]);
+    const float b2 = bfly_mirror(a[4], a[5]), b3 = bfly_mirror(a[6], a[7]);
     const float b4 = bfly0<0x140>(a[8], h1);
-    const float c0 = bfly<0x141>(b0, b1, h2), c1 = bfly<0x141>(b2, b3, h2);
+    const float c0 = bfly_half_mirror(b0, b1), c1 = bfly_half_mirror(b2, b3);
     const float c2 = bfly0<0x141>(b4, h2);
     const float d0 = bfly<0xB1>(c0, c1, h3), d1 = bfly0<0xB1>(c2, h3);
     float e = bfly<0x4E>(d0, d1, h4);

@@ -41,7 +41,7 @@ struct Rec {
 // back with three broadcast LDS loads instead of eleven readlanes, which
 // would take VALU issue slots from the per-pixel work that bounds it).
 struct WaveStage {
-    float4 rec[3][GS_WAVE];   // rec[2] holds (b, sigma, splat index, -): the box is only needed by the cull
+    float4 rec[3][GS_WAVE];   // rec[2] holds (b, splat index, 1 / sigma, -): the box is only needed by the cull
 };
 
 // A wave's copy of part of its current batch in LDS: the forward reads an
@@ -339,7 +339,9 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
             __builtin_amdgcn_wave_barrier();
             stage->rec[0][lane] = cur.a;
             stage->rec[1][lane] = cur.b;
-            stage->rec[2][lane] = make_float4(cur.c.x, cur.c.y, __int_as_float(g_cur), 0.0f);
+            // 1 / sigma once per staged entry, not once per composited entry
+            stage->rec[2][lane] =
+                make_float4(cur.c.x, __int_as_float(g_cur), __builtin_amdgcn_rcpf(cur.c.y), 0.0f);
             __builtin_amdgcn_wave_barrier();
             while (mask) {
                 const int j = __builtin_ctzll(mask);
@@ -364,9 +366,9 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                 // keeps those loads above the branch
                 asm volatile("" ::"v"(rb.z), "v"(rb.w), "v"(rc.x), "v"(rc.y), "v"(rc.z));
                 if (__ballot(any) == 0ull) continue;
-                const int gid = __builtin_amdgcn_readfirstlane(__float_as_int(rc.z));
+                const int gid = __builtin_amdgcn_readfirstlane(__float_as_int(rc.y));
                 const float cr = rb.z, cg = rb.w, cb = rc.x;
-                const float inv_sig = __builtin_amdgcn_rcpf(rc.y);
+                const float inv_sig = rc.z;
                 // a0..a4 leave out constant factors (-ln 2 times 2, 2, c0,
                 // 2 c0, c0) that are applied once to the wave sums (gscale)
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
