@@ -193,6 +193,26 @@ def counted_traffic(stage, r, workload):
     return None
 
 
+def counted_issue(stage, r, workload):
+    """Executed vector work of the stage's kernel from the committed SQ
+    counter summary of this workload: (vector instructions per launch, share
+    of the SIMDs' busy quad-cycles that issued one), or None when there is
+    none or it was taken on other kernel sources."""
+    name = kernel_name(stage, r)
+    path = os.path.join(ROOT, "profiles", f"{workload}_sq_counters.md")
+    if name is None or not os.path.exists(path):
+        return None
+    sha = sources_sha1(stage)
+    for line in open(path):
+        # sq: kernel=<name> | valu_insts=<int> | valu_issue=<float> | waves=<int> | sources=<sha1 prefix>
+        if not line.startswith("sq: "):
+            continue
+        f = dict(kv.split("=", 1) for kv in line[len("sq: "):].strip().split(" | "))
+        if f.get("kernel") == name and f.get("sources") == sha:
+            return int(f["valu_insts"]), float(f["valu_issue"])
+    return None
+
+
 def algorithmic_bytes(scene, visible, isect, total_tiles):
     """HBM bytes each HBM-bound call of the step must move at minimum, from
     the workload's counts (N Gaussians, V views, visible (view, Gaussian)
@@ -528,6 +548,12 @@ def main():
         if tr:
             ent["trace_avg_us"] = tr
             ent["frac_from_trace"] = round(ops / (tr * 1e-6) / 1e12 / PEAK_FP32_TFLOPS, 4)
+        ex = counted_issue(k, r_main, scene.name)
+        if ex:
+            # executed work: vector instructions per launch (SQ_INSTS_VALU) and
+            # the share of busy SIMD quad-cycles that issued one
+            ent["executed"] = {"valu_insts": ex[0], "valu_issue": ex[1],
+                               "lane_valu_insts_per_visit": round(ex[0] * 64 / max(nv, 1), 2)}
         rooflines[k] = ent
     for k in ("project", "bin_sort", "loss", "project_bwd"):
         a = work[k] / (st[k] * 1e-3) / 1e9
