@@ -39,8 +39,6 @@ import numpy as np  # noqa: E402
 # HBM / VALU peaks of one MI355X (published)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-# without packed FP32 instructions (the build disables them): 256 CU x 64 lanes x 2 x 2.4 GHz
-PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # algorithmic FP32 operations per visit (one list entry examined by one
 # pixel): the compositing forward ~20 vector operations and one exponential,
 # the backward ~50 vector operations, one exponential and one division
@@ -542,8 +540,7 @@ def main():
         ops = opv * nv
         ent = {"bound": "alu", "achieved": round(ops / (st[k] * 1e-3) / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
                "unit": "TFLOP/s", "frac": round(ops / (st[k] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-               "ops_per_visit": opv, "visits": nv, "work_per_launch": ops, "launch_us": round(st[k] * 1e3, 2),
-               "frac_unpacked_fp32_peak": round(ops / (st[k] * 1e-3) / 1e12 / PEAK_FP32_UNPACKED_TFLOPS, 4)}
+               "ops_per_visit": opv, "visits": nv, "work_per_launch": ops, "launch_us": round(st[k] * 1e3, 2)}
         tr = trace_avg_us(k, r_main, scene.name)
         if tr:
             ent["trace_avg_us"] = tr
