@@ -146,8 +146,8 @@ def kernel_name(stage, r):
     return None
 
 
-def trace_avg_us(stage, r, workload):
-    """Average duration (us) of the stage's kernel in the committed
+def trace_us(stage, r, workload):
+    """(average, median) duration (us) of the stage's kernel in the committed
     rocprofv3 --kernel-trace --stats summary of this workload, or None."""
     name = kernel_name(stage, r)
     path = os.path.join(ROOT, "profiles", f"{workload}_step_kernel_stats.md")
@@ -157,7 +157,7 @@ def trace_avg_us(stage, r, workload):
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cells) >= 4 and cells[0] == f"`{name}`":
             try:
-                return float(cells[3])
+                return float(cells[3]), (float(cells[5]) if len(cells) >= 6 and cells[5] else None)
             except ValueError:
                 return None
     return None
@@ -541,10 +541,13 @@ def main():
         ent = {"bound": "alu", "achieved": round(ops / (st[k] * 1e-3) / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
                "unit": "TFLOP/s", "frac": round(ops / (st[k] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
                "ops_per_visit": opv, "visits": nv, "work_per_launch": ops, "launch_us": round(st[k] * 1e3, 2)}
-        tr = trace_avg_us(k, r_main, scene.name)
+        tr = trace_us(k, r_main, scene.name)
         if tr:
-            ent["trace_avg_us"] = tr
-            ent["frac_from_trace"] = round(ops / (tr * 1e-6) / 1e12 / PEAK_FP32_TFLOPS, 4)
+            ent["trace_avg_us"] = tr[0]
+            ent["frac_from_trace"] = round(ops / (tr[0] * 1e-6) / 1e12 / PEAK_FP32_TFLOPS, 4)
+            if tr[1]:
+                ent["trace_median_us"] = tr[1]
+                ent["frac_from_trace_median"] = round(ops / (tr[1] * 1e-6) / 1e12 / PEAK_FP32_TFLOPS, 4)
         ex = counted_issue(k, r_main, scene.name)
         if ex:
             # executed work: vector instructions per launch (SQ_INSTS_VALU) and
