@@ -82,6 +82,24 @@ def test_fullsize_binning_bit_exact():
     np.testing.assert_array_equal(rg, ranges)
 
 
+def test_fullsize_binning_large_capacity_bit_exact():
+    """The same binning with a capacity of 2^24 intersections: more emission
+    workgroups (8,192) than histogram block columns (4,096), so the emission
+    does not count the first tile digit itself and the first tile pass runs
+    its own histogram, over block counts capped at 4,096; the lists are the
+    same bits."""
+    s, P, projs, arrs, keys, vals, ranges = _stage()
+    M = len(keys)
+    cap = 1 << 24
+    assert cap > 4096 * 2048 > M
+    it, ig, rg, info = G.gpu_bin_sort(arrs, s.sizes, TILE, cap)
+    G.say(f"[fullsize] binning at capacity 2^24: M {M}, GPU info {info[:3]}")
+    assert info[1] == M and info[2] == 0
+    np.testing.assert_array_equal(it[:M], (keys >> np.uint64(32)).astype(np.int32))
+    np.testing.assert_array_equal(ig[:M], vals)
+    np.testing.assert_array_equal(rg, ranges)
+
+
 def test_fullsize_raster_forward_persistent():
     s, P, projs, arrs, keys, vals, ranges = _stage()
     sp, f = _fwd()
