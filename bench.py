@@ -626,6 +626,34 @@ def main():
         del gf, P_tr, opt_f
         torch.cuda.empty_cache()
 
+        # the other per-step calls of the training loop, alone: the fused SSIM
+        # + L1 loss on the step's images (forward and image gradient), and the
+        # 3-D Morton order of the means with the gather of all 59 parameter
+        # planes (run at densification time, not every step)
+        ws_s = torch.empty(B.ssim_workspace_size(scene.sizes), dtype=torch.uint8, device="cuda")
+        loss_s = torch.empty(1, device="cuda")
+        d_s = torch.empty_like(r_main.images)
+        ms_ssim = timed(lambda: B.loss_ssim_l1(r_main.images, tg, scene.sizes, 0.2, loss_s, d_s, ws_s),
+                        args.steps, torch)
+        n = scene.n
+        means = P["means"]
+        ws_m = torch.empty(max(1, B.morton_workspace_size(n)), dtype=torch.uint8, device="cuda")
+        order = torch.empty(n, dtype=torch.int32, device="cuda")
+        lo = means.min(dim=1).values.cpu().numpy().astype(np.float32)
+        hi = means.max(dim=1).values.cpu().numpy().astype(np.float32)
+        inv = ((1 << 10) / np.maximum(hi.astype(np.float64) - lo, 1e-30)).astype(np.float32)
+        ms_morton = timed(lambda: B.morton_order(means, lo, inv, ws_m, order), args.steps, torch)
+        cols = {k: torch.empty_like(v) for k, v in P.items()}
+        ms_gather = timed(lambda: [B.gather_columns(P[k], order, cols[k]) for k in P], args.steps, torch)
+        n_el = sum(t.numel() for t in P.values())
+        extra["ssim_l1"] = {"ms": round(ms_ssim, 4), "mp_per_s": round(pixels / ms_ssim / 1e3, 1)}
+        extra["morton"] = {"order_ms": round(ms_morton, 4), "gather_ms": round(ms_gather, 4),
+                           "gather_gb_s": round(n_el * 4 * 2 / (ms_gather * 1e-3) / 1e9, 1)}
+        log(f"SSIM + L1 loss and image gradient: {ms_ssim:.3f} ms; Morton order {ms_morton:.3f} ms, "
+            f"gather of the parameters {ms_gather:.3f} ms")
+        del ws_s, loss_s, d_s, ws_m, order, cols
+        torch.cuda.empty_cache()
+
     cpu = None
     cpu_small = None
     if not args.no_cpu_baseline and scene.n_views == 1:
