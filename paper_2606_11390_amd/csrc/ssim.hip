@@ -20,7 +20,11 @@
 //   backward: the three partial maps are staged with the same halo and
 //     correlated with the (symmetric) window again, the same way:
 //       dL/dx = w * dmu + 2 x (w * dExx) + y (w * dExy)
-//               + (1 - lam) sign(x - y) / n.
+//               + (1 - lam) sign(x - y) / n;
+//     its first workgroup also adds up the forward's partial losses.
+// Staging issues all of a thread's loads before storing any, and the staged
+// inputs and the filtered rows share one LDS array, so that enough
+// workgroups stay resident to cover the memory latency.
 // A tile's 64 staged rows by 4 row segments and its 32 columns by 8 column
 // segments (7 rows each, the last 5) give every thread one task per pass.
 #include <cmath>
