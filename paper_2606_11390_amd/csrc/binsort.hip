@@ -989,7 +989,15 @@ __global__ void k_gather_columns(const float* __restrict__ src, int C, long long
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long j = order[i];
-    for (int c = 0; c < C; c++) dst[c * n + i] = src[c * n + j];
+    // eight planes' loads in flight before their stores
+    for (int c0 = 0; c0 < C; c0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = c0 + u < C ? src[(c0 + u) * n + j] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            if (c0 + u < C) dst[(c0 + u) * n + i] = v[u];
+    }
 }
 }  // namespace
 
