@@ -297,40 +297,51 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
     const int nd = 1 << bits;
     const uint32_t mask = (1u << bits) - 1u;
 
-    // global start of each digit for this block
-    {
-        uint32_t x[DPT];
-#pragma unroll
-        for (int i = 0; i < DPT; i++) x[i] = t * DPT + i < nd ? dtot[t * DPT + i] : 0u;
-        const uint32_t all = block_excl_scan_digits<DPT>(x, s_tmp);
-#pragma unroll
-        for (int i = 0; i < DPT; i++) {
-            const int d = t * DPT + i;
-            s_base[d] = d < nd ? x[i] + excl[(size_t)d * nb + b] : 0u;
-        }
-        if (count_out && b == 0 && t == 0) *count_out = all;
-    }
-
     const uint32_t n = io_count(io);
     uint32_t beg, end;
     block_span(n, nb, b, beg, end);
     const uint64_t lt = lanemask_lt();
-
-    for (uint32_t cb = beg; cb < end; cb += RS_CHUNK) {
-        for (int i = t; i < RS_WAVES * nd; i += RS_THREADS) s_wcnt[i >> bits][i & (nd - 1)] = 0;
-        __syncthreads();
-        uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
-        int2 rct[GATHER ? RS_ITEMS : 1];
-        bool ok[RS_ITEMS];
+    uint32_t key[RS_ITEMS], val[RS_ITEMS];
+    bool ok[RS_ITEMS];
+    // all loads of a thread for a chunk are issued before any is used; the
+    // first chunk's are issued before the digit offsets below are set up, so
+    // that both wait on memory together
+    auto load_chunk = [&](uint32_t cb) {
         const uint32_t wb = cb + (uint32_t)w * RS_WAVE_SPAN;
-        // all loads of a thread are issued before any is used (and, when
-        // gathering, all rectangle reads before the ranking)
 #pragma unroll
         for (int r = 0; r < RS_ITEMS; r++) {
             key[r] = 0;
             val[r] = 0;
             ok[r] = load_kv<SRC>(io, wb + (uint32_t)(r * GS_WAVE + lane), end, key[r], val[r]);
         }
+    };
+    if (beg < end) load_chunk(beg);
+
+    // global start of each digit for this block (the per-block offsets are
+    // read with the digit totals, before the scan)
+    {
+        uint32_t x[DPT], ex[DPT];
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const int d = t * DPT + i;
+            x[i] = d < nd ? dtot[d] : 0u;
+            ex[i] = d < nd ? excl[(size_t)d * nb + b] : 0u;
+        }
+        const uint32_t all = block_excl_scan_digits<DPT>(x, s_tmp);
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const int d = t * DPT + i;
+            s_base[d] = d < nd ? x[i] + ex[i] : 0u;
+        }
+        if (count_out && b == 0 && t == 0) *count_out = all;
+    }
+
+    for (uint32_t cb = beg; cb < end; cb += RS_CHUNK) {
+        for (int i = t; i < RS_WAVES * nd; i += RS_THREADS) s_wcnt[i >> bits][i & (nd - 1)] = 0;
+        __syncthreads();
+        uint32_t rank[RS_ITEMS];
+        int2 rct[GATHER ? RS_ITEMS : 1];
+        if (cb != beg) load_chunk(cb);
         if (GATHER) {
             // every value is a pair index, also past the end (see load_kv)
 #pragma unroll
