@@ -141,14 +141,22 @@ __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t e
     }
 }
 
-// lanes of the wave holding the same `bits`-bit digit as this lane
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits)
+// lanes of the wave holding the same digit as this lane.  NB is the widest
+// digit the kernel instance handles; a narrower pass leaves the high bits of
+// every digit zero, where all lanes agree, so the loop is unrolled to NB
+// steps with no per-pass count.  Per bit: the lanes with the bit set (one
+// ballot) and a mask that keeps them or their complement (xor, and).
+template <int NB>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
 {
     uint64_t m = __ballot(valid);
-    for (int k = 0; k < bits; k++) {
-        const bool bit = (d >> k) & 1u;
-        const uint64_t b = __ballot(bit);
-        m &= bit ? b : ~b;
+    const uint32_t dn = ~d;
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+        // all ones where bit k of d is clear, zero where it is set
+        const uint32_t nb = (uint32_t)((int)(dn << (31 - k)) >> 31);
+        const uint64_t b = __ballot(nb == 0u);
+        m &= b ^ (((uint64_t)nb << 32) | nb);
     }
     return valid ? m : 0ull;
 }
@@ -210,7 +218,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortIO io, int shift, in
 #pragma unroll
         for (int r = 0; r < RS_ITEMS; r++) {
             const uint32_t d = (k[r] >> shift) & mask;
-            const uint64_t peers = match_digit(d, valid[r], bits);
+            const uint64_t peers = match_digit<DBITS>(d, valid[r]);
             if (valid[r] && (peers & lt) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
         }
     }
@@ -350,7 +358,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
 #pragma unroll
         for (int r = 0; r < RS_ITEMS; r++) {
             const uint32_t d = (key[r] >> shift) & mask;
-            const uint64_t peers = match_digit(d, ok[r], bits);
+            const uint64_t peers = match_digit<DBITS>(d, ok[r]);
             const uint32_t before = s_wcnt[w][d];
             rank[r] = before + (uint32_t)__popcll(peers & lt);
             if (ok[r] && (peers & lt) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
