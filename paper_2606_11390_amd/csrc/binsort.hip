@@ -149,16 +149,22 @@ __device__ __forceinline__ bool load_kv(const SortIO& io, uint32_t i, uint32_t e
 template <int NB>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
 {
-    uint64_t m = __ballot(valid);
+    const uint64_t v = __ballot(valid);
+    uint32_t mlo = (uint32_t)v, mhi = (uint32_t)(v >> 32);
     const uint32_t dn = ~d;
 #pragma unroll
     for (int k = 0; k < NB; k++) {
         // all ones where bit k of d is clear, zero where it is set
         const uint32_t nb = (uint32_t)((int)(dn << (31 - k)) >> 31);
         const uint64_t b = __ballot(nb == 0u);
-        m &= b ^ (((uint64_t)nb << 32) | nb);
+        // m & (b ^ nb) in one gfx950 three-input logic op per half: with m as
+        // the middle operand the function is symmetric in the outer two, so
+        // table 0x48 (true for (1,1,0) and (0,1,1)) holds for either operand
+        // order of the lookup index
+        mlo = __builtin_amdgcn_bitop3_b32((uint32_t)b, mlo, nb, 0x48);
+        mhi = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), mhi, nb, 0x48);
     }
-    return valid ? m : 0ull;
+    return valid ? (((uint64_t)mhi << 32) | mlo) : 0ull;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt()
