@@ -96,21 +96,22 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
     """Average duration of each call of the step inside whole steps: the calls
     of `steps` steps launched one after another on the launch stream, in the
     order of the captured step, with HIP events between them (the host stays
-    ahead of the GPU, so an interval is the call's own GPU time).  The
-    backward's 2-D gradient buffer is zeroed by a separate fill before the
-    rasteriser backward is called in accumulate mode: the same work as the
-    step's non-accumulating call, with the fill outside the timed kernel."""
-    from paper_2606_11390_amd import binding as B
-    s, q = r._sched(r.order_bwd)
+    ahead of the GPU, so an interval is the call's own GPU time).  As in the
+    step, the projection zeroes the visible pairs' 2-D gradient records and
+    the rasteriser backward accumulates into them."""
+    if r.fused_l2_active:
+        # the loss is formed inside the rasteriser backward: its call (the
+        # backward kernel and the two small kernels that sum the loss
+        # partials) is the "raster_bwd" stage
+        loss_bwd = [("raster_bwd", lambda: r.loss_raster_bwd(tg, accumulate=True))]
+    else:
+        loss_bwd = [("loss", lambda: r.loss_l2(tg)),
+                    ("raster_bwd", lambda: r.raster_bwd(r.d_images, accumulate=True))]
     calls = [
-        ("project", lambda: r.project(P, cams)),
+        ("project", lambda: r.project(P, cams, clear_grad2d=True)),
         ("bin_sort", r.bin_sort),
         ("raster_fwd", r.raster_fwd),
-        ("loss", lambda: r.loss_l2(tg)),
-        ("zero_grad2d", r.grad2d.zero_),
-        ("raster_bwd", lambda: B.rasterize_bwd(r.splats, r.isect_gid, r.ranges, r.n, r.sizes, r.tile,
-                                               r.background, s, q, r.T_final, r.n_contrib, r.d_images, None,
-                                               r.grad2d, accumulate=True, block=r.block_bwd)),
+        *loss_bwd,
         ("project_bwd", lambda: r.project_bwd(P, cams, grads)),
     ]
     for _ in range(2):
@@ -139,6 +140,8 @@ def kernel_name(stage, r):
         fwd = stage == "raster_fwd"
         blk = r.block if fwd else r.block_bwd
         order = r.order if fwd else r.order_bwd
+        if not fwd and r.fused_l2_active:
+            return f"k_raster_bwd_l2<{r.tile}, {blk[0]}, {blk[1]}>"
         kind = "fwd" if fwd else "bwd"
         suffix = "_persistent" if order == "queue" else ""
         last = "" if (order == "queue" and kind == "fwd") else ", false"
@@ -220,7 +223,8 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
                  parameters (224 B at SH degree 3) for the Gaussians some view
                  sees (counted as min(N, visible pairs), exact for one view);
                  per pair depth, radii, tile count, tile rectangle and flags
-                 written (25 B); the 48-byte splat record per visible pair
+                 written (25 B); the 48-byte splat record and the zeroed
+                 36-byte 2-D gradient record per visible pair
     bin_sort     LSD radix sort, 16 B (key + value, read + write) per element
                  per pass: 4 depth passes over visible pairs (the first reads
                  depth and tile count, 8 B per pair), emission (24 B read per
@@ -242,7 +246,7 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
     sort = (8 * V * N + 8 * visible + 3 * 16 * visible + 24 * visible + 8 * isect + tpasses * 16 * isect +
             4 * isect + 8 * total_tiles)
     seen = min(N, visible)
-    return {"project": 12 * N + (param - 12) * seen + 25 * V * N + 48 * visible,
+    return {"project": 12 * N + (param - 12) * seen + 25 * V * N + (48 + 36) * visible,
             "bin_sort": sort,
             "loss": 12 * 3 * scene.pixels,
             "project_bwd": N * param + seen * param + V * N + 36 * visible}
@@ -556,6 +560,8 @@ def main():
                                "lane_valu_insts_per_visit": round(ex[0] * 64 / max(nv, 1), 2)}
         rooflines[k] = ent
     for k in ("project", "bin_sort", "loss", "project_bwd"):
+        if k not in st:
+            continue
         a = work[k] / (st[k] * 1e-3) / 1e9
         rooflines[k] = {"bound": "hbm", "achieved": round(a, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": round(a / PEAK_HBM_GBS, 4), "work_per_launch": int(work[k]),

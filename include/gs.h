@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 3
+#define GS_ABI_VERSION 4
 #define GS_MAX_VIEWS 64
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD_FLOATS 9
@@ -155,13 +155,19 @@ const char* gs_strerror(int code);
  *                         grid, packed as x0 | y0 << 16, x1 | y1 << 16 (int32);
  *                         all zero when culled
  *   flags                 GS_FLAG_* bits (uint8)
+ *   grad2d_clear[V][N][9] optional (may be NULL): the 2-D gradient records of
+ *                         the visible pairs are zeroed, so that a following
+ *                         gs_rasterize_bwd / gs_rasterize_bwd_l2 of these
+ *                         lists can accumulate (accumulate != 0) instead of
+ *                         clearing all V N records first; records of culled
+ *                         pairs are left as they are (no call reads them)
  */
 int gs_project(const float* means, const float* log_scales, const float* quats,
                const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
                const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
                float near_plane, float far_plane, float eps2d, int tile, int radius_mode,
                float* splats, float* depths, int32_t* radii, int32_t* tiles_touched,
-               int32_t* tile_rects, uint8_t* flags, void* stream);
+               int32_t* tile_rects, uint8_t* flags, float* grad2d_clear, void* stream);
 
 /*
  * gs_bin_sort_workspace_size - bytes of device workspace gs_bin_sort needs
@@ -279,6 +285,38 @@ int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_
                      const float* background, const void* schedule, int32_t* queue, const float* T_final,
                      const int32_t* n_contrib, const float* d_images, const float* d_alpha,
                      float* grad2d, int accumulate, void* stream);
+
+/*
+ * gs_rasterize_bwd_l2_workspace_size - bytes of device workspace
+ * gs_rasterize_bwd_l2 needs for these views and tile edge (8 bytes per
+ * 64 pixels of tile area: one partial sum per wavefront).
+ */
+size_t gs_rasterize_bwd_l2_workspace_size(int n_views, const int32_t* sizes, int tile);
+
+/*
+ * gs_rasterize_bwd_l2 - the L2 image loss and the rasteriser backward in one
+ * pass (paper Section 4: per camera the image loss, then the backward of the
+ * rasteriser with gradient accumulation by atomics).  Equals gs_loss_l2 over
+ * all packed elements (n = 3 * sum of W * H) followed by gs_rasterize_bwd
+ * with d_images = 2 (images - targets) / n and no d_alpha, except that
+ * d_images is never stored: each wavefront forms its pixels' gradient from
+ * images and targets as gs_loss_l2 does (same float32 operations, so grad2d
+ * gets the same per-pixel terms), and adds its pixels' squared errors to a
+ * per-wavefront partial sum.
+ * Inputs: as gs_rasterize_bwd, with images (the gs_rasterize_fwd output) and
+ *   targets (packed [3][H][W] per view) instead of d_images and d_alpha.
+ *   Grid dispatch only (schedule NULL or a tile order; no work queue).
+ * Outputs: loss (device float[1]) = mean squared error, reduced in a fixed
+ *   order (per-wavefront float sums, then in double by one workgroup), so it
+ *   is deterministic; grad2d as gs_rasterize_bwd (accumulate likewise).
+ * workspace: >= gs_rasterize_bwd_l2_workspace_size() bytes, 8-byte aligned,
+ *   clobbered (one double per wavefront, then one per 4,096 of those).
+ */
+int gs_rasterize_bwd_l2(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges, int64_t n,
+                        int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
+                        const float* background, const void* schedule, const float* T_final,
+                        const int32_t* n_contrib, const float* images, const float* targets, float* loss,
+                        float* grad2d, int accumulate, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * gs_project_bwd - backward of gs_project (paper Section 4: backward of the

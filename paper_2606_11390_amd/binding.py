@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
-GS_ABI_VERSION = 3
+GS_ABI_VERSION = 4
 GS_MAX_VIEWS = 64
 SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
@@ -38,7 +38,7 @@ _SIGS = {
     "gs_abi_version": (_int, []),
     "gs_strerror": (ctypes.c_char_p, [_int]),
     "gs_project": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _f, _f, _int, _int,
-                          _p, _p, _p, _p, _p, _p, _p]),
+                          _p, _p, _p, _p, _p, _p, _p, _p]),
     "gs_densify_stats": (_int, [_p, _p, _p, _i64, _int, _p, _p, _p, _p, _p]),
     "gs_bin_sort_workspace_size": (_sz, [_i64, _int, _i64, _i64]),
     "gs_bin_sort": (_int, [_p, _p, _i64, _int, _p, _int, _i64, _p, _sz, _p, _p, _p, _p, _p]),
@@ -48,6 +48,9 @@ _SIGS = {
     "gs_rasterize_fwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p]),
     "gs_rasterize_bwd": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p,
                                 _int, _p]),
+    "gs_rasterize_bwd_l2_workspace_size": (_sz, [_int, _p, _int]),
+    "gs_rasterize_bwd_l2": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p,
+                                   _p, _int, _p, _sz, _p]),
     "gs_project_bwd": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
                               _p, _p, _p, _p]),
     "gs_project_bwd_adam": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p, _p,
@@ -138,7 +141,8 @@ F32, I32, U8 = torch.float32, torch.int32, torch.uint8
 
 
 def project(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes,
-            near, far, eps2d, tile, splats, depths, radii, tiles_touched, tile_rects, flags, radius_mode=0):
+            near, far, eps2d, tile, splats, depths, radii, tiles_touched, tile_rects, flags, radius_mode=0,
+            grad2d_clear=None):
     n = means.shape[1]
     sz, szp = _host_i32(sizes)
     rc = lib().gs_project(_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
@@ -147,7 +151,8 @@ def project(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, i
                           _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(near), float(far),
                           float(eps2d), int(tile), int(radius_mode), _ptr(splats, F32, "splats"), _ptr(depths, F32, "depths"),
                           _ptr(radii, I32, "radii"), _ptr(tiles_touched, I32, "tiles_touched"),
-                          _ptr(tile_rects, I32, "tile_rects"), _ptr(flags, U8, "flags"), _stream())
+                          _ptr(tile_rects, I32, "tile_rects"), _ptr(flags, U8, "flags"),
+                          _ptr(grad2d_clear, F32, "grad2d_clear"), _stream())
     _check(rc, "gs_project")
 
 
@@ -206,6 +211,26 @@ def rasterize_bwd(splats, isect_gid, tile_ranges, n, sizes, tile, background, sc
                                 _ptr(d_images, F32, "d_images"), _ptr(d_alpha, F32, "d_alpha"),
                                 _ptr(grad2d, F32, "grad2d"), int(bool(accumulate)), _stream())
     _check(rc, "gs_rasterize_bwd")
+
+
+def rasterize_bwd_l2_workspace_size(sizes, tile):
+    sz, szp = _host_i32(sizes)
+    return int(lib().gs_rasterize_bwd_l2_workspace_size(sz.shape[0], szp, int(tile)))
+
+
+def rasterize_bwd_l2(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, T_final, n_contrib,
+                     images, targets, loss, grad2d, workspace, accumulate=False, block=(0, 0)):
+    """gs_loss_l2 and gs_rasterize_bwd in one pass (d_images is not stored)."""
+    sz, szp = _host_i32(sizes)
+    bg, bgp = _host_f32(background)
+    rc = lib().gs_rasterize_bwd_l2(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
+                                   _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile),
+                                   int(block[0]), int(block[1]), bgp, _ptr(schedule, U8, "schedule"),
+                                   _ptr(T_final, F32, "T_final"), _ptr(n_contrib, I32, "n_contrib"),
+                                   _ptr(images, F32, "images"), _ptr(targets, F32, "targets"),
+                                   _ptr(loss, F32, "loss"), _ptr(grad2d, F32, "grad2d"), int(bool(accumulate)),
+                                   _ptr(workspace, U8, "workspace"), workspace.numel(), _stream())
+    _check(rc, "gs_rasterize_bwd_l2")
 
 
 def project_bwd(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes,

@@ -9,7 +9,7 @@ hipError_t launch_project(int deg, const float* means, const float* log_scales, 
                           const float* opac, const float* sh, long long N, const float* viewmats,
                           const float* intr, const ViewTable& vt, float near_plane, float far_plane,
                           float eps2d, int tile, int radius_mode, float* splats, float* depths, int2* radii,
-                          int* tiles, int2* rects, uint8_t* flags, hipStream_t stream);
+                          int* tiles, int2* rects, uint8_t* flags, float* g2clear, hipStream_t stream);
 hipError_t launch_densify_stats(const float* grad2d, const uint8_t* flags, const int2* radii, long long N,
                                 const ViewTable& vt, float* grad_accum, int* count, int* max_radius,
                                 hipStream_t st);
@@ -40,6 +40,12 @@ hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, con
                              const int* gids, const int2* ranges, long long N, const float* bg,
                              const int* order, int* queue, const float* Tfin, const int* nlast,
                              const float* dimg, const float* dalpha, float* grad2d, hipStream_t st);
+size_t raster_bwd_l2_workspace_size(const ViewTable& vt, int tile);
+hipError_t launch_raster_bwd_l2(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
+                                const int* gids, const int2* ranges, long long N, const float* bg,
+                                const int* order, const float* Tfin, const int* nlast, const float* img,
+                                const float* tgt, long long n_elems, float* loss, void* part, float* grad2d,
+                                hipStream_t st);
 size_t loss_workspace_size(long long n);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
 size_t morton_workspace_size(long long n);
@@ -120,7 +126,7 @@ int gs_project(const float* means, const float* log_scales, const float* quats,
                const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
                float near_plane, float far_plane, float eps2d, int tile, int radius_mode, float* splats,
                float* depths, int32_t* radii, int32_t* tiles_touched, int32_t* tile_rects, uint8_t* flags,
-               void* stream)
+               float* grad2d_clear, void* stream)
 {
     ViewTable vt;
     if (n < 0 || n > 0x7FFFFFFFll || sh_degree < 0 || sh_degree > 3 || !tile_ok(tile) ||
@@ -137,7 +143,8 @@ int gs_project(const float* means, const float* log_scales, const float* quats,
     return status(gs::launch_project(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
                                      intrinsics, vt, near_plane, far_plane, eps2d, tile, radius_mode, splats,
                                      depths, reinterpret_cast<int2*>(radii), tiles_touched,
-                                     reinterpret_cast<int2*>(tile_rects), flags, as_stream(stream)));
+                                     reinterpret_cast<int2*>(tile_rects), flags, grad2d_clear,
+                                     as_stream(stream)));
 }
 
 size_t gs_bin_sort_workspace_size(int64_t n, int n_views, int64_t capacity, int64_t total_tiles)
@@ -238,6 +245,43 @@ int gs_rasterize_bwd(const float* splats, const int32_t* isect_gid, const int32_
                                         reinterpret_cast<const int2*>(tile_ranges), n, background,
                                         static_cast<const int*>(schedule), queue, T_final, n_contrib, d_images,
                                         d_alpha, grad2d, as_stream(stream)));
+}
+
+size_t gs_rasterize_bwd_l2_workspace_size(int n_views, const int32_t* sizes, int tile)
+{
+    ViewTable vt;
+    if (!tile_ok(tile) || !make_views(sizes, n_views, tile, vt)) return 0;
+    return gs::raster_bwd_l2_workspace_size(vt, tile);
+}
+
+int gs_rasterize_bwd_l2(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges, int64_t n,
+                        int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
+                        const float* background, const void* schedule, const float* T_final,
+                        const int32_t* n_contrib, const float* images, const float* targets, float* loss,
+                        float* grad2d, int accumulate, void* workspace, size_t workspace_bytes, void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
+        return GS_ERR_ARG;
+    if (!tile_ranges || !T_final || !n_contrib || !images || !targets || !loss || !grad2d || !background ||
+        !isect_gid || !workspace)
+        return GS_ERR_ARG;
+    if (!gs::raster_cfg_ok(tile, block_w, px_per_lane)) return GS_ERR_ARG;
+    if (n > 0 && (!splats || !aligned16(splats))) return GS_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 7u) != 0) return GS_ERR_ARG;
+    for (int c = 0; c < 3; c++)
+        if (!std::isfinite(background[c])) return GS_ERR_ARG;
+    if (workspace_bytes < gs::raster_bwd_l2_workspace_size(vt, tile)) return GS_ERR_WORKSPACE;
+    if (!accumulate) {
+        const hipError_t e = gs::launch_fill_i32(reinterpret_cast<int*>(grad2d), 0,
+                                                 n * n_views * GS_GRAD_FLOATS, as_stream(stream));
+        if (e != hipSuccess) return GS_ERR_HIP;
+    }
+    return status(gs::launch_raster_bwd_l2(tile, block_w, px_per_lane, vt, splats, isect_gid,
+                                           reinterpret_cast<const int2*>(tile_ranges), n, background,
+                                           static_cast<const int*>(schedule), T_final, n_contrib, images, targets,
+                                           3ll * vt.pix_off[n_views], loss, workspace, grad2d,
+                                           as_stream(stream)));
 }
 
 int gs_project_bwd(const float* means, const float* log_scales, const float* quats,

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_project(
     long long N, const float* __restrict__ viewmats, const float* __restrict__ intr, ViewTable vt,
     float near_plane, float far_plane, float eps2d, int tile, int radius_mode, float* __restrict__ splats,
     float* __restrict__ depths, int2* __restrict__ radii, int* __restrict__ tiles,
-    int2* __restrict__ rects, uint8_t* __restrict__ flags)
+    int2* __restrict__ rects, uint8_t* __restrict__ flags, float* __restrict__ g2clear)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,6 +319,28 @@ __global__ __launch_bounds__(256) void k_project(
             const float ex = sqrtf(tau * ge.a), ey = sqrtf(tau * ge.c);
             rec[2] = make_float4(col[2], sigma, __int_as_float(pack_range(u, ex)),
                                  __int_as_float(pack_range(vv, ey)));
+        }
+        // the visible pairs' 2-D gradient records, zeroed for a backward that
+        // accumulates.  In a full wave the 64 consecutive records are one run
+        // of 576 floats, written by 9 coalesced stores in which lane l takes
+        // float 64 k + l if its record's pair is visible; the last wave of the
+        // grid, whose lanes past N have exited and cannot take their share,
+        // writes each visible record from its own lane.
+        if (g2clear) {
+            const uint64_t vm = __ballot(vis);
+            const int lane = __lane_id();
+            if (__ballot(true) == ~0ull) {
+                float* run = g2clear + (o_vg - lane) * GS_GRAD_FLOATS;
+#pragma unroll
+                for (int k = 0; k < GS_GRAD_FLOATS; k++) {
+                    const int f = k * GS_WAVE + lane;
+                    if ((vm >> (f / GS_GRAD_FLOATS)) & 1ull) run[f] = 0.0f;
+                }
+            } else if (vis) {
+                float* rec2 = g2clear + o_vg * GS_GRAD_FLOATS;
+#pragma unroll
+                for (int k = 0; k < GS_GRAD_FLOATS; k++) rec2[k] = 0.0f;
+            }
         }
         depths[o_vg] = ge.pz;
         radii[o_vg] = vis ? make_int2(rx, ry) : make_int2(0, 0);
@@ -592,17 +614,17 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     if (vt.n_views == 1)                                                                               \
         hipLaunchKernelGGL((k_project<DEG, true>), dim3(blocks), dim3(256), 0, stream, means, log_scales, \
                            quats, opac, sh, N, viewmats, intr, vt, near_plane, far_plane, eps2d, tile,   \
-                           radius_mode, splats, depths, radii, tiles, rects, flags);                     \
+                           radius_mode, splats, depths, radii, tiles, rects, flags, g2clear);            \
     else                                                                                               \
         hipLaunchKernelGGL((k_project<DEG, false>), dim3(blocks), dim3(256), 0, stream, means,            \
                            log_scales, quats, opac, sh, N, viewmats, intr, vt, near_plane, far_plane,     \
-                           eps2d, tile, radius_mode, splats, depths, radii, tiles, rects, flags)
+                           eps2d, tile, radius_mode, splats, depths, radii, tiles, rects, flags, g2clear)
 
 hipError_t launch_project(int deg, const float* means, const float* log_scales, const float* quats,
                           const float* opac, const float* sh, long long N, const float* viewmats,
                           const float* intr, const ViewTable& vt, float near_plane, float far_plane,
                           float eps2d, int tile, int radius_mode, float* splats, float* depths, int2* radii,
-                          int* tiles, int2* rects, uint8_t* flags, hipStream_t stream)
+                          int* tiles, int2* rects, uint8_t* flags, float* g2clear, hipStream_t stream)
 {
     if (N == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((N + 255) / 256);

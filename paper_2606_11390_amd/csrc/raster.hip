@@ -268,7 +268,12 @@ __device__ __forceinline__ void fwd_unit(const ViewTable& vt, int gt, int wit,
     }
 }
 
-template <int TS, int BW, int P, bool HAS_DA>
+// L2: the upstream image gradient is that of the L2 loss, formed here from
+// the image and the target (dimg then holds the image) as the loss kernel
+// forms it, 2 (img - target) / n; the wave's share of the loss sum (float
+// over its pixels, like the loss kernel's per-thread sums) goes to
+// part[tile * waves per tile + wave].
+template <int TS, int BW, int P, bool HAS_DA, bool L2 = false>
 __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                                          const float* __restrict__ splats,
                                          const int* __restrict__ gids,
@@ -277,7 +282,9 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
                                          const int* __restrict__ nlast,
                                          const float* __restrict__ dimg,
                                          const float* __restrict__ dalpha,
-                                         float* __restrict__ grad2d, WaveStage* __restrict__ stage)
+                                         float* __restrict__ grad2d, WaveStage* __restrict__ stage,
+                                         const float* __restrict__ tgt = nullptr, float l2scale = 0.0f,
+                                         double* __restrict__ part = nullptr)
 {
     using L = Layout<TS, BW, P>;
     const Unit U = unit_of<TS, BW, P>(vt, gt, wit);
@@ -289,6 +296,7 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
     float fx[P], T[P], S0[P], S1[P], S2[P], g0[P], g1[P], g2[P], gA[P];
     int last[P];
     int kmax = 0;
+    float lsum = 0.0f;
 #pragma unroll
     for (int p = 0; p < P; p++) {
         fx[p] = (float)(U.px0 + p) + 0.5f;
@@ -296,15 +304,31 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
         const long long pix = (long long)U.py * W + U.px0 + p;
         T[p] = in ? Tfin[po + pix] : 1.0f;
         last[p] = in ? nlast[po + pix] : 0;
-        g0[p] = in ? dimg[3 * po + pix] : 0.0f;
-        g1[p] = in ? dimg[3 * po + plane + pix] : 0.0f;
-        g2[p] = in ? dimg[3 * po + 2 * plane + pix] : 0.0f;
+        if (L2) {
+            const float e0 = in ? dimg[3 * po + pix] - tgt[3 * po + pix] : 0.0f;
+            const float e1 = in ? dimg[3 * po + plane + pix] - tgt[3 * po + plane + pix] : 0.0f;
+            const float e2 = in ? dimg[3 * po + 2 * plane + pix] - tgt[3 * po + 2 * plane + pix] : 0.0f;
+            g0[p] = l2scale * e0;
+            g1[p] = l2scale * e1;
+            g2[p] = l2scale * e2;
+            lsum = __builtin_fmaf(e0, e0, lsum);
+            lsum = __builtin_fmaf(e1, e1, lsum);
+            lsum = __builtin_fmaf(e2, e2, lsum);
+        } else {
+            g0[p] = in ? dimg[3 * po + pix] : 0.0f;
+            g1[p] = in ? dimg[3 * po + plane + pix] : 0.0f;
+            g2[p] = in ? dimg[3 * po + 2 * plane + pix] : 0.0f;
+        }
         // d(1 - T_N)/d alpha_k = T_N / (1 - alpha_k): keep gA * T_N
         gA[p] = (HAS_DA && in) ? dalpha[po + pix] * T[p] : 0.0f;
         S0[p] = bg0;
         S1[p] = bg1;
         S2[p] = bg2;
         kmax = max(kmax, last[p]);
+    }
+    if (L2) {
+        const float ws = wave_sum(lsum);
+        if (__lane_id() == 0) part[(size_t)gt * L::WPT + wit] = (double)ws;
     }
     // the wave maximum is uniform; readfirstlane lets the compiler know, so the
     // batch loop's control stays scalar
@@ -511,6 +535,70 @@ __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_b
                                 grad2d, &stage[wit]);
 }
 
+// the backward with the L2 loss's image gradient formed from images and targets
+template <int TS, int BW, int P>
+__global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_bwd_l2(
+    ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
+    const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
+    const int* __restrict__ order, const float* __restrict__ Tfin, const int* __restrict__ nlast,
+    const float* __restrict__ img, const float* __restrict__ tgt, float l2scale, double* __restrict__ part,
+    float* __restrict__ grad2d)
+{
+    __shared__ WaveStage stage[Layout<TS, BW, P>::WPT];
+    const int gt = tile_of_block(order, vt.total_tiles);
+    if (gt < 0) return;
+    const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
+    bwd_unit<TS, BW, P, false, true>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, img,
+                                     nullptr, grad2d, &stage[wit], tgt, l2scale, part);
+}
+
+// Sum of the per-wave partials in a fixed order: blocks of L2_SPAN
+// consecutive partials (each thread's L2_ITEMS loads in flight at once, then
+// a fixed tree), then one block over the block sums.
+constexpr int L2_THREADS = 256;
+constexpr int L2_ITEMS = 16;
+constexpr long long L2_SPAN = (long long)L2_THREADS * L2_ITEMS;
+
+__device__ __forceinline__ double block_tree_sum(double x, double* s)
+{
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = L2_THREADS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    return s[0];
+}
+
+__global__ __launch_bounds__(L2_THREADS) void k_l2_parts_sum(const double* __restrict__ part, long long np,
+                                                             double* __restrict__ out)
+{
+    __shared__ double s[L2_THREADS];
+    const long long base = (long long)blockIdx.x * L2_SPAN + threadIdx.x;
+    double v[L2_ITEMS];
+#pragma unroll
+    for (int k = 0; k < L2_ITEMS; k++) {
+        const long long i = base + (long long)k * L2_THREADS;
+        v[k] = i < np ? part[i] : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < L2_ITEMS; k++) acc += v[k];
+    const double t = block_tree_sum(acc, s);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// loss = (sum of the nb block sums, strided per thread, then a fixed tree) / n
+__global__ __launch_bounds__(L2_THREADS) void k_l2_parts_final(const double* __restrict__ sums, int nb,
+                                                               double inv_n, float* __restrict__ loss)
+{
+    __shared__ double s[L2_THREADS];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += L2_THREADS) acc += sums[i];
+    const double t = block_tree_sum(acc, s);
+    if (threadIdx.x == 0) loss[0] = (float)(t * inv_n);
+}
+
 template <int TS, int BW, int P, bool HAS_DA>
 __global__ __launch_bounds__(GS_WAVE) void k_raster_bwd_persistent(
     ViewTable vt, const float* __restrict__ splats, const int* __restrict__ gids,
@@ -603,6 +691,31 @@ hipError_t bwd_cfg(const ViewTable& vt, const float* splats, const int* gids, co
     return hipGetLastError();
 }
 
+template <int TS, int BW, int P>
+hipError_t bwd_l2_cfg(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges, long long N,
+                      const float* bg, const int* order, const float* Tfin, const int* nlast, const float* img,
+                      const float* tgt, long long n_elems, float* loss, double* part, float* grad2d,
+                      hipStream_t st)
+{
+    using L = Layout<TS, BW, P>;
+    // the same scale as the loss kernel's gradient
+    const float scale = n_elems > 0 ? (float)(2.0 / (double)n_elems) : 0.0f;
+    if (vt.total_tiles > 0)
+        hipLaunchKernelGGL((k_raster_bwd_l2<TS, BW, P>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st, vt,
+                           splats, gids, ranges, N, bg[0], bg[1], bg[2], order, Tfin, nlast, img, tgt, scale,
+                           part, grad2d);
+    // the block sums follow the largest possible number of per-wave partials
+    const long long np = (long long)vt.total_tiles * L::WPT;
+    const long long np_max = (long long)vt.total_tiles * (TS * TS / GS_WAVE);
+    const int nb = (int)((np + L2_SPAN - 1) / L2_SPAN);
+    double* sums = part + np_max;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_l2_parts_sum, dim3(nb), dim3(L2_THREADS), 0, st, (const double*)part, np, sums);
+    hipLaunchKernelGGL(k_l2_parts_final, dim3(1), dim3(L2_THREADS), 0, st, (const double*)sums, nb,
+                       n_elems > 0 ? 1.0 / (double)n_elems : 0.0, loss);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Wave blocks available per tile edge (block width, pixels per lane); the
@@ -672,5 +785,40 @@ hipError_t launch_raster_bwd(int tile, int bw, int ppl, const ViewTable& vt, con
     }
 }
 #undef GS_BWD
+
+// one partial per wave (at most tile^2 / 64 waves per tile: every wave covers
+// at least 64 pixels), then one sum per L2_SPAN partials
+size_t raster_bwd_l2_workspace_size(const ViewTable& vt, int tile)
+{
+    const size_t np = (size_t)vt.total_tiles * (size_t)(tile * tile / GS_WAVE);
+    return sizeof(double) * (np + (np + L2_SPAN - 1) / L2_SPAN);
+}
+
+#define GS_BWDL2(TS, BW, P) \
+    return bwd_l2_cfg<TS, BW, P>(vt, splats, gids, ranges, N, bg, order, Tfin, nlast, img, tgt, n_elems, loss, \
+                                 (double*)part, grad2d, st)
+
+hipError_t launch_raster_bwd_l2(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
+                                const int* gids, const int2* ranges, long long N, const float* bg,
+                                const int* order, const float* Tfin, const int* nlast, const float* img,
+                                const float* tgt, long long n_elems, float* loss, void* part, float* grad2d,
+                                hipStream_t st)
+{
+    if (bw == 0) { bw = 8; ppl = 1; }
+    switch (tile) {
+    case 8: GS_BWDL2(8, 8, 1);
+    case 16:
+        if (bw == 16 && ppl == 4) GS_BWDL2(16, 16, 4);
+        if (bw == 16 && ppl == 2) GS_BWDL2(16, 16, 2);
+        if (bw == 16) GS_BWDL2(16, 16, 1);
+        GS_BWDL2(16, 8, 1);
+    default:
+        if (bw == 32) GS_BWDL2(32, 32, 4);
+        if (bw == 16 && ppl == 2) GS_BWDL2(32, 16, 2);
+        if (bw == 16) GS_BWDL2(32, 16, 4);
+        GS_BWDL2(32, 8, 1);
+    }
+}
+#undef GS_BWDL2
 
 }  // namespace gs

@@ -4,8 +4,12 @@
 SH degree and set of view sizes, and runs the C-ABI calls in order on torch's
 current stream:
 
-    gs_project -> gs_bin_sort -> [gs_tile_schedule] -> gs_rasterize_fwd
-    -> gs_loss_l2 -> gs_rasterize_bwd -> gs_project_bwd
+    gs_project (also zeroing the visible pairs' 2-D gradient records)
+    -> gs_bin_sort -> [gs_tile_schedule] -> gs_rasterize_fwd
+    -> gs_rasterize_bwd_l2 (the L2 loss and the rasteriser backward in one
+       pass, accumulating into those records; gs_loss_l2 -> gs_rasterize_bwd
+       when ``fuse_l2`` is off or the backward runs on the work queue)
+    -> gs_project_bwd
 
 The rasterisers' tile order is chosen per pass (``order``, ``order_bwd``):
 "tile" (one workgroup per tile in tile order), "xcd" (a static order giving
@@ -38,9 +42,11 @@ N_XCD = 8
 class Renderer:
     def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
                  background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda",
-                 radius_mode=0, order=None, order_bwd=None):
+                 radius_mode=0, order=None, order_bwd=None, fuse_l2=True):
         # screen box rule of the projection (GS_RADIUS_*)
         self.radius_mode = int(radius_mode)
+        # step(): L2 loss formed inside the rasteriser backward (d_images not stored)
+        self.fuse_l2 = bool(fuse_l2)
         # wave pixel blocks (width, pixels per lane) of the forward and backward rasterisers
         self.block = tuple(int(x) for x in block)
         self.block_bwd = self.block if block_bwd is None else tuple(int(x) for x in block_bwd)
@@ -80,6 +86,7 @@ class Renderer:
         self.d_images = e(3 * self.pixels)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.loss_ws = e(max(1, B.loss_workspace_size(3 * self.pixels)), dt=torch.uint8)
+        self.l2_ws = e(max(8, B.rasterize_bwd_l2_workspace_size(self.sizes, self.tile)), dt=torch.uint8)
         self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
         self.schedule = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
         self.schedule_xcd = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
@@ -104,11 +111,13 @@ class Renderer:
         return sum(t.numel() * t.element_size() for t in self.__dict__.values() if isinstance(t, torch.Tensor))
 
     # ------------------------------------------------------------ the stages
-    def project(self, P, cams):
+    def project(self, P, cams, clear_grad2d=False):
+        """``clear_grad2d``: also zero the visible pairs' 2-D gradient records,
+        so that the backward of this step may accumulate into them."""
         B.project(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
                   cams["viewmats"], cams["intrinsics"], self.sizes, self.near, self.far, self.eps2d,
                   self.tile, self.splats, self.depths, self.radii, self.tiles_touched, self.tile_rects,
-                  self.flags, self.radius_mode)
+                  self.flags, self.radius_mode, grad2d_clear=self.grad2d if clear_grad2d else None)
 
     def bin_sort(self):
         B.bin_sort(self.tile_rects, self.depths, self.n, self.sizes, self.tile, self.capacity, self.workspace,
@@ -151,11 +160,31 @@ class Renderer:
     def loss_l2(self, targets):
         B.loss_l2(self.images, targets, self.loss, self.d_images, self.loss_ws)
 
-    def forward(self, P, cams, images=None):
+    @property
+    def fused_l2_active(self):
+        return self.fuse_l2 and self.order_bwd != "queue"
+
+    def loss_raster_bwd(self, targets, accumulate=False):
+        """L2 loss of ``images`` against ``targets`` and the rasteriser
+        backward of its gradient in one pass (``self.d_images`` is not
+        written)."""
+        s, _ = self._sched(self.order_bwd)
+        B.rasterize_bwd_l2(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
+                           self.background, s, self.T_final, self.n_contrib, self.images, targets, self.loss,
+                           self.grad2d, self.l2_ws, accumulate=accumulate, block=self.block_bwd)
+
+    def loss_and_raster_bwd(self, targets, accumulate=False):
+        if self.fused_l2_active:
+            self.loss_raster_bwd(targets, accumulate)
+        else:
+            self.loss_l2(targets)
+            self.raster_bwd(self.d_images, accumulate=accumulate)
+
+    def forward(self, P, cams, images=None, clear_grad2d=False):
         """Projection, binning and compositing of every view into ``images``
         (default: the renderer's own buffer).  T_final and n_contrib stay in
         the renderer for the backward."""
-        self.project(P, cams)
+        self.project(P, cams, clear_grad2d)
         self.bin_sort()
         self.raster_fwd(images)
         return self.images if images is None else images
@@ -178,9 +207,11 @@ class Renderer:
     def step(self, P, cams, targets, grads):
         """Forward, L2 loss against packed ``targets`` and backward into
         ``grads`` (dict of tensors shaped like the parameters)."""
-        self.forward(P, cams)
-        self.loss_l2(targets)
-        return self.backward(P, cams, self.d_images, grads)
+        # the projection zeroes the 2-D gradient records the backward adds to
+        self.forward(P, cams, clear_grad2d=True)
+        self.loss_and_raster_bwd(targets, accumulate=True)
+        self.project_bwd(P, cams, grads)
+        return grads
 
     def train_step(self, P, cams, targets, grads, optimizer, fused=False):
         """``step`` followed by the optimizer's fused update of ``P`` (the
@@ -191,9 +222,8 @@ class Renderer:
             self.step(P, cams, targets, grads)
             optimizer.update(grads)
             return
-        self.forward(P, cams)
-        self.loss_l2(targets)
-        self.raster_bwd(self.d_images)
+        self.forward(P, cams, clear_grad2d=True)
+        self.loss_and_raster_bwd(targets, accumulate=True)
         optimizer.update_fused(self, P, cams)
 
     def fit_capacity(self, P, cams, headroom=1.25):
@@ -454,8 +484,11 @@ def autotune(P, cams, targets, sh_degree, sizes, tiles=(8, 16, 32), steps=5, cac
                     r.order = r.order_bwd = order
                     r.raster_fwd()
                     fwd_t.setdefault((order, blk), []).append(_time_ms(r.raster_fwd, steps))
-                    r.raster_bwd(r.d_images)
-                    bwd_t.setdefault((order, blk), []).append(_time_ms(lambda: r.raster_bwd(r.d_images), steps))
+                    # the loss and the backward as the step runs them (in one
+                    # pass unless the backward takes the work queue)
+                    r.loss_and_raster_bwd(targets)
+                    bwd_t.setdefault((order, blk), []).append(
+                        _time_ms(lambda: r.loss_and_raster_bwd(targets), steps))
         fwd_ms = {k: float(np.median(v)) for k, v in fwd_t.items()}
         bwd_ms = {k: float(np.median(v)) for k, v in bwd_t.items()}
         # isolated launches see other cache states than the captured step: the

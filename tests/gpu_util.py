@@ -71,21 +71,28 @@ def oracle_binning(arrs, sizes, tile):
 
 
 # ------------------------------------------------------------------- GPU side
-def gpu_project(scene, tile, near=0.01, far=1e10, eps2d=0.3, radius_mode=0):
+def gpu_project(scene, tile, near=0.01, far=1e10, eps2d=0.3, radius_mode=0, clear=None):
+    """``clear``: an initial [V][N][9] 2-D gradient buffer handed to the
+    projection as grad2d_clear; its contents after the call are returned as
+    ``grad2d``."""
     V, N = scene.n_views, scene.n
     out = dict(splats=torch.zeros(V * N * 12, device="cuda"), depths=torch.zeros(V * N, device="cuda"),
                radii=torch.zeros(V * N * 2, dtype=torch.int32, device="cuda"),
                tiles=torch.zeros(V * N, dtype=torch.int32, device="cuda"),
                rects=torch.zeros(V * N * 2, dtype=torch.int32, device="cuda"),
                flags=torch.zeros(V * N, dtype=torch.uint8, device="cuda"))
+    g2 = None if clear is None else dev(np.asarray(clear, np.float32).reshape(-1))
     B.project(dev(scene.means), dev(scene.log_scales), dev(scene.quats), dev(scene.opacity_logits),
               dev(scene.sh), scene.sh_degree, dev(scene.viewmats), dev(scene.intrinsics), scene.sizes, near,
               far, eps2d, tile, out["splats"], out["depths"], out["radii"], out["tiles"], out["rects"],
-              out["flags"], radius_mode)
+              out["flags"], radius_mode, grad2d_clear=g2)
     h = {k: host(v) for k, v in out.items()}
-    return dict(splats=h["splats"].reshape(V, N, 12), depths=h["depths"].reshape(V, N),
-                radii=h["radii"].reshape(V, N, 2), tiles=h["tiles"].reshape(V, N),
-                rects=h["rects"].reshape(V, N, 2), flags=h["flags"].reshape(V, N))
+    res = dict(splats=h["splats"].reshape(V, N, 12), depths=h["depths"].reshape(V, N),
+               radii=h["radii"].reshape(V, N, 2), tiles=h["tiles"].reshape(V, N),
+               rects=h["rects"].reshape(V, N, 2), flags=h["flags"].reshape(V, N))
+    if g2 is not None:
+        res["grad2d"] = host(g2).reshape(V, N, 9)
+    return res
 
 
 def gpu_bin_sort(arrs, sizes, tile, capacity):

@@ -47,7 +47,7 @@ def test_host_side_argument_checks():
     # gs_project: negative N, bad degree, bad tile, bad view size, bad near/far
     args = lambda **kw: [kw.get("means", p), p, p, p, p, kw.get("n", 10), kw.get("deg", 0), p, p,
                          kw.get("sizes", szp), kw.get("V", 1), kw.get("near", 0.01), kw.get("far", 1e10),
-                         0.3, kw.get("tile", 16), kw.get("mode", 0), p, p, p, p, p, p, None]
+                         0.3, kw.get("tile", 16), kw.get("mode", 0), p, p, p, p, p, p, None, None]
     assert L.gs_project(*args(n=-1)) == -1
     assert L.gs_project(*args(deg=4)) == -1
     assert L.gs_project(*args(tile=12)) == -1

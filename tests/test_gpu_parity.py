@@ -125,6 +125,25 @@ def test_project_parity(name, tile):
         assert (e_fac.max() if m.any() else 0) <= 1e-5
 
 
+@pytest.mark.parametrize("name,tile", [("ragged", 16), ("multi", 8)])
+def test_project_clears_visible_grad2d(name, tile):
+    """With grad2d_clear the projection zeroes exactly the 2-D gradient
+    records of the pairs it marks visible, leaves every other record as it
+    was, and changes none of its own outputs."""
+    s = scene(name)
+    V, N = s.n_views, s.n
+    init = np.random.default_rng(9).standard_normal((V, N, 9)).astype(np.float32) + np.float32(3.0)
+    plain = G.gpu_project(s, tile)
+    g = G.gpu_project(s, tile, clear=init)
+    vis = (g["flags"] & 1).astype(bool)
+    G.say(f"[project clear] {name} tile={tile}: {int(vis.sum())} of {V * N} records cleared")
+    assert vis.any() and (~vis).any()
+    assert not g["grad2d"][vis].any()
+    np.testing.assert_array_equal(g["grad2d"][~vis], init[~vis])
+    for k in ("splats", "depths", "radii", "tiles", "rects", "flags"):
+        np.testing.assert_array_equal(g[k], plain[k])
+
+
 @pytest.mark.parametrize("name,tile", CASES + [("wide", 8)])
 def test_bin_sort_bit_exact(name, tile):
     s = scene(name)
@@ -373,6 +392,71 @@ def test_raster_bwd_parity(name, tile, with_alpha, persistent):
         ref = np.stack([o["u"], o["v"], o["conic"][0], o["conic"][1], o["conic"][2], o["sigma"],
                         o["rgb"][0], o["rgb"][1], o["rgb"][2]], axis=1)
         errs = [G.rel_l2(g[v][:, j], ref[:, j]) for j in range(9)]
+        G.say(f"  view {v}: rel L2 (u v A B C sigma r g b) " + " ".join(f"{e:.1e}" for e in errs))
+        assert max(errs) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name,tile,order,block", [("tiny", 16, "tile", (0, 0)), ("ragged", 32, "heavy", (16, 2)),
+                                                    ("multi", 8, "xcd", (0, 0)), ("hd", 16, "heavy", (16, 4)),
+                                                    ("multi", 16, "tile", (16, 1))])
+def test_raster_bwd_l2_parity(name, tile, order, block):
+    """The L2 loss fused into the rasteriser backward against the two separate
+    calls (same loss to 1e-6, same 2-D gradients up to atomic summation
+    order) and against the oracle's loss and backward.  Targets equal the
+    image at pixels the oracle marks ambiguous, so no gradient flows there."""
+    import torch
+    from paper_2606_11390_amd import binding as B
+    s = scene(name)
+    bg = (0.0, 0.0, 0.0)
+    _, projs, arrs, keys, vals, ranges, offs = oracle_stage(name, tile)
+    rng = np.random.default_rng(17)
+    fw = oracle_fwd(name, tile, bg)
+    imgs, tgts = [], []
+    for sp, f in fw:
+        img = f["img"].astype(np.float32)
+        tgt = rng.uniform(0, 1, img.shape).astype(np.float32)
+        amb = f["margin"] < PIX_MARGIN
+        tgt[:, amb] = img[:, amb]
+        imgs.append(img)
+        tgts.append(tgt)
+    G.say(f"[raster_bwd_l2] {name} tile={tile} order={order} block={block}")
+    V, N = s.n_views, s.n
+    _, toff, poff = B.tile_grid(s.sizes, tile)
+    T_all = int(toff[-1])
+    sp_d = G.dev(arrs["splats"].reshape(-1))
+    gid_d = G.dev(np.asarray(vals, np.int32))
+    rg = G.dev(np.asarray(ranges, np.int32).reshape(-1))
+    sched, _ = G._order(order, rg, T_all)
+    Tf = G.dev(np.concatenate([f["T"].reshape(-1) for _, f in fw]), np.float32)
+    last = G.dev(np.concatenate([f["last"].reshape(-1) for _, f in fw]), np.int32)
+    im_d = G.dev(np.concatenate([a.reshape(-1) for a in imgs]))
+    tg_d = G.dev(np.concatenate([a.reshape(-1) for a in tgts]))
+    # fused
+    loss_f = torch.zeros(1, device="cuda")
+    g_f = torch.full((V * N * 9,), float("nan"), device="cuda")
+    ws = torch.empty(B.rasterize_bwd_l2_workspace_size(s.sizes, tile), dtype=torch.uint8, device="cuda")
+    B.rasterize_bwd_l2(sp_d, gid_d, rg, N, s.sizes, tile, bg, sched, Tf, last, im_d, tg_d, loss_f, g_f, ws,
+                       block=block)
+    # separate calls
+    loss_u = torch.zeros(1, device="cuda")
+    d_u = torch.empty_like(im_d)
+    lws = torch.empty(B.loss_workspace_size(im_d.numel()), dtype=torch.uint8, device="cuda")
+    B.loss_l2(im_d, tg_d, loss_u, d_u, lws)
+    g_u = torch.zeros(V * N * 9, device="cuda")
+    B.rasterize_bwd(sp_d, gid_d, rg, N, s.sizes, tile, bg, sched, None, Tf, last, d_u, None, g_u, block=block)
+    L, drefs = oracle.l2_loss(imgs, tgts)
+    lf, lu = float(G.host(loss_f)[0]), float(G.host(loss_u)[0])
+    gf, gu = G.host(g_f).reshape(V, N, 9), G.host(g_u).reshape(V, N, 9)
+    e_sep = max(G.rel_l2(gf[..., j], gu[..., j]) for j in range(9))
+    G.say(f"  loss fused {lf:.9g} separate {lu:.9g} oracle {L:.9g}; grad2d vs separate {e_sep:.1e}")
+    assert lf == pytest.approx(lu, rel=1e-6) and lf == pytest.approx(L, rel=1e-6)
+    assert e_sep <= 1e-6
+    for v, (sp, f) in enumerate(fw):
+        W, H = (int(x) for x in s.sizes[v])
+        o = oracle.raster_bwd(W, H, tile, ranges[offs[v]:offs[v + 1]], vals, sp, drefs[v], None, bg)
+        ref = np.stack([o["u"], o["v"], o["conic"][0], o["conic"][1], o["conic"][2], o["sigma"],
+                        o["rgb"][0], o["rgb"][1], o["rgb"][2]], axis=1)
+        errs = [G.rel_l2(gf[v][:, j], ref[:, j]) for j in range(9)]
         G.say(f"  view {v}: rel L2 (u v A B C sigma r g b) " + " ".join(f"{e:.1e}" for e in errs))
         assert max(errs) <= GRAD_TOL
 
