@@ -457,12 +457,17 @@ __device__ __forceinline__ unsigned long long block_excl_scan_256_u64(unsigned l
 // sums the tile counts of the visible pairs' rectangles (in depth order, as
 // the last depth pass wrote them) per block (64-bit: a pair may cover up to
 // 2^32 - 1 tiles)
+//
+// It also zeroes the tile ranges (the range pass only writes non-empty tiles).
 __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ n_dev,
                                                             const int2* __restrict__ srect,
-                                                            unsigned long long* __restrict__ part)
+                                                            unsigned long long* __restrict__ part,
+                                                            int2* __restrict__ ranges, long long n_ranges)
 {
     __shared__ unsigned long long s_tmp[RS_WAVES];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+    for (long long i = (long long)b * SC_THREADS + t; i < n_ranges; i += (long long)nb * SC_THREADS)
+        ranges[i] = make_int2(0, 0);
     uint32_t beg, end;
     block_span(*n_dev, nb, b, beg, end);
     unsigned long long s = 0;
@@ -481,63 +486,54 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __re
     if (t == 0) part[b] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_spine(const unsigned long long* __restrict__ part, int nb,
-                                                     unsigned long long* __restrict__ part_ex,
-                                                     uint32_t capacity, uint32_t* __restrict__ cnt,
-                                                     int* __restrict__ info)
-{
-    __shared__ unsigned long long s_w[16];
-    const int t = threadIdx.x, lane = __lane_id(), w = t / GS_WAVE;
-    const int nw = blockDim.x / GS_WAVE;
-    unsigned long long carry = 0;
-    for (int s0 = 0; s0 < nb; s0 += blockDim.x) {
-        const int i = s0 + t;
-        const unsigned long long x = i < nb ? part[i] : 0ull;
-        unsigned long long inc = x;
-        for (int o = 1; o < GS_WAVE; o <<= 1) {
-            const unsigned long long y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
-        }
-        if (lane == GS_WAVE - 1) s_w[w] = inc;
-        __syncthreads();
-        unsigned long long before = 0, total = 0;
-        for (int k = 0; k < nw; k++) {
-            if (k < w) before += s_w[k];
-            total += s_w[k];
-        }
-        if (i < nb) part_ex[i] = carry + before + inc - x;
-        carry += total;
-        __syncthreads();
-    }
-    if (t == 0) {
-        const unsigned long long cap = capacity;
-        cnt[1] = (uint32_t)(carry < cap ? carry : cap);
-        info[GS_INFO_VISIBLE] = (int)cnt[0];
-        info[GS_INFO_ISECT] = (int)(carry < 0x7FFFFFFFull ? carry : 0x7FFFFFFFull);
-        info[GS_INFO_OVERFLOW] = carry > cap ? 1 : 0;
-    }
-}
-
 constexpr int EMIT_SPAN = 2048;   // output slots per emission workgroup
+
+// sum of one uint64 per thread over a 256-thread block, returned to every thread
+__device__ __forceinline__ unsigned long long block_sum_256_u64(unsigned long long x, unsigned long long* s_tmp)
+{
+    for (int o = GS_WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (__lane_id() == 0) s_tmp[threadIdx.x / GS_WAVE] = x;
+    __syncthreads();
+    unsigned long long total = 0;
+    for (int i = 0; i < RS_WAVES; i++) total += s_tmp[i];
+    __syncthreads();
+    return total;
+}
 
 // Writes offs[i] (first output slot of source i, clamped to the capacity) and,
 // for every emission workgroup k, bsrc[k] = the source whose slots contain
 // slot k * EMIT_SPAN (each source has at least one slot, so exactly one does);
-// bsrc[last] = the source holding the last emitted slot m - 1, where m
-// (m_dev) is the intersection count clamped to the capacity.
+// bsrc[last] = the source holding the last emitted slot m - 1, where m is the
+// intersection count clamped to the capacity.  Each block forms its own
+// carry (the tile counts of the blocks before it) and the total from the
+// nb per-block sums, so no separate scan of them runs; block 0 publishes the
+// counts (cnt[1] = m, the info words).
 __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const int2* __restrict__ srect,
-                                                          const uint32_t* __restrict__ n_dev,
-                                                          const unsigned long long* __restrict__ part_ex,
-                                                          uint32_t capacity, const uint32_t* __restrict__ m_dev,
-                                                          uint32_t* __restrict__ offs,
+                                                          const unsigned long long* __restrict__ part,
+                                                          uint32_t capacity, uint32_t* __restrict__ cnt,
+                                                          int* __restrict__ info, uint32_t* __restrict__ offs,
                                                           uint32_t* __restrict__ bsrc, uint32_t last)
 {
-    const unsigned long long m = *m_dev;
     __shared__ unsigned long long s_tmp[RS_WAVES];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+    unsigned long long before = 0, all = 0;
+    for (int i = t; i < nb; i += SC_THREADS) {
+        const unsigned long long x = part[i];
+        all += x;
+        if (i < b) before += x;
+    }
+    unsigned long long carry = block_sum_256_u64(before, s_tmp);
+    const unsigned long long total = block_sum_256_u64(all, s_tmp);
+    const unsigned long long cap = capacity;
+    const unsigned long long m = total < cap ? total : cap;
+    if (b == 0 && t == 0) {
+        cnt[1] = (uint32_t)m;
+        info[GS_INFO_VISIBLE] = (int)cnt[0];
+        info[GS_INFO_ISECT] = (int)(total < 0x7FFFFFFFull ? total : 0x7FFFFFFFull);
+        info[GS_INFO_OVERFLOW] = total > cap ? 1 : 0;
+    }
     uint32_t beg, end;
-    block_span(*n_dev, nb, b, beg, end);
-    unsigned long long carry = part_ex[b];
+    block_span(cnt[0], nb, b, beg, end);
     for (uint32_t cb = beg; cb < end; cb += SC_THREADS * SC_ITEMS) {
         // thread t owns SC_ITEMS consecutive elements
         uint32_t x[SC_ITEMS];
@@ -793,7 +789,7 @@ uint32_t bsrc_last(unsigned long long cap) { return (uint32_t)((cap + EMIT_SPAN 
 
 struct BinWs {
     uint32_t *dk0, *dv0, *dk1, *dv1, *offs, *tk, *tv, *hist, *dtot, *cnt, *bsrc;
-    unsigned long long *part, *part_ex;
+    unsigned long long* part;
     int2* srect;
     size_t bytes;
 };
@@ -818,7 +814,6 @@ BinWs bin_layout(char* base, unsigned long long vn, unsigned long long cap)
     w.dtot = (uint32_t*)take(4 * (1u << RS_MAX_BITS));
     w.part = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
     w.srect = (int2*)take(8 * vn);
-    w.part_ex = (unsigned long long*)take(8 * RS_MAX_BLOCKS);
     w.cnt = (uint32_t*)take(4 * 16);
     w.bsrc = (uint32_t*)take(4 * ((size_t)bsrc_last(cap) + 1));
     w.bytes = o;
@@ -875,11 +870,10 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
     const uint32_t* pids = vi;   // visible pairs in (depth, view, Gaussian) order
 
     // 2. scan of tiles_touched in that order
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb_d), dim3(SC_THREADS), 0, st, w.cnt + 0, w.srect, w.part);
-    hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, st, w.part, nb_d, w.part_ex, (uint32_t)cap,
-                       w.cnt, info);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb_d), dim3(SC_THREADS), 0, st, w.srect, w.cnt + 0, w.part_ex,
-                       (uint32_t)cap, w.cnt + 1, w.offs, w.bsrc, bsrc_last(cap));
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb_d), dim3(SC_THREADS), 0, st, w.cnt + 0, w.srect, w.part, ranges,
+                       (long long)vt.total_tiles);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb_d), dim3(SC_THREADS), 0, st, w.srect, w.part, (uint32_t)cap, w.cnt,
+                       info, w.offs, w.bsrc, bsrc_last(cap));
 
     // 3. emission; 4. tile passes (the last one lands in the caller's arrays)
     const int tbits = bits_for((unsigned long long)vt.total_tiles);
@@ -909,9 +903,7 @@ hipError_t launch_bin_sort(const int2* rects, const float* depths, long long N, 
         uint32_t* tv = tvi; tvi = tvo; tvo = tv;
     }
 
-    // 5. ranges
-    const long long nr = 2ll * vt.total_tiles;
-    if ((e = fill_i32((int*)ranges, 0, nr, st)) != hipSuccess) return e;
+    // 5. ranges (zeroed by the scan's first kernel)
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 1023) / 1024)), dim3(256), 0, st, isect_tile, w.cnt,
                        (uint32_t)vt.total_tiles, ranges);
     return hipGetLastError();

@@ -229,10 +229,17 @@ __device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v,
     p = __builtin_fmaf(-(step * m), __builtin_amdgcn_rcpf(den), p);
 }
 
+// Maximum of x over the 64 lanes of the wave, returned uniformly (DPP steps
+// as in wave_sum; a lane a step does not write keeps its own value)
 __device__ __forceinline__ int wave_max_i(int x)
 {
-    for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o));
-    return x;
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x140, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x142, 0xA, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(x, 63);
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }

@@ -297,17 +297,36 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
     int last[P];
     int kmax = 0;
     float lsum = 0.0f;
+    // The pixel inputs are loaded unconditionally, so that all of them are in
+    // flight at once (a load guarded by the pixel test becomes a branch with
+    // a wait of its own, one memory round trip per plane); a pixel outside
+    // the view reads the view's first pixel and is then masked.
+    bool in[P];
+    float tv[P], a0v[P], a1v[P], a2v[P], b0v[P], b1v[P], b2v[P], dav[P];
+    int lv[P];
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+        in[p] = U.px0 + p < W && U.py < H;
+        const long long pix = in[p] ? (long long)U.py * W + U.px0 + p : 0;
+        tv[p] = Tfin[po + pix];
+        lv[p] = nlast[po + pix];
+        a0v[p] = dimg[3 * po + pix];
+        a1v[p] = dimg[3 * po + plane + pix];
+        a2v[p] = dimg[3 * po + 2 * plane + pix];
+        b0v[p] = L2 ? tgt[3 * po + pix] : 0.0f;
+        b1v[p] = L2 ? tgt[3 * po + plane + pix] : 0.0f;
+        b2v[p] = L2 ? tgt[3 * po + 2 * plane + pix] : 0.0f;
+        dav[p] = HAS_DA ? dalpha[po + pix] : 0.0f;
+    }
 #pragma unroll
     for (int p = 0; p < P; p++) {
         fx[p] = (float)(U.px0 + p) + 0.5f;
-        const bool in = U.px0 + p < W && U.py < H;
-        const long long pix = (long long)U.py * W + U.px0 + p;
-        T[p] = in ? Tfin[po + pix] : 1.0f;
-        last[p] = in ? nlast[po + pix] : 0;
+        T[p] = in[p] ? tv[p] : 1.0f;
+        last[p] = in[p] ? lv[p] : 0;
         if (L2) {
-            const float e0 = in ? dimg[3 * po + pix] - tgt[3 * po + pix] : 0.0f;
-            const float e1 = in ? dimg[3 * po + plane + pix] - tgt[3 * po + plane + pix] : 0.0f;
-            const float e2 = in ? dimg[3 * po + 2 * plane + pix] - tgt[3 * po + 2 * plane + pix] : 0.0f;
+            const float e0 = in[p] ? a0v[p] - b0v[p] : 0.0f;
+            const float e1 = in[p] ? a1v[p] - b1v[p] : 0.0f;
+            const float e2 = in[p] ? a2v[p] - b2v[p] : 0.0f;
             g0[p] = l2scale * e0;
             g1[p] = l2scale * e1;
             g2[p] = l2scale * e2;
@@ -315,12 +334,12 @@ __device__ __forceinline__ void bwd_unit(const ViewTable& vt, int gt, int wit,
             lsum = __builtin_fmaf(e1, e1, lsum);
             lsum = __builtin_fmaf(e2, e2, lsum);
         } else {
-            g0[p] = in ? dimg[3 * po + pix] : 0.0f;
-            g1[p] = in ? dimg[3 * po + plane + pix] : 0.0f;
-            g2[p] = in ? dimg[3 * po + 2 * plane + pix] : 0.0f;
+            g0[p] = in[p] ? a0v[p] : 0.0f;
+            g1[p] = in[p] ? a1v[p] : 0.0f;
+            g2[p] = in[p] ? a2v[p] : 0.0f;
         }
         // d(1 - T_N)/d alpha_k = T_N / (1 - alpha_k): keep gA * T_N
-        gA[p] = (HAS_DA && in) ? dalpha[po + pix] * T[p] : 0.0f;
+        gA[p] = (HAS_DA && in[p]) ? dav[p] * T[p] : 0.0f;
         S0[p] = bg0;
         S1[p] = bg1;
         S2[p] = bg2;

@@ -80,7 +80,7 @@ def bin_layout(vn, cap):
     regions = [("dk0", 4 * vn), ("dv0", 4 * vn), ("dk1", 4 * vn), ("dv1", 4 * vn), ("offs", 4 * vn),
                ("tk", 4 * cap), ("tv", 4 * cap), ("hist", 4 * (1 << RS_MAX_BITS) * RS_MAX_BLOCKS),
                ("dtot", 4 * (1 << RS_MAX_BITS)), ("part", 8 * RS_MAX_BLOCKS), ("srect", 8 * vn),
-               ("part_ex", 8 * RS_MAX_BLOCKS), ("cnt", 4 * 16),
+               ("cnt", 4 * 16),
                ("bsrc", 4 * ((cap + EMIT_SPAN - 1) // EMIT_SPAN + 1))]
     return {k: v for k, v in regions}, sum(align256(v) for _, v in regions)
 
@@ -141,9 +141,11 @@ def model_step(sizes, n, tile, cap):
     for p, bits in enumerate(dw):
         check_radix_pass(vn, nb_d, bits, regions["hist"], regions["dk0"], regions["dk1"],
                          regions["srect"] if p == len(dw) - 1 else None)
-    # 2. scan: partial sums per block, one spine block, offsets and emission sources
+    # 2. scan: partial sums per block (the first kernel also zeroes the 2 T
+    # range ints, grid-stride), then offsets and emission sources, every block
+    # reading all nb_d partial sums
     grid_ok(nb_d, SC_THREADS)
-    assert nb_d <= regions["part"] // 8 and nb_d <= regions["part_ex"] // 8
+    assert nb_d <= regions["part"] // 8
     assert vn - 1 + SC_THREADS * SC_ITEMS - 1 < U32
     last = (cap + EMIT_SPAN - 1) // EMIT_SPAN
     # bsrc[k] for k * EMIT_SPAN < min(offset + count, cap), and bsrc[last]
@@ -173,7 +175,7 @@ def model_step(sizes, n, tile, cap):
             # the emission's histogram columns are the scatter's blocks: one
             # EMIT_SPAN-slot chunk each
             assert block_span(cap, nb, 0)[1] <= EMIT_SPAN or cap <= EMIT_SPAN
-    # 5. ranges: fill 2 T ints, then 4 keys per thread over the capacity
+    # 5. ranges: 4 keys per thread over the capacity
     grid_ok((cap + 1023) // 1024, 256)
     assert 4 * ((cap + 1023) // 1024 * 256) < U32
     # tile schedule: one 8-bit pass over the tiles
