@@ -84,7 +84,9 @@ __device__ __forceinline__ TileOf tile_of(const SsimTiles& st, int b)
 
 // stages the RH x RW region of one plane around the tile (zero outside the
 // image): all of a thread's loads are issued before any is stored, so that
-// they are in flight together
+// they are in flight together.  The loads are unconditional, from the
+// position clamped into the image, and masked afterwards (a load guarded by
+// the position test becomes a branch with a wait of its own).
 constexpr int STAGE_PER_THREAD = (RH * RW + THREADS - 1) / THREADS;
 __device__ __forceinline__ void stage(const float* __restrict__ p, const TileOf& T, float (*s)[XP])
 {
@@ -95,7 +97,9 @@ __device__ __forceinline__ void stage(const float* __restrict__ p, const TileOf&
         const int r = i / RW, q = i - r * RW;
         const int gy = T.y0 + r - SR, gx = T.x0 + q - SR;
         const bool in = i < RH * RW && gx >= 0 && gx < T.W && gy >= 0 && gy < T.H;
-        val[u] = in ? p[(long long)gy * T.W + gx] : 0.0f;
+        const int cy = min(max(gy, 0), T.H - 1), cx = min(max(gx, 0), T.W - 1);
+        const float x = p[(long long)cy * T.W + cx];
+        val[u] = in ? x : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < STAGE_PER_THREAD; u++) {
@@ -229,7 +233,8 @@ __device__ __forceinline__ void final_sum(const double* __restrict__ part, long 
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             const long long i = i0 + (long long)THREADS * u;
-            if (i < nb) acc[u] += part[i];
+            const double x = part[i < nb ? i : nb - 1];
+            acc[u] += i < nb ? x : 0.0;
         }
     s[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
@@ -277,8 +282,9 @@ __global__ __launch_bounds__(THREADS) void k_ssim_bwd(SsimTiles st, Window win, 
         const int gy = T.y0 + j0 + j;
         const bool in = j < nj && gx < T.W && gy < T.H;
         const long long o = cb + (long long)(in ? gy : 0) * T.W + (in ? gx : 0);
-        px[j] = in ? img[o] : 0.0f;
-        py[j] = in ? tgt[o] : 0.0f;
+        const float a = img[o], b = tgt[o];
+        px[j] = in ? a : 0.0f;
+        py[j] = in ? b : 0.0f;
     }
     __syncthreads();
     float p[3][HSEG + NT - 1];
