@@ -430,7 +430,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     for (int j = 0; j < (SV ? K : 1); j++) Ysv[j] = 0.0f;
 
     bool any = false;
-    for (int v = 0; v < vt.n_views; v++) any |= (flags[(long long)v * N + g] & GS_FLAG_VISIBLE) != 0;
+    uint8_t fl0 = 0;   // the flags of the first view (the only one when SV)
+    for (int v = 0; v < vt.n_views; v++) {
+        const uint8_t f = flags[(long long)v * N + g];
+        if (v == 0) fl0 = f;
+        any |= (f & GS_FLAG_VISIBLE) != 0;
+    }
 
     // a Gaussian no view sees gets zero gradients without reading its
     // parameters (whole cache lines are skipped when such Gaussians are
@@ -440,11 +445,21 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     auto ldp = [&](const float* base, long long c) {
         return ADAM ? nt_load(at(base + c * N, boff)) : nt_load(&base[c * N + g]);
     };
+    // The loads of one wave are issued together where possible: a load under
+    // a condition becomes a branch with a wait of its own, and a loop of
+    // loads each used at once waits once per iteration.
     float mu[3] = {0.0f, 0.0f, 0.0f}, ls[3] = {0.0f, 0.0f, 0.0f}, q[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+    float ologit = 0.0f;
+    // one view: the pair's whole 2-D gradient record, read with the parameters
+    float gr1[GS_GRAD_FLOATS];
+    for (int k = 0; k < GS_GRAD_FLOATS; k++) gr1[k] = 0.0f;
     if (ADAM || any) {
         for (int i = 0; i < 3; i++) mu[i] = ldp(means, i);
         for (int i = 0; i < 3; i++) ls[i] = ldp(log_scales, i);
         for (int i = 0; i < 4; i++) q[i] = ldp(quats, i);
+        ologit = ldp(opac, 0);
+        if (SV && any)
+            for (int k = 0; k < GS_GRAD_FLOATS; k++) gr1[k] = nt_load(&grad2d[g * GS_GRAD_FLOATS + k]);
     }
     const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     const float iq = any ? 1.0f / sqrtf(qn2) : 0.0f;
@@ -467,11 +482,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(
 
     for (int v = 0; any && v < (SV ? 1 : vt.n_views); v++) {
         const long long o_vg = (long long)v * N + g;
-        const uint8_t fl = flags[o_vg];
+        const uint8_t fl = SV ? fl0 : flags[o_vg];
         if (!(fl & GS_FLAG_VISIBLE)) continue;
         const float* gr = grad2d + o_vg * GS_GRAD_FLOATS;
-        const float gu = nt_load(&gr[0]), gv = nt_load(&gr[1]), gA = nt_load(&gr[2]), gB = nt_load(&gr[3]), gC = nt_load(&gr[4]);
-        gsig += nt_load(&gr[5]);
+        float grv[GS_GRAD_FLOATS];
+        for (int k = 0; k < GS_GRAD_FLOATS; k++) grv[k] = SV ? gr1[k] : nt_load(&gr[k]);
+        const float gu = grv[0], gv = grv[1], gA = grv[2], gB = grv[3], gC = grv[4];
+        gsig += grv[5];
         const Camera cam = load_camera(viewmats, intr, vt, v);
         Geo ge;
         geometry(cam, mu, M, eps2d, ge);
@@ -528,16 +545,29 @@ __global__ __launch_bounds__(256) void k_project_bwd(
         d0 *= idn; d1 *= idn; d2 *= idn;
         float Y[K], sdot[K];
         sh_basis<DEG>(d0, d1, d2, Y);
-        const float gc[3] = {(fl & GS_FLAG_CLAMP_R) ? 0.0f : nt_load(&gr[6]), (fl & GS_FLAG_CLAMP_G) ? 0.0f : nt_load(&gr[7]),
-                             (fl & GS_FLAG_CLAMP_B) ? 0.0f : nt_load(&gr[8])};
-        for (int j = 0; j < K; j++) {
-            sdot[j] = cf(j, 0) * gc[0] + cf(j, 1) * gc[1] + cf(j, 2) * gc[2];
-            if constexpr (SV) {
-                Ysv[j] = Y[j];
-            } else {
-                gsh[3 * j] += Y[j] * gc[0];
-                gsh[3 * j + 1] += Y[j] * gc[1];
-                gsh[3 * j + 2] += Y[j] * gc[2];
+        const float gc[3] = {(fl & GS_FLAG_CLAMP_R) ? 0.0f : grv[6], (fl & GS_FLAG_CLAMP_G) ? 0.0f : grv[7],
+                             (fl & GS_FLAG_CLAMP_B) ? 0.0f : grv[8]};
+        // coefficients read from memory in batches of SH_BATCH basis functions,
+        // the batch's three channels all in flight before any is used
+        constexpr int SH_BATCH = 8;
+        for (int j0 = 0; j0 < K; j0 += SH_BATCH) {
+            float cb[SH_BATCH][3];
+#pragma unroll
+            for (int jj = 0; jj < SH_BATCH; jj++)
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) cb[jj][ch] = j0 + jj < K ? cf(j0 + jj, ch) : 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < SH_BATCH; jj++) {
+                const int j = j0 + jj;
+                if (j >= K) break;
+                sdot[j] = cb[jj][0] * gc[0] + cb[jj][1] * gc[1] + cb[jj][2] * gc[2];
+                if constexpr (SV) {
+                    Ysv[j] = Y[j];
+                } else {
+                    gsh[3 * j] += Y[j] * gc[0];
+                    gsh[3 * j + 1] += Y[j] * gc[1];
+                    gsh[3 * j + 2] += Y[j] * gc[2];
+                }
             }
         }
         if constexpr (SV)
@@ -587,7 +617,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     gq[3] = 2.0f * (-2.0f * zq * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0f * zq * gR[4] +
                     y * gR[5] + x * gR[6] + y * gR[7]);
     const float qd = w * gq[0] + x * gq[1] + y * gq[2] + zq * gq[3];
-    const float ologit = (ADAM || any) ? ldp(opac, 0) : 0.0f;
     const float sigma = any ? 1.0f / (1.0f + expf(-ologit)) : 0.0f;
 
     for (int i = 0; i < 3; i++)
