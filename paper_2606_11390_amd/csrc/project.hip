@@ -301,14 +301,20 @@ __global__ __launch_bounds__(256) void k_project(
                     have_sh = true;
                 }
             }
+            // the three channels' sums run side by side over the basis
+            // functions (each in the same order as alone), so that all 3 K
+            // coefficient loads can be in flight together
+            float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int j = 0; j < K; j++)
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++)
+                    acc[ch] += (SV ? nt_load(&sh[((long long)j * 3 + ch) * N + g]) : coef[SV ? 0 : 3 * j + ch]) * Y[j];
             float col[3];
             for (int ch = 0; ch < 3; ch++) {
-                float acc = 0.0f;
-                for (int j = 0; j < K; j++)
-                    acc += (SV ? nt_load(&sh[((long long)j * 3 + ch) * N + g]) : coef[SV ? 0 : 3 * j + ch]) * Y[j];
-                acc += 0.5f;
-                if (acc < 0.0f) fl |= (uint8_t)(GS_FLAG_CLAMP_R << ch);
-                col[ch] = fmaxf(acc, 0.0f);
+                const float a = acc[ch] + 0.5f;
+                if (a < 0.0f) fl |= (uint8_t)(GS_FLAG_CLAMP_R << ch);
+                col[ch] = fmaxf(a, 0.0f);
             }
             fl |= GS_FLAG_VISIBLE;
             float4* rec = reinterpret_cast<float4*>(splats + o_vg * GS_SPLAT_FLOATS);
