@@ -5,9 +5,9 @@
 // itself is Adam (Kingma and Ba 2015) with bias correction:
 //   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
 //   p <- p - lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps).
-// One launch updates up to GS_ADAM_MAX_TENSORS tensors: the grid walks their
-// concatenated 16-byte chunks (one HBM read of p, g, m, v and one write of p,
-// m, v per element: 28 bytes, the algorithmic minimum).  The step count t is
+// One launch updates up to GS_ADAM_MAX_TENSORS tensors, each by its own range
+// of blocks (one HBM read of p, g, m, v and one write of p, m, v per element:
+// 28 bytes, the algorithmic minimum).  The step count t is
 // read from device memory and advanced by a one-thread kernel afterwards, so
 // a captured graph replays successive steps correctly.  The same element
 // update (adam_elem) is applied inside the projection backward by
@@ -23,12 +23,12 @@ struct AdamList {
     float* m[GS_ADAM_MAX_TENSORS];
     float* v[GS_ADAM_MAX_TENSORS];
     long long n[GS_ADAM_MAX_TENSORS];
-    long long chunk_off[GS_ADAM_MAX_TENSORS + 1];   // prefix of ceil(n / 4)
+    int block_off[GS_ADAM_MAX_TENSORS + 1];   // the blocks of tensor k: [block_off[k], block_off[k + 1])
     float lr[GS_ADAM_MAX_TENSORS];
     int count;
 };
 
-// chunks a thread handles per loop step (all their loads in flight at once)
+// 16-byte chunks a thread handles per loop step (all their loads in flight at once)
 constexpr int ADAM_UNROLL = 4;
 typedef float af4 __attribute__((ext_vector_type(4)));
 
@@ -44,67 +44,62 @@ __device__ __forceinline__ void adam4(af4& p, af4 g, af4& m, af4& v, float b1, f
     v = af4{vv[0], vv[1], vv[2], vv[3]};
 }
 
-__device__ __forceinline__ int tensor_of(const AdamList& L, long long c)
-{
-    int k = 0;
-    while (k + 1 < L.count && L.chunk_off[k + 1] <= c) k++;
-    return k;
-}
-
+// Each block updates one tensor (the tensor is uniform per block, so its
+// pointers are scalar kernel-argument loads): a grid-stride walk over the
+// tensor's whole 16-byte chunks by the tensor's blocks, ADAM_UNROLL chunks
+// per thread and step whose loads are unconditional (clamped to the last
+// whole chunk) and all in flight together; the n mod 4 trailing elements
+// are updated one by one by the tensor's first block.
 __global__ __launch_bounds__(256) void k_adam(AdamList L, float b1, float b2, float eps,
                                               const int* __restrict__ step_dev)
 {
-    const long long total = L.chunk_off[L.count];
-    const long long stride = (long long)gridDim.x * blockDim.x;
+    int k = 0;
+    while (k + 1 < L.count && L.block_off[k + 1] <= (int)blockIdx.x) k++;
+    k = __builtin_amdgcn_readfirstlane(k);
     const AdamCoef ac = adam_coef(*step_dev, b1, b2);
     const float rbc2 = ac.rbc2;
+    const float step = L.lr[k] * ac.step_scale;
+    float* const P = L.p[k];
+    const float* const G = L.g[k];
+    float* const M = L.m[k];
+    float* const V = L.v[k];
+    const long long n = L.n[k];
+    const long long whole = n / 4;
+    const int b = (int)blockIdx.x - L.block_off[k];
+    const long long stride = (long long)(L.block_off[k + 1] - L.block_off[k]) * blockDim.x;
+    af4* const P4 = reinterpret_cast<af4*>(P);
+    const af4* const G4 = reinterpret_cast<const af4*>(G);
+    af4* const M4 = reinterpret_cast<af4*>(M);
+    af4* const V4 = reinterpret_cast<af4*>(V);
     // every element is read and written once per step: streaming
-    // (non-temporal) accesses; ADAM_UNROLL chunks c, c + stride, ... per
-    // thread and step, so that 4 x ADAM_UNROLL 16-byte loads are in flight
-    for (long long c0 = (long long)blockIdx.x * blockDim.x + threadIdx.x; c0 < total;
-         c0 += ADAM_UNROLL * stride) {
+    // (non-temporal) accesses
+    for (long long c0 = (long long)b * blockDim.x + threadIdx.x; c0 < whole; c0 += ADAM_UNROLL * stride) {
         af4 p[ADAM_UNROLL], g[ADAM_UNROLL], m[ADAM_UNROLL], v[ADAM_UNROLL];
-        int kk[ADAM_UNROLL];
-        long long ii[ADAM_UNROLL];
-        bool full[ADAM_UNROLL];
 #pragma unroll
         for (int u = 0; u < ADAM_UNROLL; u++) {
-            const long long c = c0 + u * stride;
-            const int k = c < total ? tensor_of(L, c) : 0;
-            const long long i = 4 * (c - L.chunk_off[k]);
-            kk[u] = k;
-            ii[u] = i;
-            full[u] = c < total && i + 4 <= L.n[k];
-            if (full[u]) {
-                p[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.p[k] + i));
-                g[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.g[k] + i));
-                m[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.m[k] + i));
-                v[u] = __builtin_nontemporal_load(reinterpret_cast<const af4*>(L.v[k] + i));
-            }
+            const long long c = min(c0 + u * stride, whole - 1);
+            p[u] = __builtin_nontemporal_load(P4 + c);
+            g[u] = __builtin_nontemporal_load(G4 + c);
+            m[u] = __builtin_nontemporal_load(M4 + c);
+            v[u] = __builtin_nontemporal_load(V4 + c);
         }
 #pragma unroll
         for (int u = 0; u < ADAM_UNROLL; u++) {
             const long long c = c0 + u * stride;
-            if (c >= total) continue;
-            const int k = kk[u];
-            const long long i = ii[u];
-            const float step = L.lr[k] * ac.step_scale;
-            if (full[u]) {
-                adam4(p[u], g[u], m[u], v[u], b1, b2, step, rbc2, eps);
-                __builtin_nontemporal_store(p[u], reinterpret_cast<af4*>(L.p[k] + i));
-                __builtin_nontemporal_store(m[u], reinterpret_cast<af4*>(L.m[k] + i));
-                __builtin_nontemporal_store(v[u], reinterpret_cast<af4*>(L.v[k] + i));
-            } else {
-                // the ragged tail of a tensor, element by element
-                for (long long e = i; e < L.n[k]; e++) {
-                    float pe = L.p[k][e], me = L.m[k][e], ve = L.v[k][e];
-                    adam_elem(pe, L.g[k][e], me, ve, b1, b2, step, rbc2, eps);
-                    L.p[k][e] = pe;
-                    L.m[k][e] = me;
-                    L.v[k][e] = ve;
-                }
-            }
+            if (c >= whole) continue;
+            adam4(p[u], g[u], m[u], v[u], b1, b2, step, rbc2, eps);
+            __builtin_nontemporal_store(p[u], P4 + c);
+            __builtin_nontemporal_store(m[u], M4 + c);
+            __builtin_nontemporal_store(v[u], V4 + c);
         }
+    }
+    if (b == 0 && (long long)threadIdx.x < n - 4 * whole) {
+        const long long e = 4 * whole + threadIdx.x;
+        float pe = P[e], me = M[e], ve = V[e];
+        adam_elem(pe, G[e], me, ve, b1, b2, step, rbc2, eps);
+        P[e] = pe;
+        M[e] = me;
+        V[e] = ve;
     }
 }
 
@@ -124,7 +119,7 @@ hipError_t launch_adam(int n_tensors, float* const* params, const float* const* 
 {
     AdamList L;
     L.count = n_tensors;
-    L.chunk_off[0] = 0;
+    long long total = 0;
     for (int k = 0; k < n_tensors; k++) {
         L.p[k] = params[k];
         L.g[k] = grads[k];
@@ -132,14 +127,21 @@ hipError_t launch_adam(int n_tensors, float* const* params, const float* const* 
         L.v[k] = exp_avg_sq[k];
         L.n[k] = numel[k];
         L.lr[k] = lrs[k];
-        L.chunk_off[k + 1] = L.chunk_off[k] + (numel[k] + 3) / 4;
+        total += (numel[k] + 3) / 4;
     }
-    const long long total = L.chunk_off[n_tensors];
-    if (total > 0) {
-        long long blocks = (total + 255) / 256;
-        if (blocks > 8192) blocks = 8192;
-        hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, L, beta1, beta2, eps, step_dev);
+    // up to ADAM_MAX_BLOCKS blocks of 256 threads, shared out in proportion
+    // to the tensors' chunk counts (at least one per tensor)
+    constexpr long long ADAM_MAX_BLOCKS = 8192;
+    const long long want = min(ADAM_MAX_BLOCKS, max(1ll, (total + 255) / 256));
+    L.block_off[0] = 0;
+    for (int k = 0; k < n_tensors; k++) {
+        const long long chunks = (numel[k] + 3) / 4;
+        const long long nb = max(1ll, min((chunks + 255) / 256, (want * chunks + total - 1) / max(total, 1ll)));
+        L.block_off[k + 1] = L.block_off[k] + (int)nb;
     }
+    if (total > 0)
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)L.block_off[n_tensors]), dim3(256), 0, st, L, beta1, beta2, eps,
+                           step_dev);
     const hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : launch_step_advance(step_dev, st);
 }
