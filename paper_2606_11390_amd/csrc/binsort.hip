@@ -516,11 +516,20 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const int2* __restrict
 {
     __shared__ unsigned long long s_tmp[RS_WAVES];
     const int nb = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+    // the nb <= RS_MAX_BLOCKS block sums, a thread's loads all in flight at
+    // once (unconditional, clamped to the last sum)
+    constexpr int PER = RS_MAX_BLOCKS / SC_THREADS;
+    unsigned long long xs[PER];
+#pragma unroll
+    for (int k = 0; k < PER; k++) xs[k] = part[min(t + k * SC_THREADS, nb - 1)];
     unsigned long long before = 0, all = 0;
-    for (int i = t; i < nb; i += SC_THREADS) {
-        const unsigned long long x = part[i];
-        all += x;
-        if (i < b) before += x;
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const int i = t + k * SC_THREADS;
+        if (i < nb) {
+            all += xs[k];
+            if (i < b) before += xs[k];
+        }
     }
     unsigned long long carry = block_sum_256_u64(before, s_tmp);
     const unsigned long long total = block_sum_256_u64(all, s_tmp);
@@ -589,6 +598,9 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
     __shared__ __align__(16) uint32_t s_src[EMIT_SPAN];   // source of each slot
     __shared__ uint32_t s_wmax[EMIT_THREADS / GS_WAVE];
     __shared__ uint32_t s_h[1 << RS_MAX_BITS];
+    // the views' tile-row widths and tile offsets, looked up per source (a
+    // per-lane index into the argument block would be a vector load each)
+    __shared__ int s_vtx[GS_MAX_VIEWS], s_vtoff[GS_MAX_VIEWS];
     const uint32_t m = cnt[1];
     const uint32_t start = blockIdx.x * (uint32_t)EMIT_SPAN;
     // with hist0: this workgroup's column of the first tile pass's digit
@@ -625,6 +637,10 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
         rc[q] = srect[s0 + k];
     }
     for (int i = t; i < EMIT_SPAN; i += EMIT_THREADS) s_src[i] = 0u;
+    for (int i = t; i < vt.n_views; i += EMIT_THREADS) {
+        s_vtx[i] = vt.tiles_x[i];
+        s_vtoff[i] = vt.tile_off[i];
+    }
     __syncthreads();
     // each source marks the slot where it starts (the first source, which
     // starts at or before this workgroup's first slot, marks slot 0); slots
@@ -637,10 +653,10 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(const uint32_t* __restric
         const uint32_t v = (uint32_t)(pid[q] / (unsigned long long)N);
         const uint32_t g = pid[q] - v * (uint32_t)N;
         const int x0 = rc[q].x & 0xFFFF, y0 = (int)((uint32_t)rc[q].x >> 16), x1 = rc[q].y & 0xFFFF;
-        const int TX = vt.tiles_x[v];
+        const int TX = s_vtx[v];
         s_off[k] = off[q];
         s_gid[k] = g;
-        s_base[k] = (uint32_t)(vt.tile_off[v] + y0 * TX + x0);
+        s_base[k] = (uint32_t)(s_vtoff[v] + y0 * TX + x0);
         s_wt[k] = (uint32_t)max(x1 - x0, 1);
         s_tx[k] = (uint32_t)TX;
         if (off[q] < end) s_src[off[q] > start ? off[q] - start : 0u] = k;
