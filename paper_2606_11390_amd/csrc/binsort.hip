@@ -402,13 +402,34 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
             if (GATHER) s_r[pos] = rct[r];
         }
         __syncthreads();
-        for (uint32_t j = t; j < ctot; j += RS_THREADS) {
-            const uint32_t k = s_k[j];
-            const uint32_t d = (k >> shift) & mask;
-            const uint32_t dst = s_base[d] + j - s_cex[d];
-            if (io.keys_out) io.keys_out[dst] = k;
-            io.vals_out[dst] = s_v[j];
-            if (GATHER) io.rects_out[dst] = s_r[j];
+        // write-out: a thread's RS_ITEMS slots j = t + r * RS_THREADS (the
+        // chunk holds at most RS_CHUNK keys) are read from LDS together, then
+        // their digits' offsets, so that the thread waits on LDS twice, not
+        // twice per slot; slots at or past ctot hold stale keys whose masked
+        // digits index the LDS arrays in range and are not written out
+        uint32_t ko[RS_ITEMS], vo[RS_ITEMS], bo[RS_ITEMS], co[RS_ITEMS];
+        int2 ro[GATHER ? RS_ITEMS : 1];
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
+            const uint32_t j = (uint32_t)(t + r * RS_THREADS);
+            ko[r] = s_k[j];
+            vo[r] = s_v[j];
+            if (GATHER) ro[r] = s_r[j];
+        }
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
+            const uint32_t d = (ko[r] >> shift) & mask;
+            bo[r] = s_base[d];
+            co[r] = s_cex[d];
+        }
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; r++) {
+            const uint32_t j = (uint32_t)(t + r * RS_THREADS);
+            if (j >= ctot) continue;
+            const uint32_t dst = bo[r] + j - co[r];
+            if (io.keys_out) io.keys_out[dst] = ko[r];
+            io.vals_out[dst] = vo[r];
+            if (GATHER) io.rects_out[dst] = ro[r];
         }
         __syncthreads();
 #pragma unroll
