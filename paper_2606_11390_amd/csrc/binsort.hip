@@ -40,6 +40,7 @@ constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;     // keys per chunk
 constexpr int RS_WAVE_SPAN = GS_WAVE * RS_ITEMS;     // keys per wave per chunk
 constexpr int RS_MAX_BLOCKS = 4096;
 constexpr int RS_MAX_BITS = 9;    // widest digit: 512 counters per wave
+constexpr int RS_RAW_MAX = 64;    // passes of at most this many blocks run without the per-digit scan kernel
 
 enum Source { SRC_PAIRS = 0, SRC_PROJ = 1, SRC_TILE_LEN = 2, SRC_MORTON = 3 };
 
@@ -291,11 +292,15 @@ __device__ __forceinline__ uint32_t block_excl_scan_digits(uint32_t (&x)[DPT], u
 // GATHER: the values are pair indices; each one's tile rectangle is read
 // with it and written beside it (io.rects -> io.rects_out), so that the scan
 // after the sort reads rectangles in order instead of gathering them
+//
+// raw: the per-digit scan across blocks was not run (a pass of at most
+// RS_RAW_MAX blocks); excl then holds the histogram's counts and every block
+// forms its own digit offsets and the digit totals from them.
 template <int SRC, int DBITS, bool GATHER = false>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift, int bits,
                                                            const uint32_t* __restrict__ excl,
                                                            const uint32_t* __restrict__ dtot,
-                                                           uint32_t* __restrict__ count_out)
+                                                           uint32_t* __restrict__ count_out, int raw)
 {
     constexpr int ND = 1 << DBITS;
     constexpr int DPT = ND / RS_THREADS;   // digits per thread in the digit scans
@@ -335,11 +340,35 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortIO io, int shift,
     // read with the digit totals, before the scan)
     {
         uint32_t x[DPT], ex[DPT];
+        if (raw) {
+            // a digit's counts over the nb <= RS_RAW_MAX blocks, sixteen loads
+            // in flight at a time (unconditional, clamped to the last block)
 #pragma unroll
-        for (int i = 0; i < DPT; i++) {
-            const int d = t * DPT + i;
-            x[i] = d < nd ? dtot[d] : 0u;
-            ex[i] = d < nd ? excl[(size_t)d * nb + b] : 0u;
+            for (int i = 0; i < DPT; i++) {
+                const int d = min(t * DPT + i, nd - 1);
+                const uint32_t* row = excl + (size_t)d * nb;
+                uint32_t tot = 0, before = 0;
+                for (int b0 = 0; b0 < nb; b0 += 16) {
+                    uint32_t h[16];
+#pragma unroll
+                    for (int u = 0; u < 16; u++) h[u] = row[min(b0 + u, nb - 1)];
+#pragma unroll
+                    for (int u = 0; u < 16; u++) {
+                        const bool in = b0 + u < nb;
+                        tot += in ? h[u] : 0u;
+                        before += (in && b0 + u < b) ? h[u] : 0u;
+                    }
+                }
+                x[i] = t * DPT + i < nd ? tot : 0u;
+                ex[i] = t * DPT + i < nd ? before : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < DPT; i++) {
+                const int d = t * DPT + i;
+                x[i] = d < nd ? dtot[d] : 0u;
+                ex[i] = d < nd ? excl[(size_t)d * nb + b] : 0u;
+            }
         }
         const uint32_t all = block_excl_scan_digits<DPT>(x, s_tmp);
 #pragma unroll
@@ -784,27 +813,31 @@ hipError_t radix_pass(const SortIO& io, int nb, int shift, int bits, uint32_t* h
                       uint32_t* count_out, hipStream_t st, bool have_hist = false)
 {
     const int sp_threads = min(1024, ((nb + GS_WAVE - 1) / GS_WAVE) * GS_WAVE);
+    // few blocks: each scatter block reads the counts of the blocks before it
+    // (at most RS_RAW_MAX per digit) instead of a scan kernel's prefixes
+    const int raw = nb <= RS_RAW_MAX ? 1 : 0;
+    const bool gather = SRC == SRC_PAIRS && io.rects_out;
     if (bits <= 8) {
         if (!have_hist)
             hipLaunchKernelGGL((k_rs_hist<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist);
-        hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
-        if (SRC == SRC_PAIRS && io.rects_out)
+        if (!raw) hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
+        if (gather)
             hipLaunchKernelGGL((k_rs_scatter<SRC, 8, true>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
-                               hist, dtot, count_out);
+                               hist, dtot, count_out, raw);
         else
             hipLaunchKernelGGL((k_rs_scatter<SRC, 8>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits, hist,
-                               dtot, count_out);
+                               dtot, count_out, raw);
     } else {
         if (!have_hist)
             hipLaunchKernelGGL((k_rs_hist<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift, bits,
                                hist);
-        hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
-        if (SRC == SRC_PAIRS && io.rects_out)
+        if (!raw) hipLaunchKernelGGL(k_rs_spine, dim3(1u << bits), dim3(sp_threads), 0, st, hist, nb, dtot);
+        if (gather)
             hipLaunchKernelGGL((k_rs_scatter<SRC, RS_MAX_BITS, true>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift,
-                               bits, hist, dtot, count_out);
+                               bits, hist, dtot, count_out, raw);
         else
             hipLaunchKernelGGL((k_rs_scatter<SRC, RS_MAX_BITS>), dim3(nb), dim3(RS_THREADS), 0, st, io, shift,
-                               bits, hist, dtot, count_out);
+                               bits, hist, dtot, count_out, raw);
     }
     return hipGetLastError();
 }

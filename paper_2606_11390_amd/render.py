@@ -255,6 +255,9 @@ class Renderer:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self.step(P, cams, targets, grads)
+        # the captured launches read and write these tensors on every replay
+        # and torch does not track them: the graph keeps them alive
+        g.gs_tensors = (P, cams, targets, grads)
         self.graph = g
         return g
 
@@ -271,6 +274,7 @@ class Renderer:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self.train_step(P, cams, targets, grads, optimizer, fused=fused)
+        g.gs_tensors = (P, cams, targets, grads, optimizer)
         return g
 
     def replay(self):

@@ -273,6 +273,31 @@ def test_graph_replay_matches_eager(order):
         (x * 2).sum().item()
 
 
+def test_captured_graph_keeps_its_tensors():
+    """The captured step reads and writes the parameters, targets and gradient
+    tensors it was captured with on every replay, and torch does not track
+    tensors used by library launches: the graph object must keep them alive,
+    so that a caller's temporary dicts are not freed and reused under it.
+    Checked by weak references only (no replay touches released memory)."""
+    import gc
+    import weakref
+    s = scenes.tiny(seed=5, n_gaussians=800, width=96, height=64, focal=80.0)
+    r, P, cams, tg, _ = _run_step(s)
+    grads = R.zeros_like_params(P)
+    tg2 = tg.clone()
+    refs = [weakref.ref(t) for t in list(grads.values()) + [tg2]]
+    g = r.capture(P, cams, tg2, grads, warmup=1)
+    del grads, tg2
+    gc.collect()
+    assert all(ref() is not None for ref in refs)
+    g.replay()
+    torch.cuda.synchronize()
+    del g
+    r.graph = None
+    gc.collect()
+    assert all(ref() is None for ref in refs)
+
+
 def test_autograd_matches_fused_step():
     s = scenes.tiny(seed=9, n_gaussians=3000, width=160, height=96, focal=110.0)
     G.say("[autograd]")
