@@ -40,7 +40,7 @@ constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;     // keys per chunk
 constexpr int RS_WAVE_SPAN = GS_WAVE * RS_ITEMS;     // keys per wave per chunk
 constexpr int RS_MAX_BLOCKS = 4096;
 constexpr int RS_MAX_BITS = 9;    // widest digit: 512 counters per wave
-constexpr int RS_RAW_MAX = 64;    // passes of at most this many blocks run without the per-digit scan kernel
+constexpr int RS_RAW_MAX = 16;    // passes of at most this many blocks run without the per-digit scan kernel
 
 enum Source { SRC_PAIRS = 0, SRC_PROJ = 1, SRC_TILE_LEN = 2, SRC_MORTON = 3 };
 
