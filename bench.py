@@ -629,7 +629,21 @@ def main():
         log(f"training step, Adam fused into the projection backward (captured): {ms_trf:.3f} ms/step; "
             f"fused kernel {ms_pba:.3f} ms against {ms_pb:.3f} + {ms_adam:.3f} ms unfused "
             f"({fused_bytes / (ms_pba * 1e-3) / 1e9:.0f} GB/s)")
-        del gf, P_tr, opt_f
+        del gf, opt_f
+        # the same fused training step with the 3D Gaussian Splatting training
+        # loss, (1 - 0.2) L1 + 0.2 (1 - SSIM), in place of L2
+        r_main.set_loss("ssim_l1", 0.2)
+        opt_s = R.Adam(P_tr)
+        gss = r_main.capture_train(P_tr, cams, tg, None, opt_s, warmup=1, fused=True)
+        for _ in range(max(1, args.warmup)):
+            gss.replay()
+        ms_trs = timed(gss.replay, args.steps, torch)
+        extra["train_step"]["fused_ssim_l1"] = {"ms_per_step": round(ms_trs, 4),
+                                                "mp_per_s": round(pixels / ms_trs / 1e3, 3)}
+        log(f"training step with the SSIM + L1 loss and Adam fused into the projection backward (captured): "
+            f"{ms_trs:.3f} ms/step")
+        del gss, opt_s, P_tr
+        r_main.set_loss("l2")
         torch.cuda.empty_cache()
 
         # the other per-step calls of the training loop, alone: the fused SSIM

@@ -42,11 +42,17 @@ N_XCD = 8
 class Renderer:
     def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
                  background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda",
-                 radius_mode=0, order=None, order_bwd=None, fuse_l2=True):
+                 radius_mode=0, order=None, order_bwd=None, fuse_l2=True, loss="l2", ssim_lambda=0.2):
         # screen box rule of the projection (GS_RADIUS_*)
         self.radius_mode = int(radius_mode)
         # step(): L2 loss formed inside the rasteriser backward (d_images not stored)
         self.fuse_l2 = bool(fuse_l2)
+        # the step's image loss: "l2" (mean squared error) or "ssim_l1" (the 3D
+        # Gaussian Splatting training loss, (1 - lambda) L1 + lambda (1 - SSIM))
+        if loss not in ("l2", "ssim_l1"):
+            raise ValueError(f"unknown loss {loss!r}")
+        self.loss_kind = loss
+        self.ssim_lambda = float(ssim_lambda)
         # wave pixel blocks (width, pixels per lane) of the forward and backward rasterisers
         self.block = tuple(int(x) for x in block)
         self.block_bwd = self.block if block_bwd is None else tuple(int(x) for x in block_bwd)
@@ -87,6 +93,8 @@ class Renderer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.loss_ws = e(max(1, B.loss_workspace_size(3 * self.pixels)), dt=torch.uint8)
         self.l2_ws = e(max(8, B.rasterize_bwd_l2_workspace_size(self.sizes, self.tile)), dt=torch.uint8)
+        self.ssim_ws = (e(max(8, B.ssim_workspace_size(self.sizes)), dt=torch.uint8) if loss == "ssim_l1"
+                        else None)
         self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
         self.schedule = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
         self.schedule_xcd = e(max(1, B.tile_schedule_size(self.total_tiles)), dt=torch.uint8)
@@ -162,7 +170,19 @@ class Renderer:
 
     @property
     def fused_l2_active(self):
-        return self.fuse_l2 and self.order_bwd != "queue"
+        return self.loss_kind == "l2" and self.fuse_l2 and self.order_bwd != "queue"
+
+    def set_loss(self, loss, ssim_lambda=None):
+        """Switch the step's image loss ("l2" or "ssim_l1"); graphs captured
+        before keep the loss they were captured with."""
+        if loss not in ("l2", "ssim_l1"):
+            raise ValueError(f"unknown loss {loss!r}")
+        self.loss_kind = loss
+        if ssim_lambda is not None:
+            self.ssim_lambda = float(ssim_lambda)
+        if loss == "ssim_l1" and self.ssim_ws is None:
+            self.ssim_ws = torch.empty(max(8, B.ssim_workspace_size(self.sizes)), dtype=torch.uint8,
+                                       device=self.device)
 
     def loss_raster_bwd(self, targets, accumulate=False):
         """L2 loss of ``images`` against ``targets`` and the rasteriser
@@ -173,8 +193,15 @@ class Renderer:
                            self.background, s, self.T_final, self.n_contrib, self.images, targets, self.loss,
                            self.grad2d, self.l2_ws, accumulate=accumulate, block=self.block_bwd)
 
+    def loss_ssim_l1(self, targets):
+        B.loss_ssim_l1(self.images, targets, self.sizes, self.ssim_lambda, self.loss, self.d_images,
+                       self.ssim_ws)
+
     def loss_and_raster_bwd(self, targets, accumulate=False):
-        if self.fused_l2_active:
+        if self.loss_kind == "ssim_l1":
+            self.loss_ssim_l1(targets)
+            self.raster_bwd(self.d_images, accumulate=accumulate)
+        elif self.fused_l2_active:
             self.loss_raster_bwd(targets, accumulate)
         else:
             self.loss_l2(targets)
@@ -205,8 +232,9 @@ class Renderer:
 
     # ---------------------------------------------------------- whole step
     def step(self, P, cams, targets, grads):
-        """Forward, L2 loss against packed ``targets`` and backward into
-        ``grads`` (dict of tensors shaped like the parameters)."""
+        """Forward, the image loss (``loss``: L2, or SSIM + L1) against packed
+        ``targets`` and backward into ``grads`` (dict of tensors shaped like
+        the parameters)."""
         # the projection zeroes the 2-D gradient records the backward adds to
         self.forward(P, cams, clear_grad2d=True)
         self.loss_and_raster_bwd(targets, accumulate=True)

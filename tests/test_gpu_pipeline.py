@@ -273,6 +273,46 @@ def test_graph_replay_matches_eager(order):
         (x * 2).sum().item()
 
 
+def test_ssim_l1_step_matches_separate_calls():
+    """The step with the SSIM + L1 training loss equals the loss call and the
+    backward run by hand (same images and loss bit for bit, gradients up to
+    atomic order), and its loss is the oracle's SSIM + L1 of the rendered
+    images; a captured training step with it replays."""
+    s = scenes.tiny(seed=7, n_gaussians=1200, width=100, height=75, focal=90.0)
+    W, H = (int(x) for x in s.sizes[0])
+    P, cams = R.params_to_device(s)
+    tg = R.packed_targets(s)
+    r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=16, capacity=1 << 16, loss="ssim_l1")
+    r.fit_capacity(P, cams)
+    grads = R.zeros_like_params(P)
+    r.step(P, cams, tg, grads)
+    torch.cuda.synchronize()
+    loss = float(G.host(r.loss)[0])
+    img = G.host(r.images).copy()
+    r2 = R.Renderer(s.n, s.sh_degree, s.sizes, tile=16, capacity=1 << 16)
+    r2.fit_capacity(P, cams)
+    r2.forward(P, cams)
+    ws = torch.empty(B.ssim_workspace_size(s.sizes), dtype=torch.uint8, device="cuda")
+    l2 = torch.zeros(1, device="cuda")
+    d = torch.empty_like(r2.images)
+    B.loss_ssim_l1(r2.images, tg, s.sizes, 0.2, l2, d, ws)
+    g2 = R.zeros_like_params(P)
+    r2.backward(P, cams, d, g2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(G.host(r2.images), img)
+    assert float(G.host(l2)[0]) == loss
+    for k in grads:
+        assert G.rel_l2(G.host(grads[k]), G.host(g2[k])) <= 1e-5, k
+    L, _ = oracle.ssim_l1_loss([img.reshape(3, H, W)], [G.host(tg).reshape(3, H, W)], lam=0.2)
+    G.say(f"[ssim step] loss {loss:.8f} oracle {L:.8f}")
+    assert loss == pytest.approx(L, rel=1e-5)
+    opt = R.Adam({k: v.clone() for k, v in P.items()})
+    g = r.capture_train(opt.P, cams, tg, None, opt, warmup=1, fused=True)
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.isfinite(G.host(r.loss)[0])
+
+
 def test_captured_graph_keeps_its_tensors():
     """The captured step reads and writes the parameters, targets and gradient
     tensors it was captured with on every replay, and torch does not track
