@@ -99,11 +99,17 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
     ahead of the GPU, so an interval is the call's own GPU time).  As in the
     step, the projection zeroes the visible pairs' 2-D gradient records and
     the rasteriser backward accumulates into them."""
+    from paper_2606_11390_amd import binding as B
+    split = r.fused_l2_active and r.unseen_in_bwd
+    part = B.GRADS_SEEN if split else B.GRADS_ALL
     if r.fused_l2_active:
         # the loss is formed inside the rasteriser backward: its call (the
         # backward kernel and the two small kernels that sum the loss
-        # partials) is the "raster_bwd" stage
-        loss_bwd = [("raster_bwd", lambda: r.loss_raster_bwd(tg, accumulate=True))]
+        # partials) is the "raster_bwd" stage; as in the step, it also
+        # writes the zero gradients of unseen Gaussians, and the projection
+        # backward the seen ones
+        loss_bwd = [("raster_bwd", lambda: r.loss_raster_bwd(tg, accumulate=True,
+                                                             unseen_grads=grads if split else None))]
     else:
         loss_bwd = [("loss", lambda: r.loss_l2(tg)),
                     ("raster_bwd", lambda: r.raster_bwd(r.d_images, accumulate=True))]
@@ -112,7 +118,7 @@ def stage_times(r, P, cams, tg, grads, steps, torch):
         ("bin_sort", r.bin_sort),
         ("raster_fwd", r.raster_fwd),
         *loss_bwd,
-        ("project_bwd", lambda: r.project_bwd(P, cams, grads)),
+        ("project_bwd", lambda: r.project_bwd(P, cams, grads, part=part)),
     ]
     for _ in range(2):
         for _, fn in calls:
@@ -214,7 +220,7 @@ def counted_issue(stage, r, workload):
     return None
 
 
-def algorithmic_bytes(scene, visible, isect, total_tiles):
+def algorithmic_bytes(scene, visible, isect, total_tiles, split=False):
     """HBM bytes each HBM-bound call of the step must move at minimum, from
     the workload's counts (N Gaussians, V views, visible (view, Gaussian)
     pairs, M intersections, T tiles, P pixels).
@@ -236,7 +242,10 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
     project_bwd  the gradients of every parameter written (236 B per
                  Gaussian, zero where no view sees it), the parameters read
                  for the Gaussians some view sees (min(N, visible pairs)),
-                 flags read per pair, the 36-byte 2-D gradient per visible pair
+                 flags read per pair, the 36-byte 2-D gradient per visible pair;
+                 with ``split`` the zeros of unseen Gaussians are written by
+                 the compositing backward instead, and only the seen
+                 Gaussians' gradients count here
     """
     N, V = scene.n, scene.n_views
     K = (scene.sh_degree + 1) ** 2
@@ -249,7 +258,7 @@ def algorithmic_bytes(scene, visible, isect, total_tiles):
     return {"project": 12 * N + (param - 12) * seen + 25 * V * N + (48 + 36) * visible,
             "bin_sort": sort,
             "loss": 12 * 3 * scene.pixels,
-            "project_bwd": N * param + seen * param + V * N + 36 * visible}
+            "project_bwd": (seen if split else N) * param + seen * param + V * N + 36 * visible}
 
 
 def host_cpu():
@@ -535,7 +544,8 @@ def main():
     fwd_visits = int(vis.to(torch.int64).sum())
     bwd_visits = int(r_main.n_contrib.to(torch.int64).sum())
     info = r_main.info.cpu().numpy()
-    work = algorithmic_bytes(scene, int(info[B.INFO_VISIBLE]), int(info[B.INFO_ISECT]), r_main.total_tiles)
+    work = algorithmic_bytes(scene, int(info[B.INFO_VISIBLE]), int(info[B.INFO_ISECT]), r_main.total_tiles,
+                             split=r_main.fused_l2_active and r_main.unseen_in_bwd)
     # algorithmic work per launch: bytes of the HBM-bound calls, FP32
     # operations of the compositing kernels (operations per visit x visits)
     alu_work = {"raster_fwd": (FWD_OPS_PER_VISIT, fwd_visits), "raster_bwd": (BWD_OPS_PER_VISIT, bwd_visits)}

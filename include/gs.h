@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 4
+#define GS_ABI_VERSION 5
 #define GS_MAX_VIEWS 64
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD_FLOATS 9
@@ -311,12 +311,25 @@ size_t gs_rasterize_bwd_l2_workspace_size(int n_views, const int32_t* sizes, int
  *   is deterministic; grad2d as gs_rasterize_bwd (accumulate likewise).
  * workspace: >= gs_rasterize_bwd_l2_workspace_size() bytes, 8-byte aligned,
  *   clobbered (one double per wavefront, then one per 4,096 of those).
+ * unseen_grads (optional, NULL: not used): a host array of five device
+ *   pointers d_means [3][N], d_log_scales [3][N], d_quats [4][N],
+ *   d_opacity_logits [N] and d_sh [K][3][N] (K = (sh_degree + 1)^2), into
+ *   which the call also writes what gs_project_bwd_part writes with
+ *   GS_GRADS_UNSEEN: zeros for every group of 64 Gaussians that no view sees
+ *   (flags, [V][N] from gs_project), leaving the other elements untouched.
+ *   That part of the projection backward needs no 2-D gradient; the
+ *   compositing waves write it while their arithmetic, not memory, bounds
+ *   them.  gs_project_bwd_part with GS_GRADS_SEEN then completes the
+ *   parameter gradients.  flags and
+ *   sh_degree are read only with unseen_grads.  Errors: GS_ERR_ARG for a
+ *   NULL flags or plane pointer (N > 0) or sh_degree outside 0..3.
  */
 int gs_rasterize_bwd_l2(const float* splats, const int32_t* isect_gid, const int32_t* tile_ranges, int64_t n,
                         int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
                         const float* background, const void* schedule, const float* T_final,
                         const int32_t* n_contrib, const float* images, const float* targets, float* loss,
-                        float* grad2d, int accumulate, void* workspace, size_t workspace_bytes, void* stream);
+                        float* grad2d, int accumulate, void* workspace, size_t workspace_bytes,
+                        const uint8_t* flags, int sh_degree, float* const* unseen_grads, void* stream);
 
 /*
  * gs_project_bwd - backward of gs_project (paper Section 4: backward of the
@@ -333,6 +346,33 @@ int gs_project_bwd(const float* means, const float* log_scales, const float* qua
                    float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
                    float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh,
                    void* stream);
+
+/* which gradients gs_project_bwd_part writes; a group is Gaussians
+ * 64 k ... 64 k + 63 (the last one shorter) */
+#define GS_GRADS_ALL 0    /* every Gaussian's: gs_project_bwd */
+#define GS_GRADS_SEEN 1   /* every Gaussian's of the groups in which some view sees a Gaussian */
+#define GS_GRADS_UNSEEN 2 /* zeros for the groups in which no view sees any Gaussian */
+
+/*
+ * gs_project_bwd_part - gs_project_bwd split by visibility (paper Section 4:
+ * backward of the SH and projection operators), in groups of 64 Gaussians:
+ * each part leaves the other part's groups untouched, and GS_GRADS_SEEN
+ * followed (or preceded) by GS_GRADS_UNSEEN writes exactly what
+ * gs_project_bwd writes.  Groups, not single Gaussians, so that each line of
+ * a gradient plane is written whole by one of the two.  The unseen part
+ * reads only flags, so it can run as soon as gs_project has written them;
+ * the two parts write disjoint elements and may overlap in time.
+ * Inputs and outputs as gs_project_bwd.  With GS_GRADS_UNSEEN the
+ * parameters, cameras, eps2d and grad2d are not read and may be NULL (sizes
+ * and n_views are still checked).  Errors: GS_ERR_ARG for another part value
+ * and for the gs_project_bwd checks of the arguments that part reads.
+ */
+int gs_project_bwd_part(const float* means, const float* log_scales, const float* quats,
+                        const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
+                        const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
+                        float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
+                        float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh, int part,
+                        void* stream);
 
 /*
  * gs_project_bwd_adam - gs_project_bwd followed by gs_adam over the five

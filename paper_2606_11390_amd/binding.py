@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
-GS_ABI_VERSION = 4
+GS_ABI_VERSION = 5
 GS_MAX_VIEWS = 64
 SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
@@ -50,9 +50,11 @@ _SIGS = {
                                 _int, _p]),
     "gs_rasterize_bwd_l2_workspace_size": (_sz, [_int, _p, _int]),
     "gs_rasterize_bwd_l2": (_int, [_p, _p, _p, _i64, _int, _p, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p,
-                                   _p, _int, _p, _sz, _p]),
+                                   _p, _int, _p, _sz, _p, _int, _p, _p]),
     "gs_project_bwd": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
                               _p, _p, _p, _p]),
+    "gs_project_bwd_part": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p,
+                                   _p, _p, _p, _int, _p]),
     "gs_project_bwd_adam": (_int, [_p, _p, _p, _p, _p, _i64, _int, _p, _p, _p, _int, _f, _p, _p, _p, _p, _p,
                                    _f, _f, _f, _p, _p]),
     "gs_raster_visits": (_int, [_p, _p, _p, _i64, _int, _p, _int, _p, _p, _p, _p, _p]),
@@ -219,33 +221,52 @@ def rasterize_bwd_l2_workspace_size(sizes, tile):
 
 
 def rasterize_bwd_l2(splats, isect_gid, tile_ranges, n, sizes, tile, background, schedule, T_final, n_contrib,
-                     images, targets, loss, grad2d, workspace, accumulate=False, block=(0, 0)):
-    """gs_loss_l2 and gs_rasterize_bwd in one pass (d_images is not stored)."""
+                     images, targets, loss, grad2d, workspace, accumulate=False, block=(0, 0), unseen=None):
+    """gs_loss_l2 and gs_rasterize_bwd in one pass (d_images is not stored).
+    ``unseen``: (flags, sh_degree, [d_means, d_log_scales, d_quats,
+    d_opacity_logits, d_sh]) to also write the zero gradients of the
+    Gaussians no view sees."""
     sz, szp = _host_i32(sizes)
     bg, bgp = _host_f32(background)
+    fl, deg, planes = None, 0, None
+    if unseen is not None:
+        flags, deg, grads = unseen
+        fl = _ptr(flags, U8, "flags")
+        names = ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_sh")
+        planes = (ctypes.c_void_p * 5)(*[_ptr(t, F32, nm) for t, nm in zip(grads, names)])
     rc = lib().gs_rasterize_bwd_l2(_ptr(splats, F32, "splats"), _ptr(isect_gid, I32, "isect_gid"),
                                    _ptr(tile_ranges, I32, "tile_ranges"), n, sz.shape[0], szp, int(tile),
                                    int(block[0]), int(block[1]), bgp, _ptr(schedule, U8, "schedule"),
                                    _ptr(T_final, F32, "T_final"), _ptr(n_contrib, I32, "n_contrib"),
                                    _ptr(images, F32, "images"), _ptr(targets, F32, "targets"),
                                    _ptr(loss, F32, "loss"), _ptr(grad2d, F32, "grad2d"), int(bool(accumulate)),
-                                   _ptr(workspace, U8, "workspace"), workspace.numel(), _stream())
+                                   _ptr(workspace, U8, "workspace"), workspace.numel(), fl, int(deg), planes,
+                                   _stream())
     _check(rc, "gs_rasterize_bwd_l2")
 
 
+GRADS_ALL, GRADS_SEEN, GRADS_UNSEEN = 0, 1, 2
+
+
 def project_bwd(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes,
-                eps2d, flags, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits, d_sh):
-    n = means.shape[1]
+                eps2d, flags, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits, d_sh, part=GRADS_ALL):
+    """gs_project_bwd, or with ``part`` GRADS_SEEN / GRADS_UNSEEN the half of
+    it gs_project_bwd_part names (with GRADS_UNSEEN the parameters, cameras
+    and grad2d may be None)."""
+    n = d_means.shape[1]
     sz, szp = _host_i32(sizes)
-    rc = lib().gs_project_bwd(_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
-                              _ptr(quats, F32, "quats"), _ptr(opacity_logits, F32, "opacity_logits"),
-                              _ptr(sh, F32, "sh"), n, int(sh_degree), _ptr(viewmats, F32, "viewmats"),
-                              _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(eps2d),
-                              _ptr(flags, U8, "flags"), _ptr(grad2d, F32, "grad2d"),
-                              _ptr(d_means, F32, "d_means"), _ptr(d_log_scales, F32, "d_log_scales"),
-                              _ptr(d_quats, F32, "d_quats"), _ptr(d_opacity_logits, F32, "d_opacity_logits"),
-                              _ptr(d_sh, F32, "d_sh"), _stream())
-    _check(rc, "gs_project_bwd")
+    args = (_ptr(means, F32, "means"), _ptr(log_scales, F32, "log_scales"),
+            _ptr(quats, F32, "quats"), _ptr(opacity_logits, F32, "opacity_logits"),
+            _ptr(sh, F32, "sh"), n, int(sh_degree), _ptr(viewmats, F32, "viewmats"),
+            _ptr(intrinsics, F32, "intrinsics"), szp, sz.shape[0], float(eps2d),
+            _ptr(flags, U8, "flags"), _ptr(grad2d, F32, "grad2d"),
+            _ptr(d_means, F32, "d_means"), _ptr(d_log_scales, F32, "d_log_scales"),
+            _ptr(d_quats, F32, "d_quats"), _ptr(d_opacity_logits, F32, "d_opacity_logits"),
+            _ptr(d_sh, F32, "d_sh"))
+    if part == GRADS_ALL:
+        _check(lib().gs_project_bwd(*args, _stream()), "gs_project_bwd")
+    else:
+        _check(lib().gs_project_bwd_part(*args, int(part), _stream()), "gs_project_bwd_part")
 
 
 def project_bwd_adam(means, log_scales, quats, opacity_logits, sh, sh_degree, viewmats, intrinsics, sizes, eps2d,

@@ -18,7 +18,7 @@ hipError_t launch_project_bwd(int deg, const float* means, const float* log_scal
                               const float* viewmats, const float* intr, const ViewTable& vt,
                               float eps2d, const uint8_t* flags, const float* grad2d,
                               float* d_means, float* d_log_scales, float* d_quats, float* d_opac,
-                              float* d_sh, hipStream_t stream);
+                              float* d_sh, int part, hipStream_t stream);
 hipError_t launch_project_bwd_adam(int deg, float* means, float* log_scales, float* quats, float* opac, float* sh,
                                    long long N, const float* viewmats, const float* intr, const ViewTable& vt,
                                    float eps2d, const uint8_t* flags, const float* grad2d, float* const* exp_avg,
@@ -45,7 +45,7 @@ hipError_t launch_raster_bwd_l2(int tile, int bw, int ppl, const ViewTable& vt, 
                                 const int* gids, const int2* ranges, long long N, const float* bg,
                                 const int* order, const float* Tfin, const int* nlast, const float* img,
                                 const float* tgt, long long n_elems, float* loss, void* part, float* grad2d,
-                                hipStream_t st);
+                                const uint8_t* flags, int sh_degree, float* const* unseen_grads, hipStream_t st);
 size_t loss_workspace_size(long long n);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
 size_t morton_workspace_size(long long n);
@@ -102,6 +102,31 @@ int status(hipError_t e) { return e == hipSuccess ? GS_OK : GS_ERR_HIP; }
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// The checks and launch of gs_project_bwd and gs_project_bwd_part: the
+// parameters and the 2-D gradients are needed unless only the gradients of
+// unseen Gaussians (zeros) are written.
+int project_bwd_checked(const float* means, const float* log_scales, const float* quats,
+                        const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
+                        const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
+                        float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
+                        float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh, int part,
+                        void* stream)
+{
+    ViewTable vt;
+    if (n < 0 || n > 0x7FFFFFFFll || sh_degree < 0 || sh_degree > 3 || !make_views(sizes, n_views, 16, vt))
+        return GS_ERR_ARG;
+    if (part != GS_GRADS_ALL && part != GS_GRADS_SEEN && part != GS_GRADS_UNSEEN) return GS_ERR_ARG;
+    const bool inputs = part != GS_GRADS_UNSEEN;
+    if (inputs && !(eps2d >= 0.0f)) return GS_ERR_ARG;
+    if (n == 0) return GS_OK;
+    if (!flags || !d_means || !d_log_scales || !d_quats || !d_opacity_logits || !d_sh) return GS_ERR_ARG;
+    if (inputs && (!means || !log_scales || !quats || !opacity_logits || !sh || !viewmats || !intrinsics || !grad2d))
+        return GS_ERR_ARG;
+    return status(gs::launch_project_bwd(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
+                                         intrinsics, vt, eps2d, flags, grad2d, d_means, d_log_scales, d_quats,
+                                         d_opacity_logits, d_sh, part, as_stream(stream)));
+}
 
 }  // namespace
 
@@ -258,7 +283,8 @@ int gs_rasterize_bwd_l2(const float* splats, const int32_t* isect_gid, const int
                         int n_views, const int32_t* sizes, int tile, int block_w, int px_per_lane,
                         const float* background, const void* schedule, const float* T_final,
                         const int32_t* n_contrib, const float* images, const float* targets, float* loss,
-                        float* grad2d, int accumulate, void* workspace, size_t workspace_bytes, void* stream)
+                        float* grad2d, int accumulate, void* workspace, size_t workspace_bytes,
+                        const uint8_t* flags, int sh_degree, float* const* unseen_grads, void* stream)
 {
     ViewTable vt;
     if (n < 0 || n > 0x7FFFFFFFll || !tile_ok(tile) || !make_views(sizes, n_views, tile, vt))
@@ -266,6 +292,11 @@ int gs_rasterize_bwd_l2(const float* splats, const int32_t* isect_gid, const int
     if (!tile_ranges || !T_final || !n_contrib || !images || !targets || !loss || !grad2d || !background ||
         !isect_gid || !workspace)
         return GS_ERR_ARG;
+    if (unseen_grads) {
+        if (!flags || sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
+        for (int k = 0; k < 5; k++)
+            if (n > 0 && !unseen_grads[k]) return GS_ERR_ARG;
+    }
     if (!gs::raster_cfg_ok(tile, block_w, px_per_lane)) return GS_ERR_ARG;
     if (n > 0 && (!splats || !aligned16(splats))) return GS_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(workspace) & 7u) != 0) return GS_ERR_ARG;
@@ -281,6 +312,7 @@ int gs_rasterize_bwd_l2(const float* splats, const int32_t* isect_gid, const int
                                            reinterpret_cast<const int2*>(tile_ranges), n, background,
                                            static_cast<const int*>(schedule), T_final, n_contrib, images, targets,
                                            3ll * vt.pix_off[n_views], loss, workspace, grad2d,
+                                           unseen_grads ? flags : nullptr, sh_degree, unseen_grads,
                                            as_stream(stream)));
 }
 
@@ -291,17 +323,21 @@ int gs_project_bwd(const float* means, const float* log_scales, const float* qua
                    float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh,
                    void* stream)
 {
-    ViewTable vt;
-    if (n < 0 || n > 0x7FFFFFFFll || sh_degree < 0 || sh_degree > 3 || !make_views(sizes, n_views, 16, vt))
-        return GS_ERR_ARG;
-    if (!(eps2d >= 0.0f)) return GS_ERR_ARG;
-    if (n == 0) return GS_OK;
-    if (!means || !log_scales || !quats || !opacity_logits || !sh || !viewmats || !intrinsics || !flags ||
-        !grad2d || !d_means || !d_log_scales || !d_quats || !d_opacity_logits || !d_sh)
-        return GS_ERR_ARG;
-    return status(gs::launch_project_bwd(sh_degree, means, log_scales, quats, opacity_logits, sh, n, viewmats,
-                                         intrinsics, vt, eps2d, flags, grad2d, d_means, d_log_scales, d_quats,
-                                         d_opacity_logits, d_sh, as_stream(stream)));
+    return project_bwd_checked(means, log_scales, quats, opacity_logits, sh, n, sh_degree, viewmats, intrinsics,
+                               sizes, n_views, eps2d, flags, grad2d, d_means, d_log_scales, d_quats,
+                               d_opacity_logits, d_sh, GS_GRADS_ALL, stream);
+}
+
+int gs_project_bwd_part(const float* means, const float* log_scales, const float* quats,
+                        const float* opacity_logits, const float* sh, int64_t n, int sh_degree,
+                        const float* viewmats, const float* intrinsics, const int32_t* sizes, int n_views,
+                        float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
+                        float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh, int part,
+                        void* stream)
+{
+    return project_bwd_checked(means, log_scales, quats, opacity_logits, sh, n, sh_degree, viewmats, intrinsics,
+                               sizes, n_views, eps2d, flags, grad2d, d_means, d_log_scales, d_quats,
+                               d_opacity_logits, d_sh, part, stream);
 }
 
 int gs_project_bwd_adam(float* means, float* log_scales, float* quats, float* opacity_logits, float* sh,

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     float* __restrict__ d_opac, float* __restrict__ d_sh, AdamState as, float* __restrict__ m0,
     float* __restrict__ m1, float* __restrict__ m2, float* __restrict__ m3, float* __restrict__ m4,
     float* __restrict__ v0, float* __restrict__ v1, float* __restrict__ v2, float* __restrict__ v3,
-    float* __restrict__ v4)
+    float* __restrict__ v4, int seen_only)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     // coefficients held in registers: several views, or the Adam update
@@ -442,6 +442,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(
         if (v == 0) fl0 = f;
         any |= (f & GS_FLAG_VISIBLE) != 0;
     }
+    // the gradients of a group of 64 Gaussians (one wave) that no view sees
+    // are left to the unseen part; a group with a seen Gaussian is written
+    // whole here (zeros included), so each line is written once, in full
+    if (seen_only && __ballot(any) == 0ull) return;
 
     // a Gaussian no view sees gets zero gradients without reading its
     // parameters (whole cache lines are skipped when such Gaussians are
@@ -643,6 +647,30 @@ __global__ __launch_bounds__(256) void k_project_bwd(
                                 a_step[4], rbc2, as);
 }
 
+constexpr long long kZeroUnseenBlocks = 256;
+
+// Zero gradients of every group of 64 Gaussians (one wave) that no view
+// sees: the part of the projection backward that needs no 2-D gradient.  A
+// grid-stride loop over Gaussians; each plane is written by consecutive
+// lanes, whole lines.
+__global__ __launch_bounds__(256) void k_zero_unseen(const uint8_t* __restrict__ flags, long long N, int n_views,
+                                                     int sh_planes, float* __restrict__ d_means,
+                                                     float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+                                                     float* __restrict__ d_opac, float* __restrict__ d_sh)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += stride) {
+        bool any = false;
+        for (int v = 0; v < n_views; v++) any |= (flags[(long long)v * N + g] & GS_FLAG_VISIBLE) != 0;
+        if (__ballot(any) != 0ull) continue;
+        for (int i = 0; i < 3; i++) nt_store(0.0f, &d_means[i * N + g]);
+        for (int i = 0; i < 3; i++) nt_store(0.0f, &d_log_scales[i * N + g]);
+        for (int i = 0; i < 4; i++) nt_store(0.0f, &d_quats[i * N + g]);
+        nt_store(0.0f, &d_opac[g]);
+        for (int c = 0; c < sh_planes; c++) nt_store(0.0f, &d_sh[c * N + g]);
+    }
+}
+
 }  // namespace
 
 #define GS_PROJ_LAUNCH(DEG)                                                                            \
@@ -679,7 +707,7 @@ hipError_t launch_bwd(int deg, ParamPtr<ADAM> means, ParamPtr<ADAM> log_scales, 
                       ParamPtr<ADAM> opac, ParamPtr<ADAM> sh, long long N, const float* viewmats, const float* intr,
                       const ViewTable& vt, float eps2d, const uint8_t* flags, const float* grad2d, float* d_means,
                       float* d_log_scales, float* d_quats, float* d_opac, float* d_sh, const AdamState& as,
-                      float* const* mo, float* const* vo, hipStream_t stream)
+                      float* const* mo, float* const* vo, int seen_only, hipStream_t stream)
 {
     if (N == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((N + 255) / 256);
@@ -688,12 +716,12 @@ hipError_t launch_bwd(int deg, ParamPtr<ADAM> means, ParamPtr<ADAM> log_scales, 
         hipLaunchKernelGGL((k_project_bwd<DEG, true, ADAM>), dim3(blocks), dim3(256), 0, stream, means,    \
                            log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,      \
                            d_means, d_log_scales, d_quats, d_opac, d_sh, as, mo[0], mo[1], mo[2], mo[3], mo[4], \
-                           vo[0], vo[1], vo[2], vo[3], vo[4]);                                           \
+                           vo[0], vo[1], vo[2], vo[3], vo[4], seen_only);                                \
     else                                                                                                \
         hipLaunchKernelGGL((k_project_bwd<DEG, false, ADAM>), dim3(blocks), dim3(256), 0, stream, means,   \
                            log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,      \
                            d_means, d_log_scales, d_quats, d_opac, d_sh, as, mo[0], mo[1], mo[2], mo[3], mo[4], \
-                           vo[0], vo[1], vo[2], vo[3], vo[4])
+                           vo[0], vo[1], vo[2], vo[3], vo[4], seen_only)
     switch (deg) {
     case 0: GS_PROJ_BWD_LAUNCH(0); break;
     case 1: GS_PROJ_BWD_LAUNCH(1); break;
@@ -711,12 +739,23 @@ hipError_t launch_project_bwd(int deg, const float* means, const float* log_scal
                               const float* viewmats, const float* intr, const ViewTable& vt,
                               float eps2d, const uint8_t* flags, const float* grad2d,
                               float* d_means, float* d_log_scales, float* d_quats, float* d_opac,
-                              float* d_sh, hipStream_t stream)
+                              float* d_sh, int part, hipStream_t stream)
 {
+    if (N == 0) return hipSuccess;
+    if (part == 2) {
+        // a few workgroups per CU, so that the kernels it runs beside keep
+        // room on every CU
+        const long long need = (N + 255) / 256;
+        const unsigned blocks = (unsigned)(need < kZeroUnseenBlocks ? need : kZeroUnseenBlocks);
+        hipLaunchKernelGGL(k_zero_unseen, dim3(blocks), dim3(256), 0, stream, flags, N, vt.n_views,
+                           3 * (deg + 1) * (deg + 1), d_means, d_log_scales, d_quats, d_opac, d_sh);
+        return hipGetLastError();
+    }
     const AdamState none = {};
     float* const no_moments[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     return launch_bwd<false>(deg, means, log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d, flags, grad2d,
-                             d_means, d_log_scales, d_quats, d_opac, d_sh, none, no_moments, no_moments, stream);
+                             d_means, d_log_scales, d_quats, d_opac, d_sh, none, no_moments, no_moments,
+                             part == 1 ? 1 : 0, stream);
 }
 
 hipError_t launch_step_advance(int* step_dev, hipStream_t st);
@@ -735,7 +774,7 @@ hipError_t launch_project_bwd_adam(int deg, float* means, float* log_scales, flo
     as.step = step_dev;
     const hipError_t e = launch_bwd<true>(deg, means, log_scales, quats, opac, sh, N, viewmats, intr, vt, eps2d,
                                           flags, grad2d, nullptr, nullptr, nullptr, nullptr, nullptr, as, exp_avg,
-                                          exp_avg_sq, stream);
+                                          exp_avg_sq, 0, stream);
     return e != hipSuccess ? e : launch_step_advance(step_dev, stream);
 }
 

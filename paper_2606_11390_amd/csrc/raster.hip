@@ -554,6 +554,50 @@ __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_b
                                 grad2d, &stage[wit]);
 }
 
+// Zero parameter gradients of the groups of 64 Gaussians that no view sees
+// (flags NULL: none): the part of the projection backward that needs no 2-D
+// gradient,
+// spread over the compositing backward's waves, whose memory traffic leaves
+// most of HBM's bandwidth unused while their vector arithmetic bounds them.
+struct UnseenZero {
+    const uint8_t* flags;   // [n_views][N]
+    float* planes[5];       // means [3][N], log-scales [3][N], quaternions [4][N], opacity [N], SH [sh_planes][N]
+    int sh_planes;
+};
+
+// wave w of n zeroes, among chunks [w C / n, (w + 1) C / n) of the C groups
+// of 64 Gaussians (rounded up), the groups in which no view sees any
+// Gaussian: one flag load per view, then one store per plane, at a uniform
+// plane address plus the lane's offset.  Groups with a seen Gaussian are
+// written whole by the projection backward, so every line of a gradient
+// plane is written by one kernel, in full
+__device__ __forceinline__ void zero_unseen_share(const UnseenZero& z, long long N, int n_views, long long w,
+                                                  long long n)
+{
+    const int lane = __lane_id();
+    const long long n_chunks = (N + GS_WAVE - 1) / GS_WAVE;
+    const long long c_lo = (w * n_chunks + n - 1) / n, c_hi = ((w + 1) * n_chunks + n - 1) / n;
+    for (long long c = c_lo; c < c_hi; c++) {
+        const long long c0 = c * GS_WAVE;
+        const long long g = c0 + lane;
+        const long long gc = g < N ? g : N - 1;
+        bool seen = false;
+        for (int v = 0; v < n_views; v++) seen |= (z.flags[(long long)v * N + gc] & GS_FLAG_VISIBLE) != 0;
+        // a group with a seen Gaussian is left whole to the projection backward
+        if (__ballot(g < N && seen) != 0ull) continue;
+        if (g < N) {
+            const uint32_t off = (uint32_t)lane * 4u;
+            const int count[5] = {3, 3, 4, 1, z.sh_planes};
+#pragma unroll
+            for (int t = 0; t < 5; t++) {
+                float* const base = z.planes[t] + c0;
+                for (int k = 0; k < count[t]; k++)
+                    nt_store(0.0f, reinterpret_cast<float*>(reinterpret_cast<char*>(base + (long long)k * N) + off));
+            }
+        }
+    }
+}
+
 // the backward with the L2 loss's image gradient formed from images and targets
 template <int TS, int BW, int P>
 __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_bwd_l2(
@@ -561,14 +605,23 @@ __global__ __launch_bounds__((GS_WAVE * Layout<TS, BW, P>::WPT)) void k_raster_b
     const int2* __restrict__ ranges, long long N, float bg0, float bg1, float bg2,
     const int* __restrict__ order, const float* __restrict__ Tfin, const int* __restrict__ nlast,
     const float* __restrict__ img, const float* __restrict__ tgt, float l2scale, double* __restrict__ part,
-    float* __restrict__ grad2d)
+    float* __restrict__ grad2d, UnseenZero uz)
 {
-    __shared__ WaveStage stage[Layout<TS, BW, P>::WPT];
+    using L = Layout<TS, BW, P>;
+    __shared__ WaveStage stage[L::WPT];
     const int gt = tile_of_block(order, vt.total_tiles);
-    if (gt < 0) return;
     const int wit = __builtin_amdgcn_readfirstlane(threadIdx.x / GS_WAVE);
-    bwd_unit<TS, BW, P, false, true>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, img,
-                                     nullptr, grad2d, &stage[wit], tgt, l2scale, part);
+    // the zeroing goes to the waves of the first half of the blocks (the
+    // heaviest tiles in a heavy-first order), before their compositing: its
+    // stores then drain while those long waves compute.  Measured at 4K
+    // against the other placements: after the compositing, or spread over
+    // every wave, or over the last blocks, the kernel ran longer.
+    const unsigned zb = (gridDim.x + 1) / 2;
+    if (uz.flags && blockIdx.x < zb)
+        zero_unseen_share(uz, N, vt.n_views, (long long)blockIdx.x * L::WPT + wit, (long long)zb * L::WPT);
+    if (gt >= 0)
+        bwd_unit<TS, BW, P, false, true>(vt, gt, wit, splats, gids, ranges, N, bg0, bg1, bg2, Tfin, nlast, img,
+                                         nullptr, grad2d, &stage[wit], tgt, l2scale, part);
 }
 
 // Sum of the per-wave partials in a fixed order: blocks of L2_SPAN
@@ -714,7 +767,7 @@ template <int TS, int BW, int P>
 hipError_t bwd_l2_cfg(const ViewTable& vt, const float* splats, const int* gids, const int2* ranges, long long N,
                       const float* bg, const int* order, const float* Tfin, const int* nlast, const float* img,
                       const float* tgt, long long n_elems, float* loss, double* part, float* grad2d,
-                      hipStream_t st)
+                      const UnseenZero& uz, hipStream_t st)
 {
     using L = Layout<TS, BW, P>;
     // the same scale as the loss kernel's gradient
@@ -722,7 +775,7 @@ hipError_t bwd_l2_cfg(const ViewTable& vt, const float* splats, const int* gids,
     if (vt.total_tiles > 0)
         hipLaunchKernelGGL((k_raster_bwd_l2<TS, BW, P>), dim3(vt.total_tiles), dim3(GS_WAVE * L::WPT), 0, st, vt,
                            splats, gids, ranges, N, bg[0], bg[1], bg[2], order, Tfin, nlast, img, tgt, scale,
-                           part, grad2d);
+                           part, grad2d, uz);
     // the block sums follow the largest possible number of per-wave partials
     const long long np = (long long)vt.total_tiles * L::WPT;
     const long long np_max = (long long)vt.total_tiles * (TS * TS / GS_WAVE);
@@ -815,14 +868,20 @@ size_t raster_bwd_l2_workspace_size(const ViewTable& vt, int tile)
 
 #define GS_BWDL2(TS, BW, P) \
     return bwd_l2_cfg<TS, BW, P>(vt, splats, gids, ranges, N, bg, order, Tfin, nlast, img, tgt, n_elems, loss, \
-                                 (double*)part, grad2d, st)
+                                 (double*)part, grad2d, uz, st)
 
 hipError_t launch_raster_bwd_l2(int tile, int bw, int ppl, const ViewTable& vt, const float* splats,
                                 const int* gids, const int2* ranges, long long N, const float* bg,
                                 const int* order, const float* Tfin, const int* nlast, const float* img,
                                 const float* tgt, long long n_elems, float* loss, void* part, float* grad2d,
-                                hipStream_t st)
+                                const uint8_t* flags, int sh_degree, float* const* unseen_grads, hipStream_t st)
 {
+    UnseenZero uz = {};
+    if (flags && unseen_grads && N > 0) {
+        uz.flags = flags;
+        for (int k = 0; k < 5; k++) uz.planes[k] = unseen_grads[k];
+        uz.sh_planes = 3 * (sh_degree + 1) * (sh_degree + 1);
+    }
     if (bw == 0) { bw = 8; ppl = 1; }
     switch (tile) {
     case 8: GS_BWDL2(8, 8, 1);

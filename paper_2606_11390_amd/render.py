@@ -42,7 +42,8 @@ N_XCD = 8
 class Renderer:
     def __init__(self, n, sh_degree, sizes, tile=16, capacity=1 << 20, near=0.01, far=1e10, eps2d=0.3,
                  background=(0.0, 0.0, 0.0), persistent=False, block=(0, 0), block_bwd=None, device="cuda",
-                 radius_mode=0, order=None, order_bwd=None, fuse_l2=True, loss="l2", ssim_lambda=0.2):
+                 radius_mode=0, order=None, order_bwd=None, fuse_l2=True, loss="l2", ssim_lambda=0.2,
+                 unseen_in_bwd=True):
         # screen box rule of the projection (GS_RADIUS_*)
         self.radius_mode = int(radius_mode)
         # step(): L2 loss formed inside the rasteriser backward (d_images not stored)
@@ -53,6 +54,11 @@ class Renderer:
             raise ValueError(f"unknown loss {loss!r}")
         self.loss_kind = loss
         self.ssim_lambda = float(ssim_lambda)
+        # step() with the fused L2 backward: the zero gradients of the
+        # Gaussians no view sees are written by the compositing backward's
+        # waves (they need only the projection's flags), and the projection
+        # backward writes the seen Gaussians' gradients alone
+        self.unseen_in_bwd = bool(unseen_in_bwd)
         # wave pixel blocks (width, pixels per lane) of the forward and backward rasterisers
         self.block = tuple(int(x) for x in block)
         self.block_bwd = self.block if block_bwd is None else tuple(int(x) for x in block_bwd)
@@ -159,11 +165,12 @@ class Renderer:
                         self.background, s, q, self.T_final, self.n_contrib, d_images, d_alpha, self.grad2d,
                         accumulate=accumulate, block=self.block_bwd)
 
-    def project_bwd(self, P, cams, grads):
+    def project_bwd(self, P, cams, grads, part=B.GRADS_ALL):
         B.project_bwd(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"], self.deg,
                       cams["viewmats"], cams["intrinsics"], self.sizes, self.eps2d, self.flags, self.grad2d,
                       grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"],
-                      grads["sh"])
+                      grads["sh"], part=part)
+
 
     def loss_l2(self, targets):
         B.loss_l2(self.images, targets, self.loss, self.d_images, self.loss_ws)
@@ -184,28 +191,39 @@ class Renderer:
             self.ssim_ws = torch.empty(max(8, B.ssim_workspace_size(self.sizes)), dtype=torch.uint8,
                                        device=self.device)
 
-    def loss_raster_bwd(self, targets, accumulate=False):
+    def loss_raster_bwd(self, targets, accumulate=False, unseen_grads=None):
         """L2 loss of ``images`` against ``targets`` and the rasteriser
         backward of its gradient in one pass (``self.d_images`` is not
-        written)."""
+        written); with ``unseen_grads`` (a gradient dict) it also writes the
+        zero gradients of the Gaussians no view sees."""
         s, _ = self._sched(self.order_bwd)
+        unseen = None
+        if unseen_grads is not None:
+            unseen = (self.flags, self.deg, [unseen_grads[k] for k in ("means", "log_scales", "quats",
+                                                                         "opacity_logits", "sh")])
         B.rasterize_bwd_l2(self.splats, self.isect_gid, self.ranges, self.n, self.sizes, self.tile,
                            self.background, s, self.T_final, self.n_contrib, self.images, targets, self.loss,
-                           self.grad2d, self.l2_ws, accumulate=accumulate, block=self.block_bwd)
+                           self.grad2d, self.l2_ws, accumulate=accumulate, block=self.block_bwd, unseen=unseen)
 
     def loss_ssim_l1(self, targets):
         B.loss_ssim_l1(self.images, targets, self.sizes, self.ssim_lambda, self.loss, self.d_images,
                        self.ssim_ws)
 
-    def loss_and_raster_bwd(self, targets, accumulate=False):
+    def loss_and_raster_bwd(self, targets, accumulate=False, unseen_grads=None):
+        """The image loss and the rasteriser backward; returns True when the
+        zero gradients of unseen Gaussians were written into ``unseen_grads``
+        (the fused L2 path), so the projection backward may write only the
+        seen ones."""
         if self.loss_kind == "ssim_l1":
             self.loss_ssim_l1(targets)
             self.raster_bwd(self.d_images, accumulate=accumulate)
         elif self.fused_l2_active:
-            self.loss_raster_bwd(targets, accumulate)
+            self.loss_raster_bwd(targets, accumulate, unseen_grads)
+            return unseen_grads is not None
         else:
             self.loss_l2(targets)
             self.raster_bwd(self.d_images, accumulate=accumulate)
+        return False
 
     def forward(self, P, cams, images=None, clear_grad2d=False):
         """Projection, binning and compositing of every view into ``images``
@@ -237,8 +255,9 @@ class Renderer:
         the parameters)."""
         # the projection zeroes the 2-D gradient records the backward adds to
         self.forward(P, cams, clear_grad2d=True)
-        self.loss_and_raster_bwd(targets, accumulate=True)
-        self.project_bwd(P, cams, grads)
+        split = self.loss_and_raster_bwd(targets, accumulate=True,
+                                         unseen_grads=grads if self.unseen_in_bwd else None)
+        self.project_bwd(P, cams, grads, part=B.GRADS_SEEN if split else B.GRADS_ALL)
         return grads
 
     def train_step(self, P, cams, targets, grads, optimizer, fused=False):

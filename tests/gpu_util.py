@@ -150,15 +150,21 @@ def gpu_raster_bwd(splats, gids, ranges, sizes, tile, T_final, last, d_img, d_al
     return host(g).reshape(V, N, 9)
 
 
-def gpu_project_bwd(scene, flags, grad2d, eps2d=0.3):
+def gpu_project_bwd(scene, flags, grad2d, eps2d=0.3, parts=(B.GRADS_ALL,), fill=0.0):
+    """gs_project_bwd (or the parts of gs_project_bwd_part in the order
+    given) into gradient buffers filled with ``fill`` beforehand."""
     N, K = scene.n, (scene.sh_degree + 1) ** 2
-    d = dict(means=torch.zeros(3, N, device="cuda"), log_scales=torch.zeros(3, N, device="cuda"),
-             quats=torch.zeros(4, N, device="cuda"), opacity_logits=torch.zeros(N, device="cuda"),
-             sh=torch.zeros(K, 3, N, device="cuda"))
-    B.project_bwd(dev(scene.means), dev(scene.log_scales), dev(scene.quats), dev(scene.opacity_logits),
-                  dev(scene.sh), scene.sh_degree, dev(scene.viewmats), dev(scene.intrinsics), scene.sizes, eps2d,
-                  dev(flags.reshape(-1)), dev(grad2d.reshape(-1), F32), d["means"], d["log_scales"], d["quats"],
-                  d["opacity_logits"], d["sh"])
+    d = dict(means=torch.full((3, N), fill, device="cuda"), log_scales=torch.full((3, N), fill, device="cuda"),
+             quats=torch.full((4, N), fill, device="cuda"), opacity_logits=torch.full((N,), fill, device="cuda"),
+             sh=torch.full((K, 3, N), fill, device="cuda"))
+    fl, g2 = dev(flags.reshape(-1)), dev(grad2d.reshape(-1), F32)
+    for part in parts:
+        inputs = part != B.GRADS_UNSEEN
+        pick = (lambda t: t) if inputs else (lambda t: None)
+        B.project_bwd(pick(dev(scene.means)), pick(dev(scene.log_scales)), pick(dev(scene.quats)),
+                      pick(dev(scene.opacity_logits)), pick(dev(scene.sh)), scene.sh_degree,
+                      pick(dev(scene.viewmats)), pick(dev(scene.intrinsics)), scene.sizes, eps2d, fl, pick(g2),
+                      d["means"], d["log_scales"], d["quats"], d["opacity_logits"], d["sh"], part=part)
     return {k: host(v) for k, v in d.items()}
 
 

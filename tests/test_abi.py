@@ -78,6 +78,14 @@ def test_host_side_argument_checks():
     assert L.gs_rasterize_bwd(p, p, p, 10, 1, szp, 16, 0, 0, bg, None, None, p, p, None, None, p, 0, None) == -1
     assert L.gs_rasterize_bwd(p, p, p, 10, 1, szp, 16, 8, 4, bg, None, None, p, p, p, None, p, 0, None) == -1
     assert L.gs_project_bwd(p, p, p, p, p, 10, 5, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, None) == -1
+    # gs_project_bwd_part: unknown part; the seen part needs the parameters,
+    # the unseen part only flags and outputs
+    assert L.gs_project_bwd_part(p, p, p, p, p, 10, 3, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, 3, None) == -1
+    assert L.gs_project_bwd_part(None, p, p, p, p, 10, 3, p, p, szp, 1, 0.3, p, p, p, p, p, p, p, 1, None) == -1
+    assert L.gs_project_bwd_part(None, None, None, None, None, 10, 3, None, None, szp, 1, 0.0, p, None, None, p, p,
+                                 p, p, 2, None) == -1
+    assert L.gs_project_bwd_part(None, None, None, None, None, 0, 3, None, None, szp, 1, float("nan"), None, None,
+                                 None, None, None, None, None, 2, None) == 0
     # gs_project_bwd_adam: N above 2^30, bad betas / eps / rate, a missing moment
     five = (ctypes.c_void_p * 5)(*([16] * 5))
     hole = (ctypes.c_void_p * 5)(16, 16, None, 16, 16)

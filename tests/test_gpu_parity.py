@@ -431,12 +431,28 @@ def test_raster_bwd_l2_parity(name, tile, order, block):
     last = G.dev(np.concatenate([f["last"].reshape(-1) for _, f in fw]), np.int32)
     im_d = G.dev(np.concatenate([a.reshape(-1) for a in imgs]))
     tg_d = G.dev(np.concatenate([a.reshape(-1) for a in tgts]))
-    # fused
+    # fused, also writing the zero parameter gradients of unseen Gaussians
+    # into buffers that hold NaN beforehand
     loss_f = torch.zeros(1, device="cuda")
     g_f = torch.full((V * N * 9,), float("nan"), device="cuda")
     ws = torch.empty(B.rasterize_bwd_l2_workspace_size(s.sizes, tile), dtype=torch.uint8, device="cuda")
+    K = (s.sh_degree + 1) ** 2
+    zplanes = [torch.full((c, N), float("nan"), device="cuda") for c in (3, 3, 4, 1, 3 * K)]
+    # the zeroing reads only the flags: every third group of 64 Gaussians is
+    # marked unseen in every view, so that groups to zero exist
+    grp = np.arange(N) // 64
+    flags = arrs["flags"].copy().reshape(V, N)
+    flags[:, grp % 3 == 1] = 0
     B.rasterize_bwd_l2(sp_d, gid_d, rg, N, s.sizes, tile, bg, sched, Tf, last, im_d, tg_d, loss_f, g_f, ws,
-                       block=block)
+                       block=block, unseen=(G.dev(flags.reshape(-1)), s.sh_degree, zplanes))
+    # zeros exactly in the groups of 64 Gaussians that no view sees
+    gseen = np.zeros(grp[-1] + 1, bool)
+    np.logical_or.at(gseen, grp, np.any(flags & 1, axis=0))
+    seen = gseen[grp]
+    assert (~seen).any()
+    for zp in zplanes:
+        h = G.host(zp)
+        assert (h[:, ~seen] == 0).all() and np.isnan(h[:, seen]).all()
     # separate calls
     loss_u = torch.zeros(1, device="cuda")
     d_u = torch.empty_like(im_d)
@@ -486,6 +502,49 @@ def test_project_bwd_parity(name):
     errs = {gn: G.rel_l2(g[gn], acc[on]) for on, gn in names}
     G.say("  rel L2: " + " ".join(f"{k} {e:.1e}" for k, e in errs.items()))
     assert max(errs.values()) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", ["ragged", "multi"])
+def test_project_bwd_parts_equal_whole(name):
+    """gs_project_bwd_part: the seen part writes exactly the gradients of the
+    groups of 64 Gaussians in which some view sees a Gaussian (bit for bit
+    those of gs_project_bwd) and leaves the others untouched; the unseen part
+    writes zeros to the others only; together, in either order, they equal
+    gs_project_bwd.  Flags are masked so that whole groups are unseen."""
+    from paper_2606_11390_amd import binding as B
+    s = scene(name)
+    _, projs, arrs, *_ = oracle_stage(name, 16)
+    rng = np.random.default_rng(12)
+    V, N = s.n_views, s.n
+    flags = arrs["flags"].copy().reshape(V, N)
+    # every third group of 64 unseen in every view (its flags cleared), and
+    # the last, partial group too when N is not a multiple of 64
+    grp = np.arange(N) // 64
+    hidden = (grp % 3 == 1) | (grp == grp[-1])
+    flags[:, hidden] = 0
+    grad2d = np.zeros((V, N, 9), np.float32)
+    for v, pr in enumerate(projs):
+        use = (pr["visible"] > 0) & ~hidden
+        grad2d[v][use] = rng.standard_normal((use.sum(), 9)).astype(np.float32)
+    gseen = np.zeros(grp[-1] + 1, bool)
+    np.logical_or.at(gseen, grp, np.any(flags & 1, axis=0))
+    seen = gseen[grp]
+    G.say(f"[project_bwd parts] {name} N={N} V={V} in seen groups={int(seen.sum())}")
+    assert 0 < seen.sum() < N and not seen[hidden].any()
+    whole = G.gpu_project_bwd(s, flags, grad2d, fill=float("nan"))
+    only_seen = G.gpu_project_bwd(s, flags, grad2d, parts=(B.GRADS_SEEN,), fill=float("nan"))
+    only_unseen = G.gpu_project_bwd(s, flags, grad2d, parts=(B.GRADS_UNSEEN,), fill=float("nan"))
+    for order in ((B.GRADS_SEEN, B.GRADS_UNSEEN), (B.GRADS_UNSEEN, B.GRADS_SEEN)):
+        both = G.gpu_project_bwd(s, flags, grad2d, parts=order, fill=float("nan"))
+        for k in whole:
+            assert np.array_equal(both[k], whole[k]), k
+    for k, w in whole.items():
+        assert not np.isnan(w).any(), k
+        cols = w.reshape(-1, N)
+        assert np.array_equal(only_seen[k].reshape(-1, N)[:, seen], cols[:, seen]), k
+        assert np.isnan(only_seen[k].reshape(-1, N)[:, ~seen]).all(), k
+        assert (only_unseen[k].reshape(-1, N)[:, ~seen] == 0).all(), k
+        assert np.isnan(only_unseen[k].reshape(-1, N)[:, seen]).all(), k
 
 
 @pytest.mark.parametrize("offset", [0, 1])

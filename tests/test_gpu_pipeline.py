@@ -259,7 +259,7 @@ def test_graph_replay_matches_eager(order):
         for v in grads.values():
             v.fill_(float("nan"))
         r.images.fill_(float("nan"))
-        # the step zeroes the 2-D gradients itself (on its second stream)
+        # the projection zeroes the 2-D gradient records the step adds to
         r.grad2d.fill_(float("nan"))
         torch.cuda.synchronize()
         r.replay()
@@ -271,6 +271,39 @@ def test_graph_replay_matches_eager(order):
         # unrelated eager work between replays
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()
+
+
+def test_step_writes_unseen_zeros_in_raster_bwd():
+    """The step with the unseen Gaussians' zero gradients written by the fused
+    L2 compositing backward and the seen ones by the projection backward
+    equals the step with one whole projection backward: no gradient left
+    unwritten, exact zeros where no view sees the Gaussian, the rest equal up
+    to the backward's atomic order."""
+    s = _multi()
+    G.say("[unseen zeros in the compositing backward]")
+    out = []
+    for split in (True, False):
+        r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=16, capacity=1 << 16, unseen_in_bwd=split)
+        P, cams = R.params_to_device(s)
+        # Morton order, so that whole groups of 64 Gaussians go unseen
+        P, _ = R.morton_permute(P)
+        r.fit_capacity(P, cams)
+        tg = R.packed_targets(s)
+        grads = {k: torch.full_like(v, float("nan")) for k, v in P.items()}
+        r.step(P, cams, tg, grads)
+        torch.cuda.synchronize()
+        out.append(({k: G.host(v).copy() for k, v in grads.items()}, G.host(r.flags).copy()))
+    (ga, fl), (gb, _) = out
+    seen = np.any(fl.reshape(s.n_views, s.n) & 1, axis=0)
+    grp = np.arange(s.n) // 64
+    gseen = np.zeros(grp[-1] + 1, bool)
+    np.logical_or.at(gseen, grp, seen)
+    G.say(f"  groups of 64 that no view sees: {int((~gseen).sum())} of {gseen.size}")
+    assert (~gseen).any() and gseen.any()
+    for k in ga:
+        assert not np.isnan(ga[k]).any(), k
+        assert (ga[k].reshape(-1, s.n)[:, ~seen] == 0).all(), k
+        assert G.rel_l2(ga[k], gb[k]) <= 1e-5, k
 
 
 def test_ssim_l1_step_matches_separate_calls():

@@ -115,6 +115,23 @@ def check_radix_pass(n, nb, bits, hist_bytes, key_bytes_in, key_bytes_out, gathe
         assert n <= gather_bytes // 8
 
 
+def check_zero_share(n, V, n_waves):
+    """Wave w of n_waves zeroes chunks [w C / n, (w + 1) C / n) of the C
+    64-Gaussian chunks: the ranges tile [0, C) exactly once, the products stay
+    in 64 bits, flag loads are clamped to [V][N] and stores (lanes g < N
+    only) land inside their [planes][N] tensor."""
+    chunks = (n + 63) // 64
+    assert (n_waves - 1 + 1) * chunks < (1 << 63)
+    w = np.arange(n_waves, dtype=np.int64)
+    lo = (w * chunks + n_waves - 1) // n_waves
+    hi = ((w + 1) * chunks + n_waves - 1) // n_waves
+    assert lo[0] == 0 and hi[-1] == chunks
+    assert (lo[1:] == hi[:-1]).all() and (hi >= lo).all()
+    last_g = min((chunks - 1) * 64 + 63, n - 1)
+    assert (V - 1) * n + last_g < V * n
+    assert (48 - 1) * n + last_g < 48 * n
+
+
 def model_step(sizes, n, tile, cap):
     """Every launch of project -> bin_sort -> tile schedule -> raster fwd ->
     loss -> raster bwd -> project bwd for one workload, capacity cap."""
@@ -197,6 +214,11 @@ def model_step(sizes, n, tile, cap):
     assert (vn - 1) * GRAD + GRAD - 1 < (1 << 63)
     # loss over 3 * pixels elements
     grid_ok(max(1, (3 * pixels + 1023) // 1024), 256)
+    # the fused L2 backward's zeroing of unseen Gaussians' parameter
+    # gradients, for every waves-per-tile count a tile edge allows
+    for wpt in (1, 2, 4, 8, 16):
+        if wpt * 64 <= tile * tile:
+            check_zero_share(n, V, (total_tiles + 1) // 2 * wpt)
     # projection backward: one thread per Gaussian; SH planes at j * 3 N + g
     grid_ok((n + 255) // 256, 256)
     assert (16 * 3 - 1) * n + n - 1 < (1 << 63)
