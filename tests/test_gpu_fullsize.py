@@ -147,3 +147,42 @@ def test_fullsize_backward_persistent():
                                                            ("sh", "sh"))}
     G.say("[fullsize] projection backward rel L2 " + " ".join(f"{k} {e:.1e}" for k, e in perrs.items()))
     assert max(perrs.values()) <= 1e-4
+
+
+def test_fullsize_step_unseen_split():
+    """The benchmarked step on the Morton-ordered 4K scene: with the unseen
+    groups' zero gradients written by the fused L2 backward and the rest by
+    the projection backward, every gradient is written (buffers hold NaN
+    beforehand), the zeros are exact, and the gradients equal those of one
+    whole projection backward up to the atomics' order; images and loss are
+    bit-identical."""
+    import torch
+    from paper_2606_11390_amd import render as R
+    s = scenes.uhd()
+    P, cams = R.params_to_device(s)
+    P, _ = R.morton_permute(P)
+    tg = R.packed_targets(s)
+    out = []
+    for split in (True, False):
+        r = R.Renderer(s.n, s.sh_degree, s.sizes, tile=TILE, capacity=1 << 22, order="heavy", order_bwd="heavy",
+                       block=(8, 1), block_bwd=(8, 1), unseen_in_bwd=split)
+        r.fit_capacity(P, cams)
+        grads = {k: torch.full_like(v, float("nan")) for k, v in P.items()}
+        r.step(P, cams, tg, grads)
+        torch.cuda.synchronize()
+        out.append(({k: G.host(v) for k, v in grads.items()}, G.host(r.images), float(G.host(r.loss)[0]),
+                    G.host(r.flags)))
+        del r, grads
+    (ga, ia, la, fl), (gb, ib, lb, _) = out
+    assert np.array_equal(ia, ib) and la == lb
+    grp = np.arange(s.n) // 64
+    gseen = np.zeros(grp[-1] + 1, bool)
+    np.logical_or.at(gseen, grp, (fl & 1).astype(bool))
+    G.say(f"[fullsize] groups of 64 no view sees: {int((~gseen).sum())} of {gseen.size}")
+    assert (~gseen).sum() > gseen.size // 4
+    for k in ga:
+        assert not np.isnan(ga[k]).any(), k
+        assert (ga[k].reshape(-1, s.n)[:, ~gseen[grp]] == 0).all(), k
+        e = G.rel_l2(ga[k], gb[k])
+        G.say(f"  {k}: rel L2 split vs whole {e:.1e}")
+        assert e <= 1e-5, k
