@@ -549,12 +549,31 @@ def main():
     # algorithmic work per launch: bytes of the HBM-bound calls, FP32
     # operations of the compositing kernels (operations per visit x visits)
     alu_work = {"raster_fwd": (FWD_OPS_PER_VISIT, fwd_visits), "raster_bwd": (BWD_OPS_PER_VISIT, bwd_visits)}
+    # in the step the compositing backward also writes the zero parameter
+    # gradients of the groups of 64 Gaussians no view sees (236 B per
+    # Gaussian at SH degree 3), work moved there from the projection backward
+    side_bytes = {}
+    if r_main.fused_l2_active and r_main.unseen_in_bwd:
+        fl = r_main.flags.cpu().numpy().reshape(scene.n_views, scene.n)
+        grp = np.arange(scene.n) // 64
+        gseen = np.zeros(int(grp[-1]) + 1, bool)
+        np.logical_or.at(gseen, grp, np.any(fl & B.FLAG_VISIBLE, axis=0))
+        K = (scene.sh_degree + 1) ** 2
+        side_bytes["raster_bwd"] = int((~gseen[grp]).sum()) * 4 * (11 + 3 * K)
     rooflines = {}
     for k, (opv, nv) in alu_work.items():
         ops = opv * nv
         ent = {"bound": "alu", "achieved": round(ops / (st[k] * 1e-3) / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
                "unit": "TFLOP/s", "frac": round(ops / (st[k] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
                "ops_per_visit": opv, "visits": nv, "work_per_launch": ops, "launch_us": round(st[k] * 1e3, 2)}
+        if k in side_bytes:
+            # the launch's two kinds of work, each at its own peak, as a share
+            # of the launch time (a lower bound on what it could reach: the
+            # stores could overlap the arithmetic entirely)
+            t_ops = ops / (PEAK_FP32_TFLOPS * 1e12)
+            t_bytes = side_bytes[k] / (PEAK_HBM_GBS * 1e9)
+            ent["zero_grad_bytes"] = side_bytes[k]
+            ent["frac_ops_plus_zero_bytes"] = round((t_ops + t_bytes) / (st[k] * 1e-3), 4)
         tr = trace_us(k, r_main, scene.name)
         if tr:
             ent["trace_avg_us"] = tr[0]
