@@ -280,3 +280,28 @@ def test_block_spans_cover_every_element_once():
             assert beg % RS_CHUNK == 0 or beg == n
             end_prev = end
         assert end_prev == n
+
+
+@pytest.mark.parametrize("n", [5_000_000, 20_000_000, 60_000_000])
+def test_morton_order_and_gather_in_bounds(n):
+    """The Morton reordering run before the benchmarks (gs_morton_order, then
+    gs_gather_columns per parameter tensor) at the 4K, 16-view and city
+    Gaussian counts: the workspace layout recomputed here matches the
+    library's size, every radix pass (8, 8, 8 and 6 bits over n keys, the
+    first computing the codes from the means) stays inside its regions, and
+    the gather's grid and largest plane offset fit."""
+    t = n
+    keys = align256(4 * t)
+    hist = align256(4 * 256 * RS_MAX_BLOCKS)
+    assert B.lib().gs_morton_workspace_size(n) == 3 * keys + hist + align256(4 * 256)
+    nb = sort_blocks(t)
+    for bits in (8, 8, 8, 6):
+        check_radix_pass(t, nb, bits, 4 * 256 * RS_MAX_BLOCKS, 4 * t, 4 * t)
+    # the index plane (values) is the caller's int32 order[n] or the third
+    # key-sized region; the 30-bit codes fit the four passes
+    assert 8 + 8 + 8 + 6 == 30
+    # gather: one thread per destination column, 64-bit plane offsets, up to
+    # 48 SH planes per tensor
+    grid_ok((t + 255) // 256, 256)
+    assert (48 - 1) * t + t - 1 < (1 << 63)
+
